@@ -1,0 +1,204 @@
+"""CPU oracle for iterated colour-index pruning -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  The product library never loads it, and it
+shares no code with the GPU path: the C file ``kz_oracle.c`` reads the
+caller's arrays itself (see its header for the thesis passages it follows,
+section 4.2 and Definition 4.2.1).
+
+Functions and their pins (each is checked in ``tests/test_oracle.py`` against
+something other than itself):
+
+* ``OracleGraph.fixpoint`` (O1, synchronous rounds) -- pinned by the thesis's
+  Figure 8 colour indices on a consistent completion (golden fixture), the
+  k=2 / k=3 closed forms (k=3 kernel = union of triangles, checked against
+  brute-force triangle enumeration), complete k-partite graphs, the
+  index-inequality family (no k-clique yet nothing removed), brute-force
+  k-clique inclusion, and, on tiny graphs, equality with the greatest stable
+  subgraph found by exhaustive search over edge subsets (``setref``).
+* ``OracleGraph.fixpoint_random_order`` (O2) -- pinned by agreeing with O1
+  over many random orders and by the same exhaustive search.
+* ``OracleGraph.ci_vertex`` / ``ci_edge`` -- pinned by the four colour
+  indices the thesis prints for Figure 8.
+* ``OracleGraph.kcliques`` -- pinned by closed-form clique counts of complete
+  k-partite graphs (prod of class sizes) and by itertools enumeration.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import build_oracle
+
+FMT_DENSE, FMT_BITSET, FMT_CSR = 0, 1, 2
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    # KZ_ORACLE_LIB lets the mutation test load a copy of the oracle with a
+    # planted mistake, to show that the pins catch it.
+    lib = C.CDLL(os.environ.get("KZ_ORACLE_LIB") or build_oracle())
+    vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    lib.kzo_load.restype = vp
+    lib.kzo_load.argtypes = [C.c_int, i32, vp, vp, i32, vp, vp, i64, vp, i32, C.POINTER(i32)]
+    lib.kzo_free.argtypes = [vp]
+    lib.kzo_reset.argtypes = [vp]
+    lib.kzo_num_entries.restype = i64
+    lib.kzo_num_entries.argtypes = [vp]
+    lib.kzo_fixpoint.restype = C.c_int
+    lib.kzo_fixpoint.argtypes = [vp, vp]
+    lib.kzo_fixpoint_random_order.restype = C.c_int
+    lib.kzo_fixpoint_random_order.argtypes = [vp, u64]
+    lib.kzo_ci_vertex.restype = i32
+    lib.kzo_ci_vertex.argtypes = [vp, i32]
+    lib.kzo_ci_edge.restype = i32
+    lib.kzo_ci_edge.argtypes = [vp, i32, i32]
+    lib.kzo_kcliques.restype = i64
+    lib.kzo_kcliques.argtypes = [vp, vp, vp]
+    lib.kzo_get_masks.argtypes = [vp, vp, vp]
+    lib.kzo_set_masks.restype = C.c_int
+    lib.kzo_set_masks.argtypes = [vp, vp, vp]
+    lib.kzo_failing.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class OracleError(ValueError):
+    def __init__(self, status):
+        super().__init__("oracle rejected the input, status %d" % status)
+        self.status = status
+
+
+class OracleGraph:
+    """One validated input graph held by the C oracle."""
+
+    def __init__(self, fmt, n, k, colour, adj=None, rows=None, row_words=0,
+                 row_ptr=None, col_idx=None):
+        lib = _load()
+        self.fmt, self.n, self.k = int(fmt), int(n), int(k)
+        self._keep = []
+        colour = np.ascontiguousarray(colour, dtype=np.int32)
+        self._keep.append(colour)
+        args = dict(adj=None, rows=None, rp=None, ci=None)
+        nnz = 0
+        if fmt == FMT_DENSE:
+            args["adj"] = np.ascontiguousarray(adj, dtype=np.uint8)
+        elif fmt == FMT_BITSET:
+            args["rows"] = np.ascontiguousarray(rows, dtype=np.uint64)
+        else:
+            args["rp"] = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            args["ci"] = np.ascontiguousarray(col_idx, dtype=np.int32)
+            nnz = int(args["ci"].size)
+        self._keep += [a for a in args.values() if a is not None]
+        self.row_words = int(row_words)
+        st = C.c_int32(0)
+        self._h = lib.kzo_load(self.fmt, self.n, _ptr(args["adj"]), _ptr(args["rows"]),
+                               self.row_words, _ptr(args["rp"]), _ptr(args["ci"]), nnz,
+                               _ptr(colour), self.k, C.byref(st))
+        self.status = int(st.value)
+        if not self._h:
+            raise OracleError(self.status)
+        self.nent = int(lib.kzo_num_entries(self._h))
+        self._keep = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().kzo_free(h)
+            self._h = None
+
+    def reset(self):
+        _load().kzo_reset(self._h)
+
+    def fixpoint(self) -> dict:
+        stats = np.zeros(5, np.int64)
+        st = _load().kzo_fixpoint(self._h, _ptr(stats))
+        if st:
+            raise OracleError(st)
+        return dict(rounds=int(stats[0]), equals_input=int(stats[1]), surv_vertices=int(stats[2]),
+                    surv_edges=int(stats[3]), edge_tests=int(stats[4]))
+
+    def fixpoint_random_order(self, seed: int):
+        st = _load().kzo_fixpoint_random_order(self._h, C.c_uint64(seed & (2**64 - 1)))
+        if st:
+            raise OracleError(st)
+
+    def ci_vertex(self, v: int) -> int:
+        return int(_load().kzo_ci_vertex(self._h, int(v)))
+
+    def ci_edge(self, u: int, v: int) -> int:
+        return int(_load().kzo_ci_edge(self._h, int(u), int(v)))
+
+    def _emask_buffer(self):
+        if self.fmt == FMT_DENSE:
+            return np.zeros((self.n, self.n), np.uint8)
+        if self.fmt == FMT_BITSET:
+            return np.zeros((self.n, self.row_words), np.uint64)
+        return np.zeros(self.nent, np.uint8)
+
+    def masks(self):
+        vmask = np.zeros(self.n, np.uint8)
+        emask = self._emask_buffer()
+        _load().kzo_get_masks(self._h, _ptr(vmask), _ptr(emask))
+        return vmask, emask
+
+    def set_masks(self, vmask, emask) -> bool:
+        vmask = np.ascontiguousarray(vmask, dtype=np.uint8)
+        emask = np.ascontiguousarray(emask, dtype=self._emask_buffer().dtype)
+        return _load().kzo_set_masks(self._h, _ptr(vmask), _ptr(emask)) == 0
+
+    def kcliques(self):
+        """(count, vin u8[n], ein u8[entries]) over the input graph's k-cliques."""
+        vin = np.zeros(max(self.n, 1), np.uint8)
+        ein = np.zeros(max(self.nent, 1), np.uint8)
+        cnt = _load().kzo_kcliques(self._h, _ptr(vin), _ptr(ein))
+        return int(cnt), vin[:self.n], ein[:self.nent]
+
+    def failing(self, vs=(), us=(), ws=()):
+        vs = np.ascontiguousarray(vs, dtype=np.int32)
+        us = np.ascontiguousarray(us, dtype=np.int32)
+        ws = np.ascontiguousarray(ws, dtype=np.int32)
+        vf = np.zeros(max(vs.size, 1), np.uint8)
+        ef = np.zeros(max(us.size, 1), np.uint8)
+        _load().kzo_failing(self._h, _ptr(vs), vs.size, _ptr(vf), _ptr(us), _ptr(ws), us.size, _ptr(ef))
+        return vf[:vs.size], ef[:us.size]
+
+
+def _run(g: OracleGraph) -> dict:
+    res = g.fixpoint()
+    res["vmask"], res["emask"] = g.masks()
+    res["status"] = 0
+    return res
+
+
+def _guard(fn):
+    try:
+        return _run(fn())
+    except OracleError as e:
+        return dict(status=e.status)
+
+
+def kernelize_dense(adj, colour, k) -> dict:
+    adj = np.asarray(adj)
+    return _guard(lambda: OracleGraph(FMT_DENSE, adj.shape[0], k, colour, adj=adj))
+
+
+def kernelize_bitset(rows, colour, k, row_words=None) -> dict:
+    rows = np.asarray(rows)
+    rw = rows.shape[1] if row_words is None else row_words
+    return _guard(lambda: OracleGraph(FMT_BITSET, rows.shape[0], k, colour, rows=rows, row_words=rw))
+
+
+def kernelize_csr(row_ptr, col_idx, colour, k) -> dict:
+    n = len(row_ptr) - 1
+    return _guard(lambda: OracleGraph(FMT_CSR, n, k, colour, row_ptr=row_ptr, col_idx=col_idx))

@@ -1,0 +1,47 @@
+"""Shows that the oracle's pins have teeth: each case plants one plausible
+mistake in a private copy of the C oracle (CPU only), builds it, and runs the
+pin suite against it; the suite must fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "kz_oracle.c")
+
+MUTANTS = {
+    "edge_threshold_k_minus_1": (
+        "ci_edge(g, u, v, g->k - 2) < g->k - 2", "ci_edge(g, u, v, g->k - 1) < g->k - 1"),
+    "vertex_threshold_k_minus_2": (
+        "ci_vertex(g, v, g->k - 1) < g->k - 1", "ci_vertex(g, v, g->k - 2) < g->k - 2"),
+    "edge_index_ignores_second_endpoint": (
+        "if (edge_alive(g, v, w)) { g->stamp[c] = g->stamp_now; ++count; }",
+        "if (1) { g->stamp[c] = g->stamp_now; ++count; }"),
+    "edge_index_uses_endpoint_colour": (
+        "    int32_t w = g->nb[e];\n    int32_t c = g->col[w];",
+        "    int32_t w = g->nb[e];\n    int32_t c = g->col[u];"),
+    "removals_applied_inside_the_round": (
+        "if (u < v && g->ea[e] && edge_fails(g, u, v)) { fe[e] = 1; any = 1; }",
+        "if (u < v && g->ea[e] && edge_fails(g, u, v)) { fe[e] = 1; any = 1; kill_entry(g, e); }"),
+    "rounds_count_the_confirming_pass": ("stats[0] = rounds;", "stats[0] = rounds + 1;"),
+    "vertex_index_counts_removed_edges": (
+        "  for (int64_t e = g->rp[v]; e < g->rp[v + 1] && count < cap; ++e) {\n    if (!g->ea[e]) continue;",
+        "  for (int64_t e = g->rp[v]; e < g->rp[v + 1] && count < cap; ++e) {\n    if (0) continue;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation site not found: " + name
+    src = tmp_path / "mutant.c"
+    src.write_text(text.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-std=c11", "-O1", "-fPIC", "-shared", "-o", str(lib), str(src)], check=True)
+    env = dict(os.environ, KZ_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "pins did not catch mutant %s:\n%s" % (name, r.stdout[-2000:])
