@@ -1,0 +1,247 @@
+"""Benchmark: colour-index kernelization to the fixpoint on one MI355X.
+
+A step is one full kz_kernelize call (validation, every pass to the fixpoint,
+outputs) on inputs already resident in device memory.  The default workload
+is the mid-size graph: k = 10 colour classes x 300 vertices, inter-class edge
+probability 0.6, one planted 10-clique, class-major uint64 bit rows.
+
+Prints one JSON line.  ``value`` is edge tests per second, counting the
+edge tests of the exact worklists (every edge in the first pass; in pass r+1
+the edges with an endpoint that lost an edge in round r).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, published
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+WORKLOADS = {
+    "c1": "k=4 classes x 25 vertices (n=100), p=0.5, dense uint8 input",
+    "c2": "k=10 classes x 300 vertices (n=3000), p=0.6, planted 10-clique, uint64 bit rows",
+    "c3a": "k=20 classes x 1000 vertices (n=20000), p=0.3, uint64 bit rows",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=None,
+                    help="steps of the per-kernel event-timed loop (default: --steps)")
+    return ap.parse_args()
+
+
+def make_workload(name, seed):
+    from paper_2212_00574_amd import inputs
+    if name == "c1":
+        g = inputs.config1(seed)
+        adj, colour = g.dense()
+        return dict(fmt="dense", adj=adj, colour=colour, k=4, sizes=g.sizes, graph=g)
+    g = inputs.config2(seed) if name == "c2" else inputs.config3a(seed)
+    rows, colour, lay = g.bitset()
+    return dict(fmt="bitset", rows=rows, colour=colour, k=g.k, sizes=g.sizes, layout=lay, graph=g)
+
+
+def pair_edge_counts(w):
+    """Edges between every pair of classes (from the generated input, CPU side)."""
+    from paper_2212_00574_amd import inputs
+    g = w["graph"]
+    lay = inputs.class_layout(g.sizes)
+    k = lay.k
+    cnt = np.zeros((k, k), np.int64)
+    slot = g.dense_slot() if g.n <= 6000 else None
+    for a in range(k):
+        if slot is not None:
+            blk = slot[lay.offsets[a]:lay.offsets[a + 1]]
+        else:
+            blk = g.slot_rows(int(lay.offsets[a]), int(lay.offsets[a + 1]))
+        for b in range(k):
+            cnt[a, b] = int(blk[:, lay.offsets[b]:lay.offsets[b + 1]].sum())
+    return cnt
+
+
+def operand_bytes_all_edges(w):
+    """Sum over edges {u,v} of 2 (n - s_cu - s_cv) / 8: the two full rows minus the endpoints' own classes."""
+    sizes = np.asarray(w["sizes"], np.int64)
+    n = int(sizes.sum())
+    cnt = pair_edge_counts(w)
+    k = len(sizes)
+    tot = 0
+    for a in range(k):
+        for b in range(a + 1, k):
+            tot += int(cnt[a, b]) * 2 * (n - sizes[a] - sizes[b]) / 8
+    return tot, int(np.triu(cnt, 1).sum())
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kz_kernels.hip", "kz_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2212_00574_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per edge-kernel launch from the committed counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "k_edge_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("source_sha") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w):
+    from oracle import FMT_BITSET, FMT_DENSE, OracleGraph
+    t0 = time.perf_counter()
+    if w["fmt"] == "dense":
+        g = OracleGraph(FMT_DENSE, len(w["colour"]), w["k"], w["colour"], adj=w["adj"])
+    else:
+        g = OracleGraph(FMT_BITSET, len(w["colour"]), w["k"], w["colour"], rows=w["rows"],
+                        row_words=w["rows"].shape[1])
+    t1 = time.perf_counter()
+    res = g.fixpoint()
+    t2 = time.perf_counter()
+    vm, em = g.masks()
+    return res, (vm, em), t2 - t1, t1 - t0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(graphs would shard by class columns; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2212_00574_amd.binding import KERNELS, Kernelizer
+
+    dev = torch.device("cuda", 0)
+    w = make_workload(args.workload, args.seed)
+    print("workload %s ready" % args.workload, file=sys.stderr, flush=True)
+    kz = Kernelizer(0)
+    colour = torch.from_numpy(w["colour"]).to(dev)
+    k = w["k"]
+    if w["fmt"] == "dense":
+        from paper_2212_00574_amd.binding import graph_dense
+        x = torch.from_numpy(w["adj"]).to(dev)
+        graph = graph_dense(x)
+        n = x.shape[0]
+        vmask = torch.empty(n, dtype=torch.uint8, device=dev)
+        emask = torch.empty((n, n), dtype=torch.uint8, device=dev)
+    else:
+        from paper_2212_00574_amd.binding import graph_bitset
+        x = torch.from_numpy(w["rows"].view(np.int64)).to(dev)
+        graph = graph_bitset(x)
+        n = x.shape[0]
+        vmask = torch.empty(n, dtype=torch.uint8, device=dev)
+        emask = torch.empty_like(x)
+    torch.cuda.synchronize()
+
+    def step():
+        return kz.run(graph, colour, k, vmask, emask)
+
+    for _ in range(args.warmup):
+        res = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = res["edge_tests"] / (ms_per_step / 1e3)
+    print("timed %d steps: %.4f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+
+    # per-kernel times with HIP events on the launch stream (same workload, same launches)
+    psteps = args.profile_steps or args.steps
+    kz.profile(True)
+    for _ in range(psteps):
+        step()
+    torch.cuda.synchronize()
+    times = kz.kernel_times()
+    kz.profile(False)
+    edge_ms, edge_launches = times["edge"]
+    edge_avg_ms = edge_ms / max(edge_launches, 1)
+    passes = res["passes"]
+
+    op_bytes, m_check = operand_bytes_all_edges(w)
+    # exact-worklist operand bytes over all passes: pass 1 = every edge; later
+    # passes re-test fewer edges (scaled by the tested-edge ratio)
+    alg_bytes_per_step = op_bytes * (res["edge_tests"] / max(res["input_edges"], 1))
+    alg_bytes_per_launch = alg_bytes_per_step / max(passes, 1)
+    achieved = alg_bytes_per_launch / (edge_avg_ms / 1e3) / 1e9
+    traffic = traffic_from_profile(args.workload)
+    roofline = {
+        "kernel": "k_edge",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "traffic": traffic,
+        "avg_launch_ms": round(edge_avg_ms, 5),
+        "launches_per_step": edge_launches / psteps,
+        "alg_bytes_per_launch": alg_bytes_per_launch,
+    }
+
+    cpu = None
+    check = None
+    if not args.no_cpu_baseline:
+        ores, (ovm, oem), secs, load_s = cpu_baseline(w)
+        cpu = {"value": ores["edge_tests"] / secs, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
+               "sample": "the whole %s graph, one oracle fixpoint (%d edge tests, %.1f s; ingest %.1f s excluded)"
+                         % (args.workload, ores["edge_tests"], secs, load_s)}
+        gvm = vmask.cpu().numpy()
+        gem = emask.cpu().numpy()
+        if w["fmt"] == "bitset":
+            gem = gem.view(np.uint64)
+        check = bool(np.array_equal(gvm, ovm) and np.array_equal(gem, oem)
+                     and ores["rounds"] == res["rounds"] and ores["edge_tests"] == res["edge_tests"])
+
+    out = {
+        "metric": "edge tests/s to fixpoint",
+        "value": value,
+        "unit": "edge tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "n": int(n), "k": int(k),
+                   "edges": int(res["input_edges"]), "rounds": res["rounds"], "passes": passes,
+                   "surviving_vertices": res["surviving_vertices"], "surviving_edges": res["surviving_edges"],
+                   "seed": args.seed, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {name: round(t[0] / psteps, 5) for name, t in times.items()},
+        "oracle_equal": check,
+    }
+    assert m_check == res["input_edges"], (m_check, res["input_edges"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

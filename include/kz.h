@@ -1,0 +1,173 @@
+/*
+ * kz.h -- C ABI of the MI355X (gfx950) colour-index kernelizer.
+ *
+ * The operation (thesis section 4.2, Definition 4.2.1 and the vertex and edge
+ * colour indices defined after it): the input is a finite simple graph whose
+ * vertices carry a legal colouring with k colours (no edge joins two vertices
+ * of one colour).  The colour index of a vertex is the number of colour
+ * classes holding a neighbour of it; a vertex whose index is below k-1 cannot
+ * be in a k-clique and is deleted (with its edges).  The colour index of an
+ * edge {u,v} is the number of colour classes holding a common neighbour of u
+ * and v; an edge whose index is below k-2 cannot be in a k-clique and is
+ * deleted, u and v staying.  With exactly k classes these read: a vertex goes
+ * when some other class holds no neighbour of it; an edge goes when some
+ * class other than its endpoints' holds no common neighbour.
+ *
+ * The library applies both tests in synchronous rounds (every test of round r
+ * reads the graph left by round r-1; the round's removals then apply
+ * together) until a round removes nothing.  The kernel reached is unique and
+ * does not depend on the order of removals; `rounds` counts the rounds that
+ * removed something, so the kernel equals the input iff rounds == 0, which
+ * is known after the first pass.  Every k-clique survives.
+ *
+ * Memory.  Every graph, colour, mask and workspace pointer is HIP device
+ * memory owned by the caller (PyTorch allocates it in the Python binding).
+ * The library allocates no device memory per call; a context owns a small
+ * pinned host staging buffer.  All device work is ordered on the caller's
+ * stream.  kz_kernelize blocks the calling host thread: it reads a few
+ * counters back after each pass to decide whether to go on.
+ *
+ * Threading.  A context belongs to one host thread at a time.
+ */
+#ifndef KZ_H
+#define KZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status */
+#define KZ_OK          0
+#define KZ_EINVAL     (-1)  /* bad argument or malformed input (see formats)    */
+#define KZ_ECOLOUR    (-2)  /* a colour outside [0, k)                           */
+#define KZ_EILLEGAL   (-3)  /* an edge joins two vertices of one colour class    */
+#define KZ_EASYM      (-4)  /* adjacency not symmetric                           */
+#define KZ_ESELFLOOP  (-5)  /* a vertex adjacent to itself                       */
+#define KZ_EWORKSPACE (-6)  /* workspace smaller than kz_workspace_bytes()       */
+#define KZ_ENOMEM     (-7)  /* host staging allocation failed                    */
+#define KZ_EHIP       (-8)  /* a HIP runtime call failed                         */
+#define KZ_EAGAIN     (-9)  /* reserved                                          */
+
+/* Input validation happens in two stages and reports one code:
+ *   1. colours: any colour outside [0,k) -> KZ_ECOLOUR; otherwise, for the
+ *      bitset format, colours not sorted ascending or a row stride that does
+ *      not match the class sizes -> KZ_EINVAL;
+ *   2. graph entries, highest priority first: malformed entry (KZ_EINVAL) >
+ *      self-loop (KZ_ESELFLOOP) > asymmetry (KZ_EASYM) > edge inside a colour
+ *      class (KZ_EILLEGAL).
+ * On any error the masks are undefined; nothing outside the masks and the
+ * workspace is written. */
+
+/* ------------------------------------------------------------ formats */
+typedef enum {
+  KZ_DENSE_U8   = 0,  /* adj: n*n bytes, row-major, entries 0/1, symmetric,
+                         zero diagonal; vertices in any order.               */
+  KZ_BITSET_U64 = 1,  /* rows: n rows of row_words uint64 words.  Vertices
+                         are numbered class by class (colour sorted
+                         ascending).  Class c has s_c vertices and its
+                         segment holds W_c = ceil(s_c/64) words starting at
+                         word sum_{c'<c} W_c'; bit j of the segment (word
+                         j/64, bit j%64) is adjacency to the j-th vertex of
+                         class c.  row_words = sum_c W_c.  Padding bits (j >=
+                         s_c) must be zero.                                   */
+  KZ_CSR        = 2   /* row_ptr[n+1] (int64), col_idx[nnz] (int32): both
+                         directions of every edge, column ids strictly
+                         increasing within a row; row_ptr[0] = 0 and
+                         row_ptr[n] = nnz.  Reserved: not implemented yet
+                         (returns KZ_EINVAL).                                 */
+} kz_format;
+
+typedef struct kz_graph {
+  int32_t format;            /* kz_format                                   */
+  int32_t n;                 /* vertices, >= 0                              */
+  const uint8_t *adj;        /* KZ_DENSE_U8                                 */
+  const uint64_t *rows;      /* KZ_BITSET_U64                               */
+  int32_t row_words;         /* KZ_BITSET_U64                               */
+  int32_t reserved0;
+  const int64_t *row_ptr;    /* KZ_CSR                                      */
+  const int32_t *col_idx;    /* KZ_CSR                                      */
+  int64_t nnz;               /* KZ_CSR                                      */
+} kz_graph;
+
+/* Outputs (device memory, caller-owned):
+ *   vmask: uint8[n], 1 = vertex survives, in the input's vertex order;
+ *   emask: surviving edges in the input's format --
+ *          KZ_DENSE_U8:   uint8[n*n] (both directions);
+ *          KZ_BITSET_U64: uint64 rows, same layout as the input rows;
+ *          KZ_CSR:        uint8[nnz] aligned with col_idx.
+ * For KZ_BITSET_U64 the library also uses emask as its working copy of the
+ * adjacency; it must not overlap the input rows. */
+typedef struct kz_result {     /* host memory, filled on return            */
+  int32_t status;              /* same as the return value                 */
+  int32_t rounds;              /* productive synchronous rounds            */
+  int32_t equals_input;        /* 1 iff rounds == 0                        */
+  int32_t passes;              /* passes run (rounds + 1 when n > 0)       */
+  int64_t surviving_vertices;
+  int64_t surviving_edges;     /* undirected                               */
+  int64_t input_edges;         /* undirected                               */
+  int64_t edge_tests;          /* edge tests on exact worklists: pass 1
+                                  tests every edge; pass r+1 the edges still
+                                  alive that have an endpoint which lost an
+                                  edge in round r                           */
+} kz_result;
+
+typedef struct kz_ctx kz_ctx;
+
+/* Creates a context on HIP device `device`.  Returns KZ_OK or KZ_EHIP /
+ * KZ_ENOMEM; *out is NULL on failure. */
+int kz_create(kz_ctx **out, int device);
+
+/* Releases a context (NULL is allowed). */
+void kz_destroy(kz_ctx *ctx);
+
+/* Static text for a status code. */
+const char *kz_strerror(int status);
+
+/* Workspace bytes kz_kernelize needs for this graph shape and k (an upper
+ * bound that depends only on format, n, k and nnz).  Returns KZ_OK or
+ * KZ_EINVAL for arguments kz_kernelize would reject on the host. */
+int kz_workspace_bytes(const kz_ctx *ctx, const kz_graph *g, int32_t k, size_t *bytes);
+
+/* Kernelizes one graph to the fixpoint.
+ *   colour: int32[n] device array, the colour of each vertex (input order);
+ *   ws, ws_bytes: device workspace of at least kz_workspace_bytes() bytes,
+ *                 256-byte aligned, contents ignored on entry;
+ *   vmask, emask: outputs as described above;
+ *   stream: a hipStream_t (NULL = the null stream);
+ *   res: host struct receiving the scalar results.
+ * Returns KZ_OK or a status code (also stored in res->status when res is
+ * not NULL).  Host-detectable argument errors return before any device
+ * work. */
+int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k,
+                 void *ws, size_t ws_bytes, uint8_t *vmask, void *emask,
+                 void *stream, kz_result *res);
+
+/* ------------------------------------------------------------ measurement
+ * When enabled, kz_kernelize brackets every kernel launch with HIP events
+ * recorded on the caller's stream and accumulates the elapsed time per
+ * kernel family (read after the call returns).  Costs a few microseconds
+ * per launch; off by default. */
+typedef enum {
+  KZ_KERNEL_SETUP = 0,   /* header, colour count, layout, partition, state init */
+  KZ_KERNEL_PACK = 1,    /* input -> class-partitioned bit rows               */
+  KZ_KERNEL_VERTEX = 2,  /* vertex colour-index test                          */
+  KZ_KERNEL_EDGE = 3,    /* edge colour-index test (tiles)                    */
+  KZ_KERNEL_APPLY = 4,   /* copy changed tiles into the state                 */
+  KZ_KERNEL_UNPACK = 5,  /* bit rows -> output masks                          */
+  KZ_KERNEL_COUNT = 6
+} kz_kernel;
+
+/* Turns timing on (on != 0) or off; clears the accumulated times. */
+int kz_profile_enable(kz_ctx *ctx, int on);
+
+/* Accumulated milliseconds and launch count of one kernel family. */
+int kz_profile_read(const kz_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KZ_H */

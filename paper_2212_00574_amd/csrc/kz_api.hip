@@ -1,0 +1,370 @@
+// Host driver and C ABI of the colour-index kernelizer (see include/kz.h).
+//
+// One call: stage-1 checks and layout run on the device (no host round trip
+// before the first pass); then synchronous passes -- vertex test, edge test,
+// apply -- each followed by one small device-to-host read of the pass
+// counters, until a pass removes nothing.
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "kz.h"
+#include "kz_internal.h"
+
+struct kz_ctx {
+  int device;
+  kzi::Hdr *pinned;  // host staging for the per-pass counter readback
+  // optional per-kernel timing (kz_profile_enable)
+  bool prof;
+  struct Pending {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  double total_ms[KZ_KERNEL_COUNT];
+  int64_t launches[KZ_KERNEL_COUNT];
+};
+
+namespace {
+
+hipEvent_t take_event(kz_ctx *c) {
+  hipEvent_t e = nullptr;
+  if (!c->pool.empty()) {
+    e = c->pool.back();
+    c->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+// Brackets one kernel launch with events on the launch stream when timing is on.
+struct ProfScope {
+  kz_ctx *c;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(kz_ctx *c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
+    if (c->prof && (a = take_event(c))) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (b && hipEventRecord(b, s) == hipSuccess) {
+      c->pending.push_back({a, b, kind});
+    } else {
+      c->pool.push_back(a);
+      if (b) c->pool.push_back(b);
+    }
+  }
+};
+
+// Call after the stream has been synchronised.
+void prof_collect(kz_ctx *c) {
+  for (auto &p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->total_ms[p.kind] += ms;
+      c->launches[p.kind] += 1;
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool shape_ok(const kz_graph *g, int32_t k) {
+  if (!g || k < 1 || g->n < 0) return false;
+  if (g->format == KZ_DENSE_U8) return g->n <= 65536;
+  if (g->format == KZ_BITSET_U64) return g->row_words >= 0 && g->row_words <= 65535;
+  return false;  // KZ_CSR: not implemented yet
+}
+
+kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k) {
+  kzi::WsSizes z{};
+  const long long n = g->n;
+  const bool dense = g->format == KZ_DENSE_U8;
+  long long Rmax;
+  if (dense) {
+    Rmax = (n + 63) / 64 + k;
+    if (Rmax > n) Rmax = n;
+  } else {
+    Rmax = g->row_words;
+  }
+  z.Rmax = (int)Rmax;
+  z.Tmax = Rmax > 1 ? Rmax * (Rmax - 1) / 2 : 0;
+  z.nchunks = (int)((n + kzi::kRankChunk - 1) / kzi::kRankChunk);
+  size_t o = align_up(sizeof(kzi::Hdr));
+  auto take = [&o](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  z.off_counts = take(sizeof(int) * (size_t)k);
+  z.off_coff = take(sizeof(int) * ((size_t)k + 1));
+  z.off_soff = take(sizeof(int) * ((size_t)k + 1));
+  z.off_bcls = take(sizeof(int) * (size_t)Rmax);
+  z.off_bstart = take(sizeof(int) * (size_t)Rmax);
+  z.off_blen = take(sizeof(int) * (size_t)Rmax);
+  z.off_hist = take(dense ? sizeof(int) * (size_t)z.nchunks * (size_t)k : 0);
+  z.off_perm = take(dense ? sizeof(int) * (size_t)n : 0);
+  z.off_inv = take(dense ? sizeof(int) * (size_t)n : 0);
+  z.off_scls = take(dense ? sizeof(int) * (size_t)n : 0);
+  z.off_valive = take(dense ? (size_t)n : 0);
+  z.off_touched0 = take((size_t)n);
+  z.off_touched1 = take((size_t)n);
+  z.off_bt0 = take((size_t)Rmax);
+  z.off_bt1 = take((size_t)Rmax);
+  z.off_tiles = take(sizeof(int2) * (size_t)z.Tmax);
+  z.off_A = take(dense ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
+  z.off_Anext = take(sizeof(uint64_t) * (size_t)n * (size_t)Rmax);
+  z.total = o;
+  return z;
+}
+
+int map_hdr_status(const kzi::Hdr &h) {
+  if (h.bad_colour) return KZ_ECOLOUR;
+  if (h.bad_layout) return KZ_EINVAL;
+  switch (h.prio) {
+    case kzi::P_EINVAL: return KZ_EINVAL;
+    case kzi::P_ESELFLOOP: return KZ_ESELFLOOP;
+    case kzi::P_EASYM: return KZ_EASYM;
+    case kzi::P_EILLEGAL: return KZ_EILLEGAL;
+    default: return KZ_OK;
+  }
+}
+
+int finish(kz_result *res, const kz_result &r) {
+  if (res) *res = r;
+  return r.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kz_create(kz_ctx **out, int device) {
+  if (!out) return KZ_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return KZ_EHIP;
+  kz_ctx *c = new (std::nothrow) kz_ctx();
+  if (!c) return KZ_ENOMEM;
+  c->device = device;
+  c->pinned = nullptr;
+  c->prof = false;
+  for (int i = 0; i < KZ_KERNEL_COUNT; ++i) {
+    c->total_ms[i] = 0.0;
+    c->launches[i] = 0;
+  }
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void **)&c->pinned, sizeof(kzi::Hdr), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return KZ_EHIP;
+  }
+  *out = c;
+  return KZ_OK;
+}
+
+void kz_destroy(kz_ctx *ctx) {
+  if (!ctx) return;
+  for (auto &p : ctx->pending) {
+    ctx->pool.push_back(p.a);
+    ctx->pool.push_back(p.b);
+  }
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+int kz_profile_enable(kz_ctx *ctx, int on) {
+  if (!ctx) return KZ_EINVAL;
+  ctx->prof = on != 0;
+  for (int i = 0; i < KZ_KERNEL_COUNT; ++i) {
+    ctx->total_ms[i] = 0.0;
+    ctx->launches[i] = 0;
+  }
+  return KZ_OK;
+}
+
+int kz_profile_read(const kz_ctx *ctx, int kernel, double *total_ms, int64_t *launches) {
+  if (!ctx || kernel < 0 || kernel >= KZ_KERNEL_COUNT || !total_ms || !launches) return KZ_EINVAL;
+  *total_ms = ctx->total_ms[kernel];
+  *launches = ctx->launches[kernel];
+  return KZ_OK;
+}
+
+const char *kz_strerror(int status) {
+  switch (status) {
+    case KZ_OK: return "ok";
+    case KZ_EINVAL: return "invalid argument or malformed input";
+    case KZ_ECOLOUR: return "colour outside [0, k)";
+    case KZ_EILLEGAL: return "edge inside a colour class (colouring not legal)";
+    case KZ_EASYM: return "adjacency not symmetric";
+    case KZ_ESELFLOOP: return "self-loop";
+    case KZ_EWORKSPACE: return "workspace too small";
+    case KZ_ENOMEM: return "host allocation failed";
+    case KZ_EHIP: return "HIP runtime error";
+    case KZ_EAGAIN: return "try again";
+    default: return "unknown status";
+  }
+}
+
+int kz_workspace_bytes(const kz_ctx *ctx, const kz_graph *g, int32_t k, size_t *bytes) {
+  if (!ctx || !bytes || !shape_ok(g, k)) return KZ_EINVAL;
+  *bytes = plan_sizes(g, k).total;
+  return KZ_OK;
+}
+
+int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, void *ws,
+                 size_t ws_bytes, uint8_t *vmask, void *emask, void *stream, kz_result *res) {
+  kz_result r{};
+  r.status = KZ_EINVAL;
+  if (!ctx || !shape_ok(g, k)) return finish(res, r);
+  const int n = g->n;
+  const bool dense = g->format == KZ_DENSE_U8;
+  if (n > 0) {
+    if (!colour || !vmask || !emask || !ws) return finish(res, r);
+    if (dense && !g->adj) return finish(res, r);
+    if (!dense && !g->rows) return finish(res, r);
+    if ((uintptr_t)ws % kAlign) return finish(res, r);
+  }
+  if (n == 0) {
+    r.status = KZ_OK;
+    r.equals_input = 1;
+    return finish(res, r);
+  }
+  const kzi::WsSizes z = plan_sizes(g, k);
+  if (ws_bytes < z.total) {
+    r.status = KZ_EWORKSPACE;
+    return finish(res, r);
+  }
+  if (z.Tmax > 0x7fffffffLL) return finish(res, r);
+  r.status = KZ_EHIP;
+  if (hipSetDevice(ctx->device) != hipSuccess) return finish(res, r);
+  hipStream_t s = (hipStream_t)stream;
+
+  char *base = (char *)ws;
+  kzi::Plan p{};
+  p.hdr = (kzi::Hdr *)base;
+  p.counts = (int *)(base + z.off_counts);
+  p.coff = (int *)(base + z.off_coff);
+  p.soff = (int *)(base + z.off_soff);
+  p.bcls = (int *)(base + z.off_bcls);
+  p.bstart = (int *)(base + z.off_bstart);
+  p.blen = (int *)(base + z.off_blen);
+  p.hist = (int *)(base + z.off_hist);
+  p.perm = (int *)(base + z.off_perm);
+  p.inv = (int *)(base + z.off_inv);
+  p.scls = (int *)(base + z.off_scls);
+  p.valive = dense ? (uint8_t *)(base + z.off_valive) : vmask;
+  p.touched[0] = (uint8_t *)(base + z.off_touched0);
+  p.touched[1] = (uint8_t *)(base + z.off_touched1);
+  p.btouched[0] = (uint8_t *)(base + z.off_bt0);
+  p.btouched[1] = (uint8_t *)(base + z.off_bt1);
+  p.tiles = (int2 *)(base + z.off_tiles);
+  p.A = dense ? (uint64_t *)(base + z.off_A) : (uint64_t *)emask;
+  p.Anext = (uint64_t *)(base + z.off_Anext);
+  p.n = n;
+  p.k = k;
+  p.Rmax = z.Rmax;
+  p.nchunks = z.nchunks;
+  p.Tmax = z.Tmax;
+
+  {
+    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+    kzi::launch_init_header(p, dense, s);
+  }
+  {
+    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+    kzi::launch_count(p, colour, dense, s);
+  }
+  {
+    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+    kzi::launch_layout(p, g->row_words, !dense, s);
+  }
+  if (dense) {
+    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+    kzi::launch_rank(p, colour, s);
+  }
+  {
+    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+    kzi::launch_init_state(p, s);
+  }
+  {
+    ProfScope t(ctx, KZ_KERNEL_PACK, s);
+    if (dense)
+      kzi::launch_pack_dense(p, g->adj, colour, s);
+    else
+      kzi::launch_copy_rows(p, g->rows, s);
+  }
+  if (hipGetLastError() != hipSuccess) return finish(res, r);
+
+  const int *scls = dense ? p.scls : colour;
+  long long removed_v = 0, removed_e = 0, tests = 0, m = 0;
+  int rounds = 0, pass = 0;
+  for (;;) {
+    ++pass;
+    const bool validate = pass == 1;
+    {
+      ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
+      kzi::launch_vertex_pass(p, scls, pass, validate, s);
+    }
+    {
+      ProfScope t(ctx, KZ_KERNEL_EDGE, s);
+      kzi::launch_edge_pass(p, pass, validate, s);
+    }
+    {
+      ProfScope t(ctx, KZ_KERNEL_APPLY, s);
+      kzi::launch_apply(p, s);
+    }
+    if (hipGetLastError() != hipSuccess) return finish(res, r);
+    if (hipMemcpyAsync(ctx->pinned, p.hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return finish(res, r);
+    prof_collect(ctx);
+    const kzi::Hdr &h = *ctx->pinned;
+    if (validate) {
+      const int st = map_hdr_status(h);
+      if (st != KZ_OK) {
+        r.status = st;
+        return finish(res, r);
+      }
+    }
+    const unsigned long long *c = h.ctr[pass & 1];
+    if (validate) m = c[2];
+    tests += c[2];
+    removed_v += c[0];
+    removed_e += c[1];
+    if (c[0] + c[1] == 0) break;
+    ++rounds;
+    if (rounds > n + m + 1) return finish(res, r);  // cannot happen: every round removes something
+  }
+  if (dense) {
+    ProfScope t(ctx, KZ_KERNEL_UNPACK, s);
+    kzi::launch_unpack_dense(p, colour, vmask, (uint8_t *)emask, s);
+  }
+  if (hipGetLastError() != hipSuccess) return finish(res, r);
+  if (!ctx->pending.empty()) {
+    if (hipStreamSynchronize(s) != hipSuccess) return finish(res, r);
+    prof_collect(ctx);
+  }
+
+  r.status = KZ_OK;
+  r.rounds = rounds;
+  r.equals_input = rounds == 0;
+  r.passes = pass;
+  r.surviving_vertices = n - removed_v;
+  r.surviving_edges = m - removed_e;
+  r.input_edges = m;
+  r.edge_tests = tests;
+  return finish(res, r);
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+"""The C ABI library loads and exports every entry point include/kz.h declares (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kz.h")
+LIB = os.path.join(ROOT, "paper_2212_00574_amd", "libkz.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kz_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2212_00574_amd import build
+        build.build()
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    assert declared() == ["kz_create", "kz_destroy", "kz_kernelize", "kz_profile_enable", "kz_profile_read",
+                          "kz_strerror", "kz_workspace_bytes"]
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2212_00574_amd import binding
+    assert sorted(binding.EXPORTED) == declared()
+    for name in declared():
+        assert callable(getattr(binding, name))
+
+
+def test_status_strings_and_host_argument_checks(lib):
+    lib.kz_strerror.restype = C.c_char_p
+    assert lib.kz_strerror(0) == b"ok"
+    assert b"symmetric" in lib.kz_strerror(-4)
+    assert lib.kz_strerror(12345) == b"unknown status"
+    # NULL arguments are rejected on the host, before any HIP call
+    lib.kz_workspace_bytes.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+    assert lib.kz_workspace_bytes(None, None, 3, None) == -1
+    lib.kz_create.argtypes = [C.c_void_p, C.c_int]
+    assert lib.kz_create(None, 0) == -1
+
+
+def test_product_does_not_reference_the_oracle():
+    """The HIP library and its binding never load, link or name the oracle."""
+    pkg = os.path.join(ROOT, "paper_2212_00574_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "kz_oracle" not in text and "kzo_" not in text, f

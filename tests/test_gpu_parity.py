@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Every case runs the same seeded input through libkz.so and through the
+oracle, and compares vertex masks, edge masks, rounds, equals_input, the
+survivor counts and the exact-worklist edge-test count.  Integer work, so
+the bar is equality; there is no tolerance.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import kernelize_bitset, kernelize_dense  # noqa: E402
+from paper_2212_00574_amd import inputs  # noqa: E402
+from paper_2212_00574_amd.binding import Kernelizer, KzError  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DEV = torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def kz():
+    k = Kernelizer(0)
+    yield k
+    k.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def check_same(res, ref, vm, em, ctx=""):
+    assert ref["status"] == 0, ctx
+    assert res["status"] == 0, ctx
+    for key in ("rounds", "equals_input"):
+        assert res[key] == ref[key], (ctx, key, res[key], ref[key])
+    assert res["surviving_vertices"] == ref["surv_vertices"], ctx
+    assert res["surviving_edges"] == ref["surv_edges"], ctx
+    assert res["edge_tests"] == ref["edge_tests"], ctx
+    assert np.array_equal(vm, ref["vmask"]), ctx
+    assert np.array_equal(em, ref["emask"]), ctx
+
+
+def run_dense(kz, adj, colour, k, ctx=""):
+    say("dense", ctx, adj.shape, "k=%d" % k)
+    vm, em, res = kz.kernelize_dense(torch.from_numpy(adj).to(DEV), torch.from_numpy(colour).to(DEV), k)
+    torch.cuda.synchronize()
+    return res, vm.cpu().numpy(), em.cpu().numpy()
+
+
+def run_bitset(kz, rows, colour, k, ctx=""):
+    say("bitset", ctx, rows.shape, "k=%d" % k)
+    t_rows = torch.from_numpy(rows.view(np.int64)).to(DEV)
+    vm, em, res = kz.kernelize_bitset(t_rows, torch.from_numpy(colour).to(DEV), k)
+    torch.cuda.synchronize()
+    return res, vm.cpu().numpy(), em.cpu().numpy().view(np.uint64)
+
+
+def both_formats(kz, g, k, ctx):
+    adj, colour = g.dense()
+    ref = kernelize_dense(adj, colour, k)
+    res, vm, em = run_dense(kz, adj, colour, k, ctx)
+    check_same(res, ref, vm, em, ctx + " dense")
+    rows, scol, lay = g.bitset()
+    refb = kernelize_bitset(rows, scol, k)
+    resb, vmb, emb = run_bitset(kz, rows, scol, k, ctx)
+    check_same(resb, refb, vmb, emb, ctx + " bitset")
+    return ref
+
+
+def test_config1(kz):
+    g = inputs.config1(0)
+    ref = both_formats(kz, g, 4, "config1")
+    assert ref["surv_edges"] > 0
+
+
+def test_figure8_completion(kz):
+    fx = json.load(open(os.path.join(GOLDEN, "figure8.json")))
+    names = fx["vertices"]
+    idx = {v: i for i, v in enumerate(names)}
+    n = len(names)
+    adj = np.zeros((n, n), np.uint8)
+    for a, b in fx["edges"]:
+        adj[idx[a], idx[b]] = adj[idx[b], idx[a]] = 1
+    colour = np.array([fx["colour"][v] for v in names], np.int32)
+    res, vm, em = run_dense(kz, adj, colour, fx["k"], "figure8")
+    assert res["rounds"] == fx["expected_fixpoint"]["rounds"] == 2
+    assert vm.sum() == 0 and em.sum() == 0
+    check_same(res, kernelize_dense(adj, colour, fx["k"]), vm, em, "figure8")
+
+
+# sizes chosen to span several 64-slot blocks with ragged tails, single
+# blocks, empty classes, and the small-k special cases
+CASES = [
+    ([25] * 4, 0.5, False),
+    ([70, 130, 64, 1, 65], 0.45, True),
+    ([200, 150, 100, 90, 80, 70], 0.35, True),
+    ([63, 64, 65, 127, 128, 129], 0.3, False),
+    ([40] * 12, 0.55, True),
+    ([33] * 3, 0.2, False),          # k = 3: kernel = union of triangles
+    ([50, 70], 0.05, False),         # k = 2: isolated vertices only
+    ([90], 0.0, False),              # k = 1
+    ([30, 0, 40, 20], 0.6, False),   # an empty class empties the graph
+    ([100] * 5, 0.12, False),        # sparse: long cascades
+    ([80] * 8, 0.22, False),
+    ([7, 300, 9, 250], 0.5, False),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(CASES)))
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_graphs(kz, ci, seed):
+    sizes, p, plant = CASES[ci]
+    g = inputs.make_graph(sizes, p, seed=seed, gid=ci, plant=plant)
+    both_formats(kz, g, len(sizes), "case%d/seed%d" % (ci, seed))
+
+
+def test_cascades_reach_several_rounds(kz):
+    """Sparse random graphs whose pruning cascades over many rounds."""
+    seen = []
+    for seed in range(12):
+        g = inputs.make_graph([60] * 6, 0.16, seed=seed, gid=99)
+        ref = both_formats(kz, g, 6, "cascade/seed%d" % seed)
+        seen.append(ref["rounds"])
+    assert max(seen) >= 3, seen
+
+
+def test_complete_multipartite_and_index_inequality(kz):
+    for k, s in [(3, 70), (5, 64), (7, 20)]:
+        colour = np.repeat(np.arange(k), s).astype(np.int32)
+        adj = (colour[:, None] != colour[None, :]).astype(np.uint8)
+        res, vm, em = run_dense(kz, adj, colour, k, "multipartite")
+        assert res["rounds"] == 0 and res["equals_input"] == 1 and vm.all()
+        assert np.array_equal(em, adj)
+    for k in (4, 6, 9):
+        verts = [(c, i) for c in range(k) for i in range(k - 1)]
+        adj = np.array([[1 if (c != d and i != j) else 0 for d, j in verts] for c, i in verts], np.uint8)
+        colour = np.array([c for c, _ in verts], np.int32)
+        res, vm, em = run_dense(kz, adj, colour, k, "index-inequality")
+        assert res["rounds"] == 0 and np.array_equal(em, adj)
+
+
+def test_bitset_and_dense_agree_and_runs_are_deterministic(kz):
+    g = inputs.make_graph([100, 90, 80, 70, 60], 0.3, seed=5, gid=1)
+    adj, colour = g.dense()
+    r1 = run_dense(kz, adj, colour, 5, "det1")
+    r2 = run_dense(kz, adj, colour, 5, "det2")
+    assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
+    rows, scol, lay = g.bitset()
+    rb = run_bitset(kz, rows, scol, 5, "det-bitset")
+    o = g.order
+    slot = np.zeros_like(r1[2])
+    slot[np.ix_(o, o)] = r1[2]
+    assert np.array_equal(inputs.unpack_rows(rb[2], lay).astype(np.uint8), slot)
+
+
+def test_empty_graph(kz):
+    vm, em, res = kz.kernelize_dense(torch.zeros((0, 0), dtype=torch.uint8, device=DEV),
+                                     torch.zeros(0, dtype=torch.int32, device=DEV), 3)
+    assert res["rounds"] == 0 and res["equals_input"] == 1 and res["passes"] == 0
+
+
+# ------------------------------------------------------------ validation
+def status_of(kz, fn):
+    try:
+        fn()
+    except KzError as e:
+        return e.status
+    return 0
+
+
+def test_validation_matches_oracle(kz):
+    g = inputs.make_graph([20, 30, 25], 0.4, seed=2, gid=4)
+    adj, colour = g.dense()
+    n = adj.shape[0]
+    c_same = np.nonzero(colour == colour[0])[0]
+    c_other = np.nonzero(colour != colour[0])[0]
+    mutants = {}
+    bad = colour.copy(); bad[5] = 3
+    mutants["colour"] = (adj, bad)
+    a = adj.copy(); a[c_same[0], c_same[1]] = a[c_same[1], c_same[0]] = 1
+    mutants["intra"] = (a, colour)
+    a = adj.copy(); a[c_same[0], c_same[1]] = 1
+    mutants["intra_asym"] = (a, colour)
+    a = adj.copy(); a[c_other[0], 0] ^= 1
+    mutants["asym"] = (a, colour)
+    a = adj.copy(); a[3, 3] = 1
+    mutants["loop"] = (a, colour)
+    a = adj.copy(); a[1, 2] = 5
+    mutants["value"] = (a, colour)
+    a = adj.copy(); a[3, 3] = 1; a[c_other[0], 0] ^= 1; a[c_same[0], c_same[1]] = a[c_same[1], c_same[0]] = 1
+    mutants["priority"] = (a, colour)
+    for name, (a, col) in mutants.items():
+        want = kernelize_dense(a, col, 3)["status"]
+        got = status_of(kz, lambda: run_dense(kz, a, col, 3, name))
+        assert want != 0 and got == want, (name, got, want)
+
+
+def test_bitset_validation(kz):
+    g = inputs.make_graph([70, 40, 90], 0.5, seed=1, gid=0, shuffle=False)
+    rows, col, lay = g.bitset()
+    cases = {}
+    cases["unsorted"] = (rows, col[::-1].copy())
+    bad = rows.copy(); bad[0, 1] |= np.uint64(1) << np.uint64(40)     # padding of class 0 (70 slots)
+    cases["padding"] = (bad, col)
+    bad = rows.copy(); bad[3, 0] |= np.uint64(1 << 3)                 # self-loop
+    cases["loop"] = (bad, col)
+    bad = rows.copy(); bad[75, 2] ^= np.uint64(1 << 1)                # intra-class, one direction
+    cases["asym_intra"] = (bad, col)
+    bad = rows.copy(); bad[75, 0] ^= np.uint64(1 << 1)                # inter-class, one direction
+    cases["asym"] = (bad, col)
+    for name, (r, c) in cases.items():
+        want = kernelize_bitset(r, c, 3)["status"]
+        got = status_of(kz, lambda: run_bitset(kz, r, c, 3, name))
+        assert want != 0 and got == want, (name, got, want)
+    # row stride that does not match the class sizes
+    got = status_of(kz, lambda: run_bitset(kz, np.ascontiguousarray(rows[:, :-1]), col, 3, "stride"))
+    assert got == -1
+
+
+def test_workspace_too_small(kz):
+    adj = torch.zeros((10, 10), dtype=torch.uint8, device=DEV)
+    colour = torch.zeros(10, dtype=torch.int32, device=DEV)
+    from paper_2212_00574_amd import binding as b
+    gr = b.graph_dense(adj)
+    vm = torch.empty(10, dtype=torch.uint8, device=DEV)
+    em = torch.empty((10, 10), dtype=torch.uint8, device=DEV)
+    ws = torch.empty(512, dtype=torch.uint8, device=DEV)
+    res = b.kz_kernelize(kz.ctx, gr, colour.data_ptr(), 1, ws.data_ptr(), 256, vm.data_ptr(), em.data_ptr(),
+                         torch.cuda.current_stream().cuda_stream)
+    assert res.status == b.KZ_EWORKSPACE
+    res = b.kz_kernelize(kz.ctx, gr, colour.data_ptr(), 0, ws.data_ptr(), 512, vm.data_ptr(), em.data_ptr(),
+                         torch.cuda.current_stream().cuda_stream)
+    assert res.status == b.KZ_EINVAL
+
+
+# ------------------------------------------------ full-size bench workload
+def test_config2_full_size(kz):
+    """The benchmark's workload (k=10 x 300, p=0.6, planted 10-clique) against the full oracle."""
+    g = inputs.config2(0)
+    rows, col, lay = g.bitset()
+    res, vm, em = run_bitset(kz, rows, col, 10, "config2")
+    ref = kernelize_bitset(rows, col, 10)
+    check_same(res, ref, vm, em, "config2")
+    assert res["rounds"] == 0 and res["equals_input"] == 1
