@@ -1,9 +1,9 @@
 // Host driver and C ABI of the colour-index kernelizer (see include/kz.h).
 //
 // One call: stage-1 checks and layout run on the device (no host round trip
-// before the first pass); then synchronous passes -- vertex test, edge test,
-// apply -- each followed by one small device-to-host read of the pass
-// counters, until a pass removes nothing.
+// before the first pass); then synchronous passes -- vertex test, edge test
+// and, from pass 2 on, apply -- each followed by one small device-to-host
+// read of the pass counters, until a pass removes nothing.
 #include <string.h>
 
 #include <new>
@@ -122,8 +122,9 @@ kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k) {
   z.off_bt0 = take((size_t)Rmax);
   z.off_bt1 = take((size_t)Rmax);
   z.off_tiles = take(sizeof(int2) * (size_t)z.Tmax);
-  z.off_A = take(dense ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
-  z.off_Anext = take(sizeof(uint64_t) * (size_t)n * (size_t)Rmax);
+  z.off_packed = take(dense ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
+  z.off_spare = take(sizeof(uint64_t) * (size_t)n * (size_t)Rmax);
+  z.off_F = take(sizeof(uint64_t) * (size_t)n * (size_t)k);
   z.total = o;
   return z;
 }
@@ -269,40 +270,32 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   p.btouched[0] = (uint8_t *)(base + z.off_bt0);
   p.btouched[1] = (uint8_t *)(base + z.off_bt1);
   p.tiles = (int2 *)(base + z.off_tiles);
-  p.A = dense ? (uint64_t *)(base + z.off_A) : (uint64_t *)emask;
-  p.Anext = (uint64_t *)(base + z.off_Anext);
+  p.packed = (uint64_t *)(base + z.off_packed);
+  p.spare = (uint64_t *)(base + z.off_spare);
+  p.F = (uint64_t *)(base + z.off_F);
   p.n = n;
   p.k = k;
   p.Rmax = z.Rmax;
   p.nchunks = z.nchunks;
   p.Tmax = z.Tmax;
 
+  // Pass 1 reads the input rows (bitset: the caller's; dense: packed here)
+  // and writes the whole state after round 1 into `cur`; later passes work
+  // in place on `cur`, staging changed tiles in `scratch`.
+  const uint64_t *in_rows = dense ? p.packed : g->rows;
+  uint64_t *cur = dense ? p.spare : (uint64_t *)emask;
+  uint64_t *scratch = dense ? p.packed : p.spare;
   {
     ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_init_header(p, dense, s);
-  }
-  {
-    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_count(p, colour, dense, s);
-  }
-  {
-    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_layout(p, g->row_words, !dense, s);
+    kzi::launch_setup(p, colour, g->row_words, dense, s);
   }
   if (dense) {
-    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_rank(p, colour, s);
-  }
-  {
-    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_init_state(p, s);
-  }
-  {
+    {
+      ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+      kzi::launch_rank(p, colour, s);
+    }
     ProfScope t(ctx, KZ_KERNEL_PACK, s);
-    if (dense)
-      kzi::launch_pack_dense(p, g->adj, colour, s);
-    else
-      kzi::launch_copy_rows(p, g->rows, s);
+    kzi::launch_pack_dense(p, g->adj, colour, p.packed, s);
   }
   if (hipGetLastError() != hipSuccess) return finish(res, r);
 
@@ -311,18 +304,19 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   int rounds = 0, pass = 0;
   for (;;) {
     ++pass;
-    const bool validate = pass == 1;
+    const bool first = pass == 1;
+    const uint64_t *src = first ? in_rows : cur;
     {
       ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
-      kzi::launch_vertex_pass(p, scls, pass, validate, s);
+      kzi::launch_vertex_pass(p, scls, src, cur, pass, first, s);
     }
     {
       ProfScope t(ctx, KZ_KERNEL_EDGE, s);
-      kzi::launch_edge_pass(p, pass, validate, s);
+      kzi::launch_edge_pass(p, src, first ? cur : scratch, pass, first, s);
     }
-    {
+    if (!first) {
       ProfScope t(ctx, KZ_KERNEL_APPLY, s);
-      kzi::launch_apply(p, s);
+      kzi::launch_apply(p, scratch, cur, s);
     }
     if (hipGetLastError() != hipSuccess) return finish(res, r);
     if (hipMemcpyAsync(ctx->pinned, p.hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -330,25 +324,27 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
       return finish(res, r);
     prof_collect(ctx);
     const kzi::Hdr &h = *ctx->pinned;
-    if (validate) {
+    if (first) {
       const int st = map_hdr_status(h);
       if (st != KZ_OK) {
         r.status = st;
         return finish(res, r);
       }
     }
-    const unsigned long long *c = h.ctr[pass & 1];
-    if (validate) m = c[2];
-    tests += c[2];
-    removed_v += c[0];
-    removed_e += c[1];
+    unsigned long long c[4] = {0, 0, 0, 0};
+    for (int slot = 0; slot < kzi::kCtrSlots; ++slot)
+      for (int j = 0; j < 4; ++j) c[j] += h.ctr[pass & 1][slot][j];
+    if (first) m = (long long)c[2];
+    tests += (long long)c[2];
+    removed_v += (long long)c[0];
+    removed_e += (long long)c[1];
     if (c[0] + c[1] == 0) break;
     ++rounds;
     if (rounds > n + m + 1) return finish(res, r);  // cannot happen: every round removes something
   }
   if (dense) {
     ProfScope t(ctx, KZ_KERNEL_UNPACK, s);
-    kzi::launch_unpack_dense(p, colour, vmask, (uint8_t *)emask, s);
+    kzi::launch_unpack_dense(p, colour, cur, vmask, (uint8_t *)emask, s);
   }
   if (hipGetLastError() != hipSuccess) return finish(res, r);
   if (!ctx->pending.empty()) {

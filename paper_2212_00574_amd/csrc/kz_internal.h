@@ -10,16 +10,24 @@ namespace kzi {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlk = 64;           // slots per block == bits per word
 constexpr int kEdgeThreads = 256;  // 4 waves per edge tile
-constexpr int kClassChunk = 32;    // classes staged in LDS at a time
+constexpr int kChunk = 8;          // third classes an edge tile handles at a time
 constexpr int kRankChunk = 256;    // vertices per stable-partition chunk
 constexpr int kPackLdsWords = 8192;  // dense pack: row assembled in LDS up to this many words
+constexpr int kSetupThreads = 1024;  // the single setup workgroup
+constexpr int kVertexLdsClasses = 2048;  // vertex pass keeps class offsets in LDS up to this k
+constexpr int kSetupLdsClasses = 4096;  // class histogram kept in LDS up to this k
+
+constexpr int kCtrSlots = 64;      // spread of the per-pass counters
 
 // stage-2 status priorities (largest wins)
 enum : int { P_NONE = 0, P_EILLEGAL = 1, P_EASYM = 2, P_ESELFLOOP = 3, P_EINVAL = 4 };
 
 // Device-resident header at the start of the workspace.
 struct Hdr {
-  unsigned long long ctr[2][4];  // per pass parity: removed vertices, removed edges, edge tests, spare
+  // per pass parity and slot: removed vertices, removed edges, edge tests,
+  // spare.  Workgroups add into slot (id % kCtrSlots) so that thousands of
+  // same-address atomics do not serialise; the host sums the slots.
+  unsigned long long ctr[2][kCtrSlots][4];
   int tile_count;        // changed tiles appended by the edge pass
   int prio;              // stage-2 status priority
   int bad_colour;        // stage 1: some colour outside [0,k)
@@ -31,7 +39,7 @@ struct Hdr {
 // Device pointers of one kernelization (workspace carve-up + caller buffers).
 struct Plan {
   Hdr *hdr;
-  int *counts;       // [k]
+  int *counts;       // [k] class sizes
   int *coff;         // [k+1] first slot of each class
   int *soff;         // [k+1] first word of each class segment
   int *bcls;         // [Rmax] class of block / word index
@@ -45,8 +53,9 @@ struct Plan {
   uint8_t *touched[2];   // [n]
   uint8_t *btouched[2];  // [Rmax]
   int2 *tiles;       // [Tmax] changed tiles of the current pass
-  uint64_t *A;       // [n*Rmax] working adjacency (bitset: the caller's emask)
-  uint64_t *Anext;   // [n*Rmax]
+  uint64_t *packed;  // [n*Rmax] dense input packed into bit rows (dense only)
+  uint64_t *spare;   // [n*Rmax] second state buffer
+  uint64_t *F;       // [k*n] F[c*n + slot]: first word of the slot's class-c segment
   int n, k, Rmax, nchunks;
   long long Tmax;    // Rmax*(Rmax-1)/2
 };
@@ -55,23 +64,28 @@ struct WsSizes {
   size_t total;
   size_t off_counts, off_coff, off_soff, off_bcls, off_bstart, off_blen, off_hist, off_perm,
       off_inv, off_scls, off_valive, off_touched0, off_touched1, off_bt0, off_bt1, off_tiles,
-      off_A, off_Anext;
+      off_packed, off_spare, off_F;
   int Rmax, nchunks;
   long long Tmax;
 };
 
 // Kernel launchers (kz_kernels.hip).  All asynchronous on `s`.
-void launch_init_header(const Plan &p, bool dense, hipStream_t s);
-void launch_count(const Plan &p, const int *colour, bool dense, hipStream_t s);
-void launch_layout(const Plan &p, int row_words, bool bitset, hipStream_t s);
+//
+// Pass 1 ("first") reads the input rows `src`; its vertex pass copies them
+// into `dst` and its edge pass rewrites the tiles that change, so `dst` ends
+// up holding the state after round 1.  Later passes read the state `cur`,
+// write changed tiles into `scratch`, and the apply pass copies them back
+// into `cur`.
+void launch_setup(const Plan &p, const int *colour, int row_words, bool dense, hipStream_t s);
 void launch_rank(const Plan &p, const int *colour, hipStream_t s);
-void launch_init_state(const Plan &p, hipStream_t s);
-void launch_pack_dense(const Plan &p, const uint8_t *adj, const int *colour, hipStream_t s);
-void launch_copy_rows(const Plan &p, const uint64_t *rows, hipStream_t s);
-void launch_vertex_pass(const Plan &p, const int *scls, int pass, bool validate, hipStream_t s);
-void launch_edge_pass(const Plan &p, int pass, bool validate, hipStream_t s);
-void launch_apply(const Plan &p, hipStream_t s);
-void launch_unpack_dense(const Plan &p, const int *colour, uint8_t *vmask, uint8_t *emask,
-                         hipStream_t s);
+void launch_pack_dense(const Plan &p, const uint8_t *adj, const int *colour, uint64_t *dst,
+                       hipStream_t s);
+void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uint64_t *dst, int pass,
+                        bool first, hipStream_t s);
+void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first,
+                      hipStream_t s);
+void launch_apply(const Plan &p, const uint64_t *scratch, uint64_t *cur, hipStream_t s);
+void launch_unpack_dense(const Plan &p, const int *colour, const uint64_t *cur, uint8_t *vmask,
+                         uint8_t *emask, hipStream_t s);
 
 }  // namespace kzi

@@ -17,10 +17,10 @@
 //                       row v (colour index below k-1);
 //   edge {u,v} fails <=> some class c outside {class(u), class(v)} has
 //                       row_u[c] & row_v[c] == 0 (colour index below k-2).
-// Rounds are synchronous: the vertex and edge passes read the state A of
-// the previous round; changed tiles are written to Anext and copied back by
-// the apply pass.  Rows track alive EDGES, so a dead vertex has an empty row
-// (every edge at a failing vertex fails the edge test in the same round).
+// Rounds are synchronous: every test of a pass reads the state left by the
+// previous round and writes only the next state.  Rows track alive EDGES, so
+// a dead vertex has an empty row (every edge at a failing vertex fails the
+// edge test in the same round).
 #include "kz_internal.h"
 
 namespace kzi {
@@ -33,6 +33,13 @@ __device__ __forceinline__ int wave_sum(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
   return x;
+}
+
+// A value every lane holds identically, moved to scalar registers.
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // Spreads workgroup ids so that each XCD (ids are dealt round-robin to the
@@ -59,99 +66,109 @@ __device__ __forceinline__ void tri_decode(long long t, int NB, int &X, int &Y) 
 
 // ---------------------------------------------------------------- setup
 
-__global__ void k_init_header(Plan p, int dense) {
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  if (tid == 0) {
-    Hdr *h = p.hdr;
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 4; ++b) h->ctr[a][b] = 0;
+// One workgroup: zeroes the header, counts the classes (stage-1 colour
+// checks), scans class and segment offsets and fills the block table.  For
+// dense input it also builds per-chunk class histograms for the stable
+// partition.
+__global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colour, int row_words,
+                                                         int dense) {
+  Hdr *h = p.hdr;
+  const int t = threadIdx.x, n = p.n, k = p.k;
+  __shared__ int sh[kSetupLdsClasses];
+  __shared__ int sa[kSetupThreads], sb[kSetupThreads];
+  __shared__ int s_bad_colour, s_bad_layout, carry_a, carry_b;
+  const bool lds_hist = k <= kSetupLdsClasses;
+  if (t == 0) {
     h->tile_count = 0;
     h->prio = 0;
     h->bad_colour = 0;
     h->bad_layout = 0;
     h->R = 0;
-    h->n = p.n;
-    h->k = p.k;
-  }
-  for (long long i = tid; i < p.k; i += stride) p.counts[i] = 0;
-  if (dense)
-    for (long long i = tid; i < (long long)p.nchunks * p.k; i += stride) p.hist[i] = 0;
-}
-
-// Class sizes (and per-chunk histograms for the stable partition); stage-1
-// colour checks.
-__global__ void k_count(Plan p, const int *colour, int dense) {
-  int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= p.n) return;
-  int c = colour[u];
-  if (c < 0 || c >= p.k) {
-    p.hdr->bad_colour = 1;
-    return;
-  }
-  atomicAdd(&p.counts[c], 1);
-  if (dense)
-    atomicAdd(&p.hist[(long long)blockIdx.x * p.k + c], 1);
-  else if (u > 0 && colour[u - 1] > c)
-    p.hdr->bad_layout = 1;
-}
-
-// One workgroup: class offsets, segment offsets and the block table.
-__global__ void k_layout(Plan p, int row_words, int bitset) {
-  Hdr *h = p.hdr;
-  if (h->bad_colour) return;
-  __shared__ int sa[256], sb[256];
-  __shared__ int carry_a, carry_b;
-  const int t = threadIdx.x;
-  if (t == 0) {
+    h->n = n;
+    h->k = k;
+    s_bad_colour = 0;
+    s_bad_layout = 0;
     carry_a = 0;
     carry_b = 0;
   }
+  for (int i = t; i < 2 * kCtrSlots * 4; i += kSetupThreads) (&h->ctr[0][0][0])[i] = 0;
+  for (int c = t; c < k; c += kSetupThreads) {
+    if (lds_hist)
+      sh[c] = 0;
+    else
+      p.counts[c] = 0;
+  }
+  if (dense)
+    for (long long i = t; i < (long long)p.nchunks * k; i += kSetupThreads) p.hist[i] = 0;
   __syncthreads();
-  for (int base = 0; base < p.k; base += 256) {
-    int c = base + t;
-    int s = c < p.k ? p.counts[c] : 0;
-    int a = s, b = (s + 63) / 64;
+  for (int u = t; u < n; u += kSetupThreads) {
+    const int c = colour[u];
+    if (c < 0 || c >= k) {
+      s_bad_colour = 1;
+      continue;
+    }
+    if (lds_hist)
+      atomicAdd(&sh[c], 1);
+    else
+      atomicAdd(&p.counts[c], 1);
+    if (dense)
+      atomicAdd(&p.hist[(long long)(u / kRankChunk) * k + c], 1);
+    else if (u > 0 && colour[u - 1] > c)
+      s_bad_layout = 1;
+  }
+  __syncthreads();
+  if (s_bad_colour) {
+    if (t == 0) h->bad_colour = 1;
+    return;
+  }
+  for (int base = 0; base < k; base += kSetupThreads) {
+    const int c = base + t;
+    int s = 0;
+    if (c < k) s = lds_hist ? sh[c] : atomicAdd(&p.counts[c], 0);
+    const int a = s, b = (s + 63) / 64;
     sa[t] = a;
     sb[t] = b;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan
-      int xa = t >= off ? sa[t - off] : 0;
-      int xb = t >= off ? sb[t - off] : 0;
+    for (int off = 1; off < kSetupThreads; off <<= 1) {  // inclusive Hillis-Steele scan
+      const int xa = t >= off ? sa[t - off] : 0;
+      const int xb = t >= off ? sb[t - off] : 0;
       __syncthreads();
       sa[t] += xa;
       sb[t] += xb;
       __syncthreads();
     }
-    if (c < p.k) {
+    if (c < k) {
+      p.counts[c] = a;
       p.coff[c] = carry_a + sa[t] - a;
       p.soff[c] = carry_b + sb[t] - b;
     }
     __syncthreads();
-    if (t == 255) {
-      carry_a += sa[255];
-      carry_b += sb[255];
+    if (t == kSetupThreads - 1) {
+      carry_a += sa[t];
+      carry_b += sb[t];
     }
     __syncthreads();
   }
   if (t == 0) {
-    p.coff[p.k] = carry_a;
-    p.soff[p.k] = carry_b;
+    p.coff[k] = carry_a;
+    p.soff[k] = carry_b;
     int R = carry_b;
-    if (bitset && R != row_words) {
+    if (!dense && R != row_words) s_bad_layout = 1;
+    if (s_bad_layout) {
       h->bad_layout = 1;
       R = row_words;
     }
     h->R = R;
   }
   __syncthreads();
-  if (h->bad_layout) return;
-  for (int c = t; c < p.k; c += 256) {
-    int s = p.counts[c];
-    int w0 = p.soff[c];
+  if (s_bad_layout) return;
+  // each thread reads back only the entries it wrote itself above
+  for (int c = t; c < k; c += kSetupThreads) {
+    const int s = p.counts[c];
+    const int w0 = p.soff[c], c0 = p.coff[c];
     for (int b = 0; 64 * b < s; ++b) {
       p.bcls[w0 + b] = c;
-      p.bstart[w0 + b] = p.coff[c] + 64 * b;
+      p.bstart[w0 + b] = c0 + 64 * b;
       p.blen[w0 + b] = min(64, s - 64 * b);
     }
   }
@@ -177,32 +194,16 @@ __global__ void k_rank(Plan p, const int *colour) {
   p.scls[slot] = c;
 }
 
-__global__ void k_init_state(Plan p) {
-  const Hdr *h = p.hdr;
-  if (stage1_bad(h)) return;
-  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = tid; i < p.n; i += stride) {
-    p.valive[i] = 1;
-    p.touched[1][i] = 1;  // pass 1 reads parity 1: everything is "touched"
-    p.touched[0][i] = 0;
-  }
-  for (long long i = tid; i < h->R; i += stride) {
-    p.btouched[1][i] = 1;
-    p.btouched[0][i] = 0;
-  }
-}
-
 // Dense u8 adjacency (caller order) -> class-partitioned bit rows.  One
 // workgroup per caller row; the row is assembled in LDS when it fits.
 __global__ void __launch_bounds__(256) k_pack_dense(Plan p, const uint8_t *adj, const int *colour,
-                                                    int use_lds) {
+                                                    uint64_t *dst, int use_lds) {
   const Hdr *h = p.hdr;
   if (stage1_bad(h)) return;
   extern __shared__ unsigned long long srow[];
   const int u = blockIdx.x, t = threadIdx.x;
   const int R = h->R, n = p.n;
-  uint64_t *Arow = p.A + (long long)p.inv[u] * R;
+  uint64_t *Arow = dst + (long long)p.inv[u] * R;
   for (int w = t; w < R; w += 256) {
     if (use_lds)
       srow[w] = 0;
@@ -234,88 +235,165 @@ __global__ void __launch_bounds__(256) k_pack_dense(Plan p, const uint8_t *adj, 
 
 // ---------------------------------------------------------------- passes
 
-// Vertex test for alive vertices touched by the previous round (all of them
-// in pass 1, which also validates every row).  One wave per slot; lane c
-// looks at class c's segment.  Also resets the "next" bookkeeping of the pass.
-__global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, int pass, int validate) {
+// Vertex test.  A workgroup takes 64 slots (lane v = slot 64*block + v) and
+// its 4 waves split the classes (wave w walks c = w, w+4, ...).  For each
+// processed row it also refreshes the first-word matrix F[c][v] (the first
+// word of row v's class-c segment), which the edge pass stages from.  Pass 1
+// processes and validates every row and first streams the block's 64 input
+// rows into `dst` (the edge pass then only rewrites tiles that change);
+// later passes process only alive vertices touched by the previous round.
+// Also resets the bookkeeping the edge pass of this pass fills.
+template <bool FIRST>
+__global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const uint64_t *__restrict__ src,
+                                                uint64_t *__restrict__ dst, int pass) {
   Hdr *h = p.hdr;
   if (stage1_bad(h)) return;
   const int R = h->R, n = p.n, k = p.k;
   const int cur = pass & 1, nxt = cur ^ 1;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   {
-    long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = tid; i < n; i += stride) p.touched[nxt][i] = 0;
-    for (long long i = tid; i < R; i += stride) p.btouched[nxt][i] = 0;
-    if (tid == 0) {
-      h->tile_count = 0;
-      for (int j = 0; j < 4; ++j) h->ctr[nxt][j] = 0;
+    const long long gt = (long long)blockIdx.x * blockDim.x + tid;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = gt; i < n; i += stride) p.touched[nxt][i] = 0;
+    for (long long i = gt; i < R; i += stride) p.btouched[nxt][i] = 0;
+    if (gt == 0) h->tile_count = 0;
+    if (gt < kCtrSlots * 4) (&h->ctr[nxt][0][0])[gt] = 0;
+  }
+  __shared__ int sFail[kWave];
+  __shared__ int sOff[2][kVertexLdsClasses + 1];  // coff, soff
+  const bool lds_off = k <= kVertexLdsClasses;
+  const int v0 = blockIdx.x * kWave;
+  if (tid < kWave) sFail[tid] = 0;
+  if (lds_off)
+    for (int c = tid; c <= k; c += 256) {
+      sOff[0][c] = p.coff[c];
+      sOff[1][c] = p.soff[c];
+    }
+  if (FIRST) {
+    // the block's rows are contiguous: stream them into the output state
+    const long long base = (long long)v0 * R;
+    const long long cnt = (long long)min(kWave, n - v0) * R;
+    if ((((uintptr_t)(src + base)) | ((uintptr_t)(dst + base))) & 15) {
+      for (long long i = tid; i < cnt; i += 256) dst[base + i] = src[base + i];
+    } else {
+      const uint4 *s4 = (const uint4 *)(src + base);
+      uint4 *d4 = (uint4 *)(dst + base);
+      const long long c2 = cnt / 2;
+      long long i = tid;
+      for (; i + 3 * 256 < c2; i += 4 * 256) {
+        const uint4 a = s4[i], b = s4[i + 256], c = s4[i + 512], d = s4[i + 768];
+        d4[i] = a;
+        d4[i + 256] = b;
+        d4[i + 512] = c;
+        d4[i + 768] = d;
+      }
+      for (; i < c2; i += 256) d4[i] = s4[i];
+      if ((cnt & 1) && tid == 0) dst[base + cnt - 1] = src[base + cnt - 1];
     }
   }
-  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (v >= n) return;
-  if (!validate && (!p.valive[v] || !p.touched[cur][v])) return;
-  const uint64_t *row = p.A + (long long)v * R;
-  const int cv = scls[v];
-  bool fail = false;
-  int pr = P_NONE;
-  for (int c = lane; c < k; c += kWave) {
-    const int w0 = p.soff[c], w1 = p.soff[c + 1];
-    const int s = p.coff[c + 1] - p.coff[c];
-    if (validate && (s & 63) && w1 > w0 && (row[w1 - 1] >> (s & 63))) pr = max(pr, P_EINVAL);
-    if (c == cv) {
-      if (!validate) continue;
-      // own segment must be empty: classify what is there
-      const int jv = v - p.coff[c];
-      for (int w = w0; w < w1; ++w) {
-        unsigned long long x = row[w];
-        if (w == w1 - 1 && (s & 63)) x &= (1ull << (s & 63)) - 1;
-        while (x) {
-          const int b = __builtin_ctzll(x);
-          x &= x - 1;
-          const int tslot = p.coff[c] + (w - w0) * 64 + b;
-          if (tslot == v) {
-            pr = max(pr, P_ESELFLOOP);
-          } else {
-            const uint64_t y = p.A[(long long)tslot * R + w0 + (jv >> 6)];
-            pr = max(pr, ((y >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL : (int)P_EASYM);
+  __syncthreads();
+  const int v = v0 + lane;
+  const bool inr = v < n;
+  const bool active = inr && (FIRST || (p.valive[v] && p.touched[cur][v]));
+  if (__ballot(active)) {
+    const int vc = inr ? v : v0;  // clamped row for inactive lanes
+    const uint64_t *row = src + (long long)vc * R;
+    const int cv = scls[vc];
+    bool fail = false;
+    int pr = P_NONE;
+    for (int c = wid; c < k; c += 4) {
+      const int w0 = lds_off ? sOff[1][c] : p.soff[c];
+      const int w1 = lds_off ? sOff[1][c + 1] : p.soff[c + 1];
+      if (w1 == w0) {  // empty class: no neighbour possible
+        if (active) p.F[(long long)c * n + v] = 0;
+        fail |= c != cv;
+        continue;
+      }
+      const unsigned long long x = row[w0];
+      if (active) p.F[(long long)c * n + v] = x;
+      const int cc0 = lds_off ? sOff[0][c] : p.coff[c];
+      const int s = (lds_off ? sOff[0][c + 1] : p.coff[c + 1]) - cc0;
+      if (c == cv) {
+        if (FIRST && active) {
+          // own segment: must be empty in the input; classify what is there
+          const int jv = v - cc0;
+          for (int w = w0; w < w1; ++w) {
+            unsigned long long y = w == w0 ? x : row[w];
+            if (w == w1 - 1 && (s & 63)) {
+              if (y >> (s & 63)) pr = max(pr, P_EINVAL);
+              y &= (1ull << (s & 63)) - 1;
+            }
+            while (y) {
+              const int b = __builtin_ctzll(y);
+              y &= y - 1;
+              const int tslot = cc0 + (w - w0) * 64 + b;
+              if (tslot == v) {
+                pr = max(pr, P_ESELFLOOP);
+              } else {
+                const uint64_t z = src[(long long)tslot * R + w0 + (jv >> 6)];
+                pr = max(pr, ((z >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL : (int)P_EASYM);
+              }
+            }
           }
         }
+        continue;
       }
-      continue;
+      if (FIRST && active && (s & 63)) {
+        const unsigned long long last = w1 - 1 == w0 ? x : row[w1 - 1];
+        if (last >> (s & 63)) pr = max(pr, P_EINVAL);
+      }
+      bool nz = x != 0;
+      if (active && !nz)
+        for (int w = w0 + 1; w < w1; ++w)
+          if (row[w]) {
+            nz = true;
+            break;
+          }
+      fail |= !nz;
     }
-    bool nz = false;
-    if (validate) {
-      for (int w = w0; w < w1; ++w) nz |= row[w] != 0;
-    } else {
-      for (int w = w0; w < w1; ++w)
-        if (row[w]) {
-          nz = true;
-          break;
-        }
-    }
-    fail |= !nz;
+    if (pr) atomicMax(&h->prio, pr);
+    if (fail && active) atomicOr(&sFail[lane], 1);
   }
-  if (pr) atomicMax(&h->prio, pr);
-  const unsigned long long fb = __ballot(fail);
-  if (fb && lane == 0 && p.valive[v]) {
-    p.valive[v] = 0;
-    atomicAdd(&h->ctr[cur][0], 1ull);
+  __syncthreads();
+  if (wid != 0 || !__ballot(active)) return;
+  const bool fail = active && sFail[lane];
+  if (active) {
+    if (FIRST)
+      p.valive[v] = fail ? 0 : 1;
+    else if (fail)
+      p.valive[v] = 0;
   }
+  const int nf = wave_sum(fail ? 1 : 0);
+  if (lane == 0 && nf) atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][0], (unsigned long long)nf);
+}
+
+// The i-th class other than cx and cy (cx < cy): the third classes of a tile.
+__device__ __forceinline__ int third_class(int i, int cx, int cy) {
+  int c = i;
+  if (c >= cx) ++c;
+  if (c >= cy) ++c;
+  return c;
 }
 
 // Edge test for every edge of one inter-class block pair (X, Y), X < Y.
 //
 // Lane v of each wave stands for slot bstart[Y]+v; wave w handles 16 rows u
-// of block X.  P(u) is the 64-bit set of v with {u,v} still passing.  For
-// each third class c, the first word of both rows' class-c segments (staged
-// in LDS) usually already holds a common neighbour; the lanes still missing
-// one (a wave ballot) scan the remaining words of the segment straight from
-// memory.  Lanes with no common neighbour in c drop out of P(u).  The tile's
-// two copies of its new bits (word Y of X's rows, word X of Y's rows) go to
-// Anext, and the tile is listed for the apply pass, only if a bit changed.
-__global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, int pass, int validate) {
+// of block X.  P(u) is the 64-bit set of v with {u,v} still passing.  The
+// tile walks its third classes (every class but class(X) and class(Y)) in
+// chunks of kChunk.  Fast path: the first words of both rows' class-c
+// segments -- row u's from LDS (a broadcast read), row v's from the lane's
+// registers -- are ANDed and a wave ballot gives the lanes that found a
+// common neighbour there; the ballots of the chunk are ANDed.  Padding slots
+// of the last chunk hold all-ones words, so they never drop a lane.  When
+// some edge of u is not covered that way (rare on dense inputs), the slow
+// path redoes u class by class and scans the remaining words of the segment
+// for the lanes still missing a witness.  When a bit of the tile changed,
+// both copies of its new bits go to `dst` (pass 1: the output state, which
+// already holds a copy of the input; later passes: scratch, and the tile is
+// listed for the apply pass).
+template <bool FIRST>
+__global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *__restrict__ src,
+                                                       uint64_t *__restrict__ dst, int pass) {
   Hdr *h = p.hdr;
   if (stage1_bad(h)) return;
   const int R = h->R, k = p.k;
@@ -325,11 +403,15 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, int pass, int val
   const int cx = p.bcls[X], cy = p.bcls[Y];
   if (cx == cy) return;
   const int cur = pass & 1, nxt = cur ^ 1;
-  if (!(p.btouched[cur][X] | p.btouched[cur][Y])) return;
+  if (!FIRST && !(p.btouched[cur][X] | p.btouched[cur][Y])) return;
 
-  __shared__ unsigned long long sU[kClassChunk][kBlk];
-  __shared__ unsigned long long sV[kClassChunk][kBlk];
+  constexpr int kWaves = kEdgeThreads / kWave;
+  constexpr int kRowsPerWave = kBlk / kWaves;
+  __shared__ unsigned long long sU[kChunk][kBlk];
   __shared__ unsigned long long sE[kBlk], sP[kBlk];
+  __shared__ unsigned long long sT[kWaves][kBlk], sTE[kWaves][kBlk];
+  __shared__ int sW[kChunk][2];
+  __shared__ int sC[kChunk];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -337,90 +419,163 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, int pass, int val
   const int ys = p.bstart[Y], yl = p.blen[Y];
   const unsigned long long ymask = yl == 64 ? ~0ull : ((1ull << yl) - 1);
   const unsigned long long xmask = xl == 64 ? ~0ull : ((1ull << xl) - 1);
-  const uint64_t *__restrict__ A = p.A;
 
   if (tid < kBlk) {
-    const unsigned long long e = tid < xl ? A[(long long)(xs + tid) * R + Y] : 0ull;
-    sE[tid] = e;
-    sP[tid] = e & ymask;
+    // row index clamped into the block so the load is always in bounds
+    const unsigned long long e = src[(long long)(xs + (tid < xl ? tid : 0)) * R + Y];
+    sE[tid] = tid < xl ? e : 0ull;
+    sP[tid] = tid < xl ? (e & ymask) : 0ull;
   }
-  __syncthreads();
+  __syncthreads();  // sE/sP are read by every wave, also when there is no third class
+  const uint64_t *rowv = src + (long long)(ys + (lane < yl ? lane : 0)) * R;
 
-  const uint64_t *rowv = A + (long long)(ys + lane) * R;  // dereferenced only for lanes < yl
-  for (int c0 = 0; c0 < k; c0 += kClassChunk) {
-    const int nc = min(kClassChunk, k - c0);
-    for (int i = tid; i < nc * kBlk; i += kEdgeThreads) {
-      const int cc = i >> 6, r = i & 63, c = c0 + cc;
-      const int w0 = p.soff[c];
-      const bool has = p.soff[c + 1] > w0;
-      sU[cc][r] = (has && r < xl) ? A[(long long)(xs + r) * R + w0] : 0ull;
-      sV[cc][r] = (has && r < yl) ? A[(long long)(ys + r) * R + w0] : 0ull;
+  const int nthird = k - 2;
+  const int n = p.n;
+  const int ur = tid & 63;                      // staging row of this thread
+  const int urc = ur < xl ? ur : xl - 1;        // clamped into the block
+  const int vrc = lane < yl ? lane : yl - 1;
+  for (int q = 0; q < nthird; q += kChunk) {
+    if (tid < kChunk) {
+      const int i = q + tid;
+      if (i < nthird) {
+        const int c = third_class(i, cx, cy);
+        sW[tid][0] = p.soff[c];
+        sW[tid][1] = p.soff[c + 1];
+        sC[tid] = c;
+      } else {
+        sW[tid][0] = -1;  // padding slot
+        sW[tid][1] = -1;
+        sC[tid] = 0;
+      }
     }
     __syncthreads();
-    for (int ui = 0; ui < kBlk / 4; ++ui) {
-      const int u = wid * (kBlk / 4) + ui;
+    // coalesced loads from the first-word matrix, then the LDS writes
+    unsigned long long vv[kChunk];
+    unsigned long long uu[kChunk * kBlk / kEdgeThreads];
+#pragma unroll
+    for (int e2 = 0; e2 < kChunk * kBlk / kEdgeThreads; ++e2) {
+      const int j = (tid + e2 * kEdgeThreads) >> 6;
+      uu[e2] = p.F[(long long)sC[j] * n + xs + urc];
+    }
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) vv[j] = p.F[(long long)sC[j] * n + ys + vrc];
+#pragma unroll
+    for (int e2 = 0; e2 < kChunk * kBlk / kEdgeThreads; ++e2) {
+      const int j = (tid + e2 * kEdgeThreads) >> 6;
+      sU[j][ur] = sW[j][0] < 0 ? ~0ull : uu[e2];
+    }
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) vv[j] = sW[j][0] < 0 ? ~0ull : (lane < yl ? vv[j] : 0ull);
+    __syncthreads();
+    for (int ui = 0; ui < kRowsPerWave; ++ui) {
+      const int u = wid * kRowsPerWave + ui;
       if (u >= xl) break;
-      unsigned long long P = sP[u];
+      unsigned long long P = uniform64(sP[u]);
       if (!P) continue;
-      const uint64_t *rowu = A + (long long)(xs + u) * R;
-      for (int cc = 0; cc < nc; ++cc) {
-        const int c = c0 + cc;
-        if (c == cx || c == cy) continue;
-        const unsigned long long hit = __ballot((sU[cc][u] & sV[cc][lane]) != 0ull);
-        unsigned long long miss = P & ~hit;
-        if (miss) {
-          const int w1 = p.soff[c + 1];
-          for (int w = p.soff[c] + 1; w < w1 && miss; ++w) {
-            const unsigned long long a = rowu[w];
-            const unsigned long long b = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
-            miss &= ~__ballot((a & b) != 0ull);
+      unsigned long long a[kChunk];
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j) a[j] = sU[j][u];
+      unsigned long long all = ~0ull;
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j) all &= __ballot((a[j] & vv[j]) != 0ull);
+      if (P & ~all) {
+        // slow path: class by class, scanning the rest of the segment
+        const uint64_t *rowu = src + (long long)(xs + u) * R;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+          unsigned long long miss = P & ~__ballot((a[j] & vv[j]) != 0ull);
+          const int w1 = sW[j][1];
+          for (int w = sW[j][0] + 1; w < w1 && miss; ++w) {
+            const unsigned long long x = rowu[w];
+            const unsigned long long y = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
+            miss &= ~__ballot((x & y) != 0ull);
           }
           P &= ~miss;
-          if (!P) break;
         }
+        if (lane == 0) sP[u] = P;
       }
-      if (lane == 0) sP[u] = P;
     }
     __syncthreads();
   }
 
-  if (wid != 0) return;
+  // transpose: lane v gathers bit v of P(u) (and, in pass 1, of E(u)) for
+  // this wave's rows u.  A wave whose rows all kept their edges contributes
+  // its slice of ET instead (by symmetry, which pass 1 verifies).
   const int v = lane;
-  const unsigned long long ET = v < yl ? A[(long long)(ys + v) * R + X] : 0ull;
-  unsigned long long newET = 0, trE = 0;
-  for (int u = 0; u < xl; ++u) {
-    newET |= ((sP[u] >> v) & 1ull) << u;
-    if (validate) trE |= ((sE[u] >> v) & 1ull) << u;
+  const unsigned long long ET = v < yl ? rowv[X] : 0ull;
+  const unsigned long long wrows = (kRowsPerWave == 64 ? ~0ull : ((1ull << kRowsPerWave) - 1)) << (wid * kRowsPerWave);
+  bool wchanged = false;
+#pragma unroll
+  for (int ui = 0; ui < kRowsPerWave; ++ui) {
+    const int u = wid * kRowsPerWave + ui;
+    wchanged |= u < xl && sP[u] != (sE[u] & ymask);
   }
-  if (validate && v < yl && ((trE ^ ET) & xmask)) atomicMax(&h->prio, P_EASYM);
+  unsigned long long part = 0, partE = 0;
+  if (wchanged || FIRST) {
+#pragma unroll
+    for (int ui = 0; ui < kRowsPerWave; ++ui) {
+      const int u = wid * kRowsPerWave + ui;
+      if (u < xl) {
+        const unsigned long long P = sP[u], E = sE[u];
+        const unsigned bp = v < 32 ? (unsigned)P >> v : (unsigned)(P >> 32) >> (v - 32);
+        part |= (unsigned long long)(bp & 1u) << u;
+        if (FIRST) {
+          const unsigned be = v < 32 ? (unsigned)E >> v : (unsigned)(E >> 32) >> (v - 32);
+          partE |= (unsigned long long)(be & 1u) << u;
+        }
+      }
+    }
+  }
+  if (!wchanged) part = ET & wrows;
+  sT[wid][lane] = part;
+  if (FIRST) sTE[wid][lane] = partE;
+  __syncthreads();
+  if (wid != 0) return;
+
+  unsigned long long newET = 0, trE = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    newET |= sT[w][v];
+    if (FIRST) trE |= sTE[w][v];
+  }
+  newET &= xmask;
+  if (FIRST && v < yl && ((trE ^ ET) & xmask)) atomicMax(&h->prio, P_EASYM);
   const unsigned long long Eu = sE[lane] & ymask, Pu = sP[lane];
   const bool chU = lane < xl && Eu != Pu;
   const bool chV = v < yl && (ET & xmask) != newET;
   const unsigned long long bu = __ballot(chU), bv = __ballot(chV);
   if (bu | bv) {
-    if (lane < xl) p.Anext[(long long)(xs + lane) * R + Y] = Pu;
-    if (v < yl) p.Anext[(long long)(ys + v) * R + X] = newET;
+    if (lane < xl) dst[(long long)(xs + lane) * R + Y] = Pu;
+    if (v < yl) dst[(long long)(ys + v) * R + X] = newET;
     if (chU) p.touched[nxt][xs + lane] = 1;
     if (chV) p.touched[nxt][ys + v] = 1;
     const int rem = wave_sum(lane < xl ? __popcll(Eu & ~Pu) : 0);
     if (lane == 0) {
       if (bu) p.btouched[nxt][X] = 1;
       if (bv) p.btouched[nxt][Y] = 1;
-      const int pos = atomicAdd(&h->tile_count, 1);
-      p.tiles[pos] = make_int2(X, Y);
-      atomicAdd(&h->ctr[cur][1], (unsigned long long)rem);
+      if (!FIRST) {
+        const int pos = atomicAdd(&h->tile_count, 1);
+        p.tiles[pos] = make_int2(X, Y);
+      }
+      atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][1], (unsigned long long)rem);
     }
   }
   // exact worklist size: edges of this tile with a touched endpoint
-  const int tU = lane < xl ? p.touched[cur][xs + lane] : 0;
-  const int tV = v < yl ? p.touched[cur][ys + v] : 0;
-  const unsigned long long TV = __ballot(tV != 0);
-  const int cnt = wave_sum(lane < xl ? __popcll(Eu & (tU ? ~0ull : TV)) : 0);
-  if (lane == 0 && cnt) atomicAdd(&h->ctr[cur][2], (unsigned long long)cnt);
+  int cnt;
+  if (FIRST) {
+    cnt = wave_sum(lane < xl ? __popcll(Eu) : 0);
+  } else {
+    const int tU = lane < xl ? p.touched[cur][xs + lane] : 0;
+    const int tV = v < yl ? p.touched[cur][ys + v] : 0;
+    const unsigned long long TV = __ballot(tV != 0);
+    cnt = wave_sum(lane < xl ? __popcll(Eu & (tU ? ~0ull : TV)) : 0);
+  }
+  if (lane == 0 && cnt) atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][2], (unsigned long long)cnt);
 }
 
-// Copies the changed tiles of this pass from Anext into A.
-__global__ void __launch_bounds__(128) k_apply(Plan p) {
+// Copies the changed tiles of this pass from scratch into the state.
+__global__ void __launch_bounds__(128) k_apply(Plan p, const uint64_t *__restrict__ scratch,
+                                               uint64_t *__restrict__ cur) {
   const Hdr *h = p.hdr;
   if (stage1_bad(h)) return;
   const int R = h->R;
@@ -435,20 +590,20 @@ __global__ void __launch_bounds__(128) k_apply(Plan p) {
       j -= 64;
       if (j < p.blen[t.y]) idx = (long long)(p.bstart[t.y] + j) * R + t.x;
     }
-    if (idx >= 0) p.A[idx] = p.Anext[idx];
+    if (idx >= 0) cur[idx] = scratch[idx];
   }
 }
 
 // Bit rows -> dense u8 masks in caller order.  One workgroup per caller row.
-__global__ void __launch_bounds__(256) k_unpack_dense(Plan p, const int *colour, uint8_t *vmask,
-                                                      uint8_t *emask, int use_lds) {
+__global__ void __launch_bounds__(256) k_unpack_dense(Plan p, const int *colour, const uint64_t *cur,
+                                                      uint8_t *vmask, uint8_t *emask, int use_lds) {
   const Hdr *h = p.hdr;
   if (stage1_bad(h)) return;
   extern __shared__ unsigned long long srow[];
   const int u = blockIdx.x, t = threadIdx.x;
   const int R = h->R, n = p.n;
   const int s = p.inv[u];
-  const uint64_t *row = p.A + (long long)s * R;
+  const uint64_t *row = cur + (long long)s * R;
   if (use_lds) {
     for (int w = t; w < R; w += 256) srow[w] = row[w];
     __syncthreads();
@@ -473,58 +628,48 @@ inline unsigned grid_for(long long work, int threads, long long cap) {
 
 }  // namespace
 
-void launch_init_header(const Plan &p, bool dense, hipStream_t s) {
-  long long work = p.k;
-  if (dense) work = (long long)p.nchunks * p.k;
-  hipLaunchKernelGGL(k_init_header, dim3(grid_for(work, 256, 1024)), dim3(256), 0, s, p, dense ? 1 : 0);
-}
-
-void launch_count(const Plan &p, const int *colour, bool dense, hipStream_t s) {
-  hipLaunchKernelGGL(k_count, dim3(grid_for(p.n, kRankChunk, 1LL << 30)), dim3(kRankChunk), 0, s, p,
-                     colour, dense ? 1 : 0);
-}
-
-void launch_layout(const Plan &p, int row_words, bool bitset, hipStream_t s) {
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(256), 0, s, p, row_words, bitset ? 1 : 0);
+void launch_setup(const Plan &p, const int *colour, int row_words, bool dense, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, p, colour, row_words, dense ? 1 : 0);
 }
 
 void launch_rank(const Plan &p, const int *colour, hipStream_t s) {
   hipLaunchKernelGGL(k_rank, dim3(p.nchunks), dim3(kRankChunk), 0, s, p, colour);
 }
 
-void launch_init_state(const Plan &p, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_state, dim3(grid_for(p.n, 256, 2048)), dim3(256), 0, s, p);
-}
-
-void launch_pack_dense(const Plan &p, const uint8_t *adj, const int *colour, hipStream_t s) {
+void launch_pack_dense(const Plan &p, const uint8_t *adj, const int *colour, uint64_t *dst, hipStream_t s) {
   const int use_lds = p.Rmax <= kPackLdsWords;
   const size_t lds = use_lds ? sizeof(unsigned long long) * (size_t)p.Rmax : 0;
-  hipLaunchKernelGGL(k_pack_dense, dim3(p.n), dim3(256), lds, s, p, adj, colour, use_lds);
+  hipLaunchKernelGGL(k_pack_dense, dim3(p.n), dim3(256), lds, s, p, adj, colour, dst, use_lds);
 }
 
-void launch_copy_rows(const Plan &p, const uint64_t *rows, hipStream_t s) {
-  (void)hipMemcpyAsync(p.A, rows, sizeof(uint64_t) * (size_t)p.n * (size_t)p.Rmax, hipMemcpyDeviceToDevice, s);
+void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uint64_t *dst, int pass,
+                        bool first, hipStream_t s) {
+  const dim3 grid(grid_for(p.n, kWave, 1LL << 30));  // 64 slots per workgroup
+  if (first)
+    hipLaunchKernelGGL(k_vertex<true>, grid, dim3(256), 0, s, p, scls, src, dst, pass);
+  else
+    hipLaunchKernelGGL(k_vertex<false>, grid, dim3(256), 0, s, p, scls, src, dst, pass);
 }
 
-void launch_vertex_pass(const Plan &p, const int *scls, int pass, bool validate, hipStream_t s) {
-  hipLaunchKernelGGL(k_vertex, dim3(grid_for(p.n, 4, 1LL << 30)), dim3(256), 0, s, p, scls, pass,
-                     validate ? 1 : 0);
-}
-
-void launch_edge_pass(const Plan &p, int pass, bool validate, hipStream_t s) {
+void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first, hipStream_t s) {
   if (p.Tmax <= 0) return;
-  hipLaunchKernelGGL(k_edge, dim3((unsigned)p.Tmax), dim3(kEdgeThreads), 0, s, p, pass, validate ? 1 : 0);
+  const dim3 grid((unsigned)p.Tmax);
+  if (first)
+    hipLaunchKernelGGL(k_edge<true>, grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+  else
+    hipLaunchKernelGGL(k_edge<false>, grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
 }
 
-void launch_apply(const Plan &p, hipStream_t s) {
+void launch_apply(const Plan &p, const uint64_t *scratch, uint64_t *cur, hipStream_t s) {
   if (p.Tmax <= 0) return;
-  hipLaunchKernelGGL(k_apply, dim3(grid_for(p.Tmax, 1, 4096)), dim3(128), 0, s, p);
+  hipLaunchKernelGGL(k_apply, dim3(grid_for(p.Tmax, 1, 4096)), dim3(128), 0, s, p, scratch, cur);
 }
 
-void launch_unpack_dense(const Plan &p, const int *colour, uint8_t *vmask, uint8_t *emask, hipStream_t s) {
+void launch_unpack_dense(const Plan &p, const int *colour, const uint64_t *cur, uint8_t *vmask,
+                         uint8_t *emask, hipStream_t s) {
   const int use_lds = p.Rmax <= kPackLdsWords;
   const size_t lds = use_lds ? sizeof(unsigned long long) * (size_t)p.Rmax : 0;
-  hipLaunchKernelGGL(k_unpack_dense, dim3(p.n), dim3(256), lds, s, p, colour, vmask, emask, use_lds);
+  hipLaunchKernelGGL(k_unpack_dense, dim3(p.n), dim3(256), lds, s, p, colour, cur, vmask, emask, use_lds);
 }
 
 }  // namespace kzi
