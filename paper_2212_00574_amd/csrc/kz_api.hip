@@ -124,7 +124,7 @@ kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k) {
   z.off_tiles = take(sizeof(int2) * (size_t)z.Tmax);
   z.off_packed = take(dense ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
   z.off_spare = take(sizeof(uint64_t) * (size_t)n * (size_t)Rmax);
-  z.off_F = take(sizeof(uint64_t) * (size_t)n * (size_t)k);
+  z.off_F = take(2 * sizeof(uint64_t) * (size_t)n * (size_t)k);
   z.total = o;
   return z;
 }

@@ -10,7 +10,6 @@ namespace kzi {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlk = 64;           // slots per block == bits per word
 constexpr int kEdgeThreads = 256;  // 4 waves per edge tile
-constexpr int kChunk = 8;          // third classes an edge tile handles at a time
 constexpr int kRankChunk = 256;    // vertices per stable-partition chunk
 constexpr int kPackLdsWords = 8192;  // dense pack: row assembled in LDS up to this many words
 constexpr int kSetupThreads = 1024;  // the single setup workgroup
@@ -55,7 +54,8 @@ struct Plan {
   int2 *tiles;       // [Tmax] changed tiles of the current pass
   uint64_t *packed;  // [n*Rmax] dense input packed into bit rows (dense only)
   uint64_t *spare;   // [n*Rmax] second state buffer
-  uint64_t *F;       // [k*n] F[c*n + slot]: first word of the slot's class-c segment
+  uint64_t *F;       // [2*k*n] (F[2*(c*n+slot)], F[2*(c*n+slot)+1]): first two words of
+                     // the slot's class-c segment (0 where the segment is shorter)
   int n, k, Rmax, nchunks;
   long long Tmax;    // Rmax*(Rmax-1)/2
 };

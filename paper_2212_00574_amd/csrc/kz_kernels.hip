@@ -304,13 +304,15 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
     for (int c = wid; c < k; c += 4) {
       const int w0 = lds_off ? sOff[1][c] : p.soff[c];
       const int w1 = lds_off ? sOff[1][c + 1] : p.soff[c + 1];
+      ulonglong2 *Fcv = (ulonglong2 *)p.F + ((long long)c * n + v);
       if (w1 == w0) {  // empty class: no neighbour possible
-        if (active) p.F[(long long)c * n + v] = 0;
+        if (active) *Fcv = make_ulonglong2(0ull, 0ull);
         fail |= c != cv;
         continue;
       }
       const unsigned long long x = row[w0];
-      if (active) p.F[(long long)c * n + v] = x;
+      const unsigned long long x1 = w1 - w0 >= 2 ? row[w0 + 1] : 0ull;
+      if (active) *Fcv = make_ulonglong2(x, x1);
       const int cc0 = lds_off ? sOff[0][c] : p.coff[c];
       const int s = (lds_off ? sOff[0][c + 1] : p.coff[c + 1]) - cc0;
       if (c == cv) {
@@ -342,9 +344,9 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
         const unsigned long long last = w1 - 1 == w0 ? x : row[w1 - 1];
         if (last >> (s & 63)) pr = max(pr, P_EINVAL);
       }
-      bool nz = x != 0;
+      bool nz = (x | x1) != 0;
       if (active && !nz)
-        for (int w = w0 + 1; w < w1; ++w)
+        for (int w = w0 + 2; w < w1; ++w)
           if (row[w]) {
             nz = true;
             break;
@@ -380,18 +382,18 @@ __device__ __forceinline__ int third_class(int i, int cx, int cy) {
 // Lane v of each wave stands for slot bstart[Y]+v; wave w handles 16 rows u
 // of block X.  P(u) is the 64-bit set of v with {u,v} still passing.  The
 // tile walks its third classes (every class but class(X) and class(Y)) in
-// chunks of kChunk.  Fast path: the first words of both rows' class-c
-// segments -- row u's from LDS (a broadcast read), row v's from the lane's
-// registers -- are ANDed and a wave ballot gives the lanes that found a
-// common neighbour there; the ballots of the chunk are ANDed.  Padding slots
-// of the last chunk hold all-ones words, so they never drop a lane.  When
-// some edge of u is not covered that way (rare on dense inputs), the slow
-// path redoes u class by class and scans the remaining words of the segment
-// for the lanes still missing a witness.  When a bit of the tile changed,
-// both copies of its new bits go to `dst` (pass 1: the output state, which
-// already holds a copy of the input; later passes: scratch, and the tile is
-// listed for the apply pass).
-template <bool FIRST>
+// chunks of CH, staged from the first-word matrix: the first two words of
+// every row's class-c segment, row u's in LDS (read as broadcasts), row v's
+// in the lane's registers.  Level 1: the first words of u and v are ANDed
+// and a wave ballot gives the lanes with a common neighbour there; the
+// ballots of the chunk are ANDed.  Level 2, when some edge of u is not
+// covered: the same with the first two words.  Level 3 (rare): class by
+// class, the lanes still missing a witness scan the rest of the segment in
+// memory.  Padding slots of the last chunk hold all-ones words, so they never
+// drop a lane.  When a bit of the tile changed, both copies of its new bits
+// go to `dst` (pass 1: the output state, which already holds a copy of the
+// input; later passes: scratch, and the tile is listed for the apply pass).
+template <bool FIRST, int CH>
 __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *__restrict__ src,
                                                        uint64_t *__restrict__ dst, int pass) {
   Hdr *h = p.hdr;
@@ -407,11 +409,13 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
 
   constexpr int kWaves = kEdgeThreads / kWave;
   constexpr int kRowsPerWave = kBlk / kWaves;
-  __shared__ unsigned long long sU[kChunk][kBlk];
+  constexpr int kStage = (CH * kBlk + kEdgeThreads - 1) / kEdgeThreads;
+  __shared__ ulonglong2 sU[CH][kBlk];
+  __shared__ unsigned long long sV2[CH][kBlk];
   __shared__ unsigned long long sE[kBlk], sP[kBlk];
   __shared__ unsigned long long sT[kWaves][kBlk], sTE[kWaves][kBlk];
-  __shared__ int sW[kChunk][2];
-  __shared__ int sC[kChunk];
+  __shared__ int sW[CH][2];
+  __shared__ int sC[CH];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -428,14 +432,15 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
   }
   __syncthreads();  // sE/sP are read by every wave, also when there is no third class
   const uint64_t *rowv = src + (long long)(ys + (lane < yl ? lane : 0)) * R;
+  const ulonglong2 *F = (const ulonglong2 *)p.F;
 
   const int nthird = k - 2;
   const int n = p.n;
   const int ur = tid & 63;                      // staging row of this thread
   const int urc = ur < xl ? ur : xl - 1;        // clamped into the block
   const int vrc = lane < yl ? lane : yl - 1;
-  for (int q = 0; q < nthird; q += kChunk) {
-    if (tid < kChunk) {
+  for (int q = 0; q < nthird; q += CH) {
+    if (tid < CH) {
       const int i = q + tid;
       if (i < nthird) {
         const int c = third_class(i, cx, cy);
@@ -449,51 +454,72 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
       }
     }
     __syncthreads();
-    // coalesced loads from the first-word matrix, then the LDS writes
-    unsigned long long vv[kChunk];
-    unsigned long long uu[kChunk * kBlk / kEdgeThreads];
+    // coalesced 16-byte loads from the first-word matrix, then the LDS writes;
+    // the lane keeps only the first words of its own row v in registers
+    unsigned long long vv[CH];
+    ulonglong2 uu[kStage];
 #pragma unroll
-    for (int e2 = 0; e2 < kChunk * kBlk / kEdgeThreads; ++e2) {
-      const int j = (tid + e2 * kEdgeThreads) >> 6;
-      uu[e2] = p.F[(long long)sC[j] * n + xs + urc];
+    for (int e2 = 0; e2 < kStage; ++e2) {
+      const int e = tid + e2 * kEdgeThreads;
+      const int j = e < CH * kBlk ? e >> 6 : 0;
+      uu[e2] = F[(long long)sC[j] * n + xs + urc];
+    }
+    if (wid == 0) {
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const ulonglong2 f = F[(long long)sC[j] * n + ys + vrc];
+        sV2[j][lane] = sW[j][0] < 0 ? ~0ull : (lane < yl ? f.y : 0ull);
+      }
     }
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) vv[j] = p.F[(long long)sC[j] * n + ys + vrc];
+    for (int j = 0; j < CH; ++j) vv[j] = F[(long long)sC[j] * n + ys + vrc].x;
 #pragma unroll
-    for (int e2 = 0; e2 < kChunk * kBlk / kEdgeThreads; ++e2) {
-      const int j = (tid + e2 * kEdgeThreads) >> 6;
-      sU[j][ur] = sW[j][0] < 0 ? ~0ull : uu[e2];
+    for (int e2 = 0; e2 < kStage; ++e2) {
+      const int e = tid + e2 * kEdgeThreads;
+      if (e < CH * kBlk) {
+        const int j = e >> 6;
+        sU[j][ur] = sW[j][0] < 0 ? make_ulonglong2(~0ull, ~0ull) : uu[e2];
+      }
     }
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) vv[j] = sW[j][0] < 0 ? ~0ull : (lane < yl ? vv[j] : 0ull);
+    for (int j = 0; j < CH; ++j) vv[j] = sW[j][0] < 0 ? ~0ull : (lane < yl ? vv[j] : 0ull);
     __syncthreads();
     for (int ui = 0; ui < kRowsPerWave; ++ui) {
       const int u = wid * kRowsPerWave + ui;
       if (u >= xl) break;
       unsigned long long P = uniform64(sP[u]);
       if (!P) continue;
-      unsigned long long a[kChunk];
-#pragma unroll
-      for (int j = 0; j < kChunk; ++j) a[j] = sU[j][u];
       unsigned long long all = ~0ull;
+      {
+        unsigned long long a[CH];
 #pragma unroll
-      for (int j = 0; j < kChunk; ++j) all &= __ballot((a[j] & vv[j]) != 0ull);
-      if (P & ~all) {
-        // slow path: class by class, scanning the rest of the segment
-        const uint64_t *rowu = src + (long long)(xs + u) * R;
+        for (int j = 0; j < CH; ++j) a[j] = sU[j][u].x;
 #pragma unroll
-        for (int j = 0; j < kChunk; ++j) {
-          unsigned long long miss = P & ~__ballot((a[j] & vv[j]) != 0ull);
-          const int w1 = sW[j][1];
-          for (int w = sW[j][0] + 1; w < w1 && miss; ++w) {
-            const unsigned long long x = rowu[w];
-            const unsigned long long y = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
-            miss &= ~__ballot((x & y) != 0ull);
-          }
-          P &= ~miss;
-        }
-        if (lane == 0) sP[u] = P;
+        for (int j = 0; j < CH; ++j) all &= __ballot((a[j] & vv[j]) != 0ull);
       }
+      if (!(P & ~all)) continue;
+      // level 2: the first two words (re-read from LDS; rare)
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const ulonglong2 a = sU[j][u];
+        all &= __ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
+      }
+      if (!(P & ~all)) continue;
+      // level 3: class by class, scanning the rest of the segment
+      const uint64_t *rowu = src + (long long)(xs + u) * R;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const ulonglong2 a = sU[j][u];
+        unsigned long long miss = P & ~__ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
+        const int w1 = sW[j][1];
+        for (int w = sW[j][0] + 2; w < w1 && miss; ++w) {
+          const unsigned long long x = rowu[w];
+          const unsigned long long y = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
+          miss &= ~__ballot((x & y) != 0ull);
+        }
+        P &= ~miss;
+      }
+      if (lane == 0) sP[u] = P;
     }
     __syncthreads();
   }
@@ -654,10 +680,20 @@ void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uin
 void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first, hipStream_t s) {
   if (p.Tmax <= 0) return;
   const dim3 grid((unsigned)p.Tmax);
-  if (first)
-    hipLaunchKernelGGL(k_edge<true>, grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
-  else
-    hipLaunchKernelGGL(k_edge<false>, grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+  // chunk of third classes: whichever of 6 and 8 pads the k-2 classes least
+  const int nthird = p.k > 2 ? p.k - 2 : 0;
+  const bool six = (nthird + 5) / 6 * 6 < (nthird + 7) / 8 * 8;
+  if (first) {
+    if (six)
+      hipLaunchKernelGGL((k_edge<true, 6>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+    else
+      hipLaunchKernelGGL((k_edge<true, 8>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+  } else {
+    if (six)
+      hipLaunchKernelGGL((k_edge<false, 6>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+    else
+      hipLaunchKernelGGL((k_edge<false, 8>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+  }
 }
 
 void launch_apply(const Plan &p, const uint64_t *scratch, uint64_t *cur, hipStream_t s) {
