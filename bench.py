@@ -24,7 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, published
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+# 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64
+# instruction per SIMD every 4 clocks); bitwise ops have no packed form.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 WORKLOADS = {
     "c1": "k=4 classes x 25 vertices (n=100), p=0.5, dense uint8 input",
@@ -43,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="steps of the per-kernel event-timed loop (default: --steps)")
+    ap.add_argument("--copy-calibration", type=int, default=None, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (memory-counter calibration)")
     return ap.parse_args()
 
 
@@ -75,17 +79,27 @@ def pair_edge_counts(w):
     return cnt
 
 
-def operand_bytes_all_edges(w):
-    """Sum over edges {u,v} of 2 (n - s_cu - s_cv) / 8: the two full rows minus the endpoints' own classes."""
+def edge_work(w):
+    """Per-edge figures of the edge test, summed over all edges of the input.
+
+    operand bytes: 2 (n - s_cu - s_cv) / 8 -- both rows minus the endpoints'
+    own classes, i.e. what a test that streams the rows reads;
+    algorithmic ops: for every third class c, W_c = ceil(s_c/64) words, each
+    one AND and one OR-accumulate on two 32-bit halves (4 ops per word).
+    """
     sizes = np.asarray(w["sizes"], np.int64)
     n = int(sizes.sum())
+    words = (sizes + 63) // 64
+    R = int(words.sum())
     cnt = pair_edge_counts(w)
     k = len(sizes)
-    tot = 0
+    op_bytes, ops = 0, 0
     for a in range(k):
         for b in range(a + 1, k):
-            tot += int(cnt[a, b]) * 2 * (n - sizes[a] - sizes[b]) / 8
-    return tot, int(np.triu(cnt, 1).sum())
+            m_ab = int(cnt[a, b])
+            op_bytes += m_ab * 2 * (n - sizes[a] - sizes[b]) / 8
+            ops += m_ab * 4 * (R - words[a] - words[b])
+    return float(op_bytes), float(ops), int(np.triu(cnt, 1).sum())
 
 
 def source_hash():
@@ -96,17 +110,27 @@ def source_hash():
 
 
 def traffic_from_profile(workload):
-    """HBM bytes per edge-kernel launch from the committed counter summary, if current."""
-    path = os.path.join(ROOT, "profiles", "k_edge_%s_traffic.json" % workload)
+    """HBM bytes per edge-pass launch from the committed counter summary.
+
+    Read from profiles/k_edge_<workload>.md ("- hbm_bytes_per_launch: B" and
+    "- source_sha: S"); None when absent or when the kernels changed since
+    the counters were taken.
+    """
+    path = os.path.join(ROOT, "profiles", "k_edge_%s.md" % workload)
     if not os.path.exists(path):
         return None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("- ") and ":" in line:
+            key, val = line[2:].split(":", 1)
+            vals[key.strip()] = val.strip()
+    if vals.get("source_sha") != source_hash() or "hbm_bytes_per_launch" not in vals:
+        return None
     try:
-        d = json.load(open(path))
+        return float(vals["hbm_bytes_per_launch"])
     except ValueError:
         return None
-    if d.get("source_sha") != source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(w):
@@ -124,8 +148,23 @@ def cpu_baseline(w):
     return res, (vm, em), t2 - t1, t1 - t0
 
 
+def copy_calibration(mib):
+    """Device-to-device copies of a known size, for scaling memory counters."""
+    import torch
+    n = mib * (1 << 20)
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(graphs would shard by class columns; see the design notes).", file=sys.stderr)
@@ -183,24 +222,29 @@ def main():
     edge_avg_ms = edge_ms / max(edge_launches, 1)
     passes = res["passes"]
 
-    op_bytes, m_check = operand_bytes_all_edges(w)
-    # exact-worklist operand bytes over all passes: pass 1 = every edge; later
-    # passes re-test fewer edges (scaled by the tested-edge ratio)
-    alg_bytes_per_step = op_bytes * (res["edge_tests"] / max(res["input_edges"], 1))
-    alg_bytes_per_launch = alg_bytes_per_step / max(passes, 1)
-    achieved = alg_bytes_per_launch / (edge_avg_ms / 1e3) / 1e9
+    op_bytes, ops, m_check = edge_work(w)
+    # exact-worklist work over all passes: pass 1 tests every edge; later
+    # passes fewer (scaled by the tested-edge ratio)
+    scale = res["edge_tests"] / max(res["input_edges"], 1)
+    ops_per_launch = ops * scale / max(edge_launches / psteps, 1)
+    bytes_per_launch = op_bytes * scale / max(edge_launches / psteps, 1)
+    achieved = ops_per_launch / (edge_avg_ms / 1e3) / 1e12
+    stream_gbps = bytes_per_launch / (edge_avg_ms / 1e3) / 1e9
     traffic = traffic_from_profile(args.workload)
     roofline = {
         "kernel": "k_edge",
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBPS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": round(VALU_PEAK_TOPS, 2),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / VALU_PEAK_TOPS, 4),
         "traffic": traffic,
+        "ops": "32-bit integer VALU ops (AND, OR) of the full-segment edge test",
+        "alg_ops_per_launch": ops_per_launch,
         "avg_launch_ms": round(edge_avg_ms, 5),
         "launches_per_step": edge_launches / psteps,
-        "alg_bytes_per_launch": alg_bytes_per_launch,
+        "operand_stream_GBps": round(stream_gbps, 1),
+        "operand_stream_frac_of_hbm": round(stream_gbps / HBM_PEAK_GBPS, 3),
     }
 
     cpu = None

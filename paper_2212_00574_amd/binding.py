@@ -146,6 +146,7 @@ class Kernelizer:
         self.device = torch.device("cuda", device)
         self.ctx = kz_create(device)
         self._ws = None
+        self._need = {}
 
     def close(self):
         if self.ctx:
@@ -166,7 +167,10 @@ class Kernelizer:
         return {name: kz_profile_read(self.ctx, i) for i, name in enumerate(KERNELS)}
 
     def workspace(self, graph: kz_graph, k: int) -> torch.Tensor:
-        need = kz_workspace_bytes(self.ctx, graph, k)
+        key = (graph.format, graph.n, graph.row_words, graph.nnz, k)
+        need = self._need.get(key)
+        if need is None:
+            need = self._need[key] = kz_workspace_bytes(self.ctx, graph, k)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         return self._ws

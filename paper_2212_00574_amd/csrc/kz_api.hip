@@ -169,12 +169,14 @@ int kz_create(kz_ctx **out, int device) {
     delete c;
     return KZ_EHIP;
   }
+
   *out = c;
   return KZ_OK;
 }
 
 void kz_destroy(kz_ctx *ctx) {
   if (!ctx) return;
+  if (!ctx->pending.empty()) (void)hipDeviceSynchronize();
   for (auto &p : ctx->pending) {
     ctx->pool.push_back(p.a);
     ctx->pool.push_back(p.b);
@@ -331,9 +333,9 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
         return finish(res, r);
       }
     }
-    unsigned long long c[4] = {0, 0, 0, 0};
+    unsigned long long c[3] = {0, 0, 0};
     for (int slot = 0; slot < kzi::kCtrSlots; ++slot)
-      for (int j = 0; j < 4; ++j) c[j] += h.ctr[pass & 1][slot][j];
+      for (int j = 0; j < 3; ++j) c[j] += h.ctr[pass & 1][slot][j];
     if (first) m = (long long)c[2];
     tests += (long long)c[2];
     removed_v += (long long)c[0];

@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
   Hdr *h = p.hdr;
   const int t = threadIdx.x, n = p.n, k = p.k;
   __shared__ int sh[kSetupLdsClasses];
-  __shared__ int sa[kSetupThreads], sb[kSetupThreads];
+  __shared__ int sa[kSetupThreads / kWave], sb[kSetupThreads / kWave];
   __shared__ int s_bad_colour, s_bad_layout, carry_a, carry_b;
   const bool lds_hist = k <= kSetupLdsClasses;
   if (t == 0) {
@@ -121,31 +121,46 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
     if (t == 0) h->bad_colour = 1;
     return;
   }
+  // exclusive scans of class sizes and segment widths: shuffle scans inside
+  // each wave, then a scan of the wave totals
+  constexpr int kSetupWaves = kSetupThreads / kWave;
+  const int lane = t & 63, wv = t >> 6;
   for (int base = 0; base < k; base += kSetupThreads) {
     const int c = base + t;
     int s = 0;
     if (c < k) s = lds_hist ? sh[c] : atomicAdd(&p.counts[c], 0);
     const int a = s, b = (s + 63) / 64;
-    sa[t] = a;
-    sb[t] = b;
-    __syncthreads();
-    for (int off = 1; off < kSetupThreads; off <<= 1) {  // inclusive Hillis-Steele scan
-      const int xa = t >= off ? sa[t - off] : 0;
-      const int xb = t >= off ? sb[t - off] : 0;
-      __syncthreads();
-      sa[t] += xa;
-      sb[t] += xb;
-      __syncthreads();
+    int ia = a, ib = b;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int xa = __shfl_up(ia, off, kWave), xb = __shfl_up(ib, off, kWave);
+      if (lane >= off) {
+        ia += xa;
+        ib += xb;
+      }
     }
+    if (lane == kWave - 1) {
+      sa[wv] = ia;
+      sb[wv] = ib;
+    }
+    __syncthreads();
+    if (t == 0) {
+      int ra = carry_a, rb = carry_b;
+      for (int w = 0; w < kSetupWaves; ++w) {
+        const int xa = sa[w], xb = sb[w];
+        sa[w] = ra;
+        sb[w] = rb;
+        ra += xa;
+        rb += xb;
+      }
+      carry_a = ra;
+      carry_b = rb;
+    }
+    __syncthreads();
     if (c < k) {
       p.counts[c] = a;
-      p.coff[c] = carry_a + sa[t] - a;
-      p.soff[c] = carry_b + sb[t] - b;
-    }
-    __syncthreads();
-    if (t == kSetupThreads - 1) {
-      carry_a += sa[t];
-      carry_b += sb[t];
+      p.coff[c] = sa[wv] + ia - a;
+      p.soff[c] = sb[wv] + ib - b;
     }
     __syncthreads();
   }
