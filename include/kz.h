@@ -76,8 +76,11 @@ typedef enum {
   KZ_CSR        = 2   /* row_ptr[n+1] (int64), col_idx[nnz] (int32): both
                          directions of every edge, column ids strictly
                          increasing within a row; row_ptr[0] = 0 and
-                         row_ptr[n] = nnz.  Reserved: not implemented yet
-                         (returns KZ_EINVAL).                                 */
+                         row_ptr[n] = nnz; vertices in any order.  k must
+                         not exceed 1024 (host check, KZ_EINVAL).  Suited to
+                         sparse graphs: the edge test first compares the
+                         endpoints' sets of neighbour classes, then merges
+                         the two rows.                                        */
 } kz_format;
 
 typedef struct kz_graph {

@@ -120,7 +120,7 @@ def kz_profile_read(ctx: int, kernel: int) -> tuple[float, int]:
 
 # ----------------------------------------------------------- tensor helpers
 def _dev_ptr(t: torch.Tensor | None) -> int | None:
-    if t is None:
+    if t is None or t.numel() == 0:
         return None
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("expected a contiguous device tensor")
@@ -137,6 +137,13 @@ def graph_bitset(rows: torch.Tensor) -> kz_graph:
     if rows.dtype not in (torch.int64, torch.uint64) or rows.dim() != 2:
         raise ValueError("bitset rows must be a 2-D 64-bit tensor")
     return kz_graph(format=KZ_BITSET_U64, n=rows.shape[0], rows=_dev_ptr(rows), row_words=rows.shape[1])
+
+
+def graph_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor) -> kz_graph:
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:
+        raise ValueError("CSR needs int64 row_ptr and int32 col_idx")
+    return kz_graph(format=KZ_CSR, n=row_ptr.shape[0] - 1, row_ptr=_dev_ptr(row_ptr),
+                    col_idx=_dev_ptr(col_idx) if col_idx.numel() else None, nnz=col_idx.shape[0])
 
 
 class Kernelizer:
@@ -193,6 +200,14 @@ class Kernelizer:
         vmask = torch.empty(n, dtype=torch.uint8, device=self.device)
         emask = torch.empty((n, n), dtype=torch.uint8, device=self.device)
         res = self.run(graph_dense(adj), colour, k, vmask, emask, **kw)
+        return vmask, emask, res
+
+    def kernelize_csr(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, colour: torch.Tensor, k: int, **kw):
+        """(vmask u8[n], emask u8[nnz] aligned with col_idx, result dict) for a CSR graph."""
+        n = row_ptr.shape[0] - 1
+        vmask = torch.empty(n, dtype=torch.uint8, device=self.device)
+        emask = torch.empty(col_idx.shape[0], dtype=torch.uint8, device=self.device)
+        res = self.run(graph_csr(row_ptr, col_idx), colour, k, vmask, emask, **kw)
         return vmask, emask, res
 
     def kernelize_bitset(self, rows: torch.Tensor, colour: torch.Tensor, k: int, **kw):

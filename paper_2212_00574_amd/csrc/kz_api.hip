@@ -83,10 +83,33 @@ bool shape_ok(const kz_graph *g, int32_t k) {
   if (!g || k < 1 || g->n < 0) return false;
   if (g->format == KZ_DENSE_U8) return g->n <= 65536;
   if (g->format == KZ_BITSET_U64) return g->row_words >= 0 && g->row_words <= 65535;
-  return false;  // KZ_CSR: not implemented yet
+  if (g->format == KZ_CSR) return g->nnz >= 0 && k <= 1024 && g->n < 0x7fffffff;
+  return false;
+}
+
+kzi::WsSizes plan_sizes_csr(const kz_graph *g, int32_t k) {
+  kzi::WsSizes z{};
+  const size_t n = (size_t)g->n, nnz = (size_t)g->nnz;
+  size_t o = align_up(sizeof(kzi::Hdr));
+  auto take = [&o](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  z.off_counts = take(sizeof(int) * (size_t)k);
+  z.off_coff = take(sizeof(int) * ((size_t)k + 1));
+  z.off_soff = take(sizeof(int) * ((size_t)k + 1));
+  z.off_touched0 = take(n);
+  z.off_touched1 = take(n);
+  z.off_src = take(sizeof(int32_t) * nnz);
+  z.off_efail = take(nnz);
+  z.off_pm = take(sizeof(uint64_t) * n * (size_t)kzi::csr_words(k));
+  z.total = o;
+  return z;
 }
 
 kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k) {
+  if (g->format == KZ_CSR) return plan_sizes_csr(g, k);
   kzi::WsSizes z{};
   const long long n = g->n;
   const bool dense = g->format == KZ_DENSE_U8;
@@ -144,6 +167,88 @@ int map_hdr_status(const kzi::Hdr &h) {
 int finish(kz_result *res, const kz_result &r) {
   if (res) *res = r;
   return r.status;
+}
+
+// Sparse path: state in place in vmask / emask; every pass is vertex test,
+// edge test, apply, then the counter readback.
+int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, char *base,
+                  const kzi::WsSizes &z, uint8_t *vmask, uint8_t *emask, hipStream_t s, kz_result *res) {
+  kz_result r{};
+  r.status = KZ_EHIP;
+  kzi::Plan p{};
+  p.hdr = (kzi::Hdr *)base;
+  p.counts = (int *)(base + z.off_counts);
+  p.coff = (int *)(base + z.off_coff);
+  p.soff = (int *)(base + z.off_soff);
+  p.touched[0] = (uint8_t *)(base + z.off_touched0);
+  p.touched[1] = (uint8_t *)(base + z.off_touched1);
+  p.src = (int32_t *)(base + z.off_src);
+  p.efail = (uint8_t *)(base + z.off_efail);
+  p.pm = (uint64_t *)(base + z.off_pm);
+  p.n = g->n;
+  p.k = k;
+  const int64_t *rp = g->row_ptr;
+  const int32_t *ci = g->col_idx;
+  const long long nnz = g->nnz;
+  {
+    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+    kzi::launch_setup(p, colour, 0, kzi::SETUP_CSR, s);
+  }
+  {
+    ProfScope t(ctx, KZ_KERNEL_PACK, s);
+    kzi::launch_csr_validate(p, rp, ci, nnz, colour, vmask, emask, s);
+  }
+  if (hipGetLastError() != hipSuccess) return finish(res, r);
+  long long removed_v = 0, removed_e = 0, tests = 0, m = 0;
+  int rounds = 0, pass = 0;
+  for (;;) {
+    ++pass;
+    const bool first = pass == 1;
+    {
+      ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
+      kzi::launch_csr_vertex(p, rp, ci, colour, vmask, emask, pass, first, s);
+    }
+    {
+      ProfScope t(ctx, KZ_KERNEL_EDGE, s);
+      kzi::launch_csr_edge(p, rp, ci, nnz, colour, emask, pass, first, s);
+    }
+    {
+      ProfScope t(ctx, KZ_KERNEL_APPLY, s);
+      kzi::launch_csr_apply(p, ci, nnz, emask, pass, s);
+    }
+    if (hipGetLastError() != hipSuccess) return finish(res, r);
+    if (hipMemcpyAsync(ctx->pinned, p.hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return finish(res, r);
+    prof_collect(ctx);
+    const kzi::Hdr &h = *ctx->pinned;
+    if (first) {
+      const int st = map_hdr_status(h);
+      if (st != KZ_OK) {
+        r.status = st;
+        return finish(res, r);
+      }
+    }
+    unsigned long long c[3] = {0, 0, 0};
+    for (int slot = 0; slot < kzi::kCtrSlots; ++slot)
+      for (int j = 0; j < 3; ++j) c[j] += h.ctr[pass & 1][slot][j];
+    if (first) m = (long long)c[2];
+    tests += (long long)c[2];
+    removed_v += (long long)c[0];
+    removed_e += (long long)c[1];
+    if (c[0] + c[1] == 0) break;
+    ++rounds;
+    if (rounds > g->n + m + 1) return finish(res, r);  // cannot happen: every round removes something
+  }
+  r.status = KZ_OK;
+  r.rounds = rounds;
+  r.equals_input = rounds == 0;
+  r.passes = pass;
+  r.surviving_vertices = g->n - removed_v;
+  r.surviving_edges = m - removed_e;
+  r.input_edges = m;
+  r.edge_tests = tests;
+  return finish(res, r);
 }
 
 }  // namespace
@@ -232,10 +337,13 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   if (!ctx || !shape_ok(g, k)) return finish(res, r);
   const int n = g->n;
   const bool dense = g->format == KZ_DENSE_U8;
+  const bool csr = g->format == KZ_CSR;
   if (n > 0) {
-    if (!colour || !vmask || !emask || !ws) return finish(res, r);
+    if (!colour || !vmask || !ws) return finish(res, r);
+    if (!emask && !(csr && g->nnz == 0)) return finish(res, r);
     if (dense && !g->adj) return finish(res, r);
-    if (!dense && !g->rows) return finish(res, r);
+    if (g->format == KZ_BITSET_U64 && !g->rows) return finish(res, r);
+    if (csr && (!g->row_ptr || (g->nnz > 0 && !g->col_idx))) return finish(res, r);
     if ((uintptr_t)ws % kAlign) return finish(res, r);
   }
   if (n == 0) {
@@ -252,6 +360,8 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   r.status = KZ_EHIP;
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(res, r);
   hipStream_t s = (hipStream_t)stream;
+
+  if (csr) return kernelize_csr(ctx, g, colour, k, (char *)ws, z, vmask, (uint8_t *)emask, s, res);
 
   char *base = (char *)ws;
   kzi::Plan p{};
@@ -289,7 +399,7 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   uint64_t *scratch = dense ? p.packed : p.spare;
   {
     ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_setup(p, colour, g->row_words, dense, s);
+    kzi::launch_setup(p, colour, g->row_words, dense ? kzi::SETUP_DENSE : kzi::SETUP_BITSET, s);
   }
   if (dense) {
     {

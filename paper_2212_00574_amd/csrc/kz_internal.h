@@ -56,6 +56,9 @@ struct Plan {
   uint64_t *spare;   // [n*Rmax] second state buffer
   uint64_t *F;       // [2*k*n] (F[2*(c*n+slot)], F[2*(c*n+slot)+1]): first two words of
                      // the slot's class-c segment (0 where the segment is shorter)
+  int32_t *src;      // [nnz] csr: row of every entry
+  uint8_t *efail;    // [nnz] csr: entry failed the edge test this pass
+  uint64_t *pm;      // [n*KW] csr: classes holding an alive neighbour of each vertex
   int n, k, Rmax, nchunks;
   long long Tmax;    // Rmax*(Rmax-1)/2
 };
@@ -64,7 +67,7 @@ struct WsSizes {
   size_t total;
   size_t off_counts, off_coff, off_soff, off_bcls, off_bstart, off_blen, off_hist, off_perm,
       off_inv, off_scls, off_valive, off_touched0, off_touched1, off_bt0, off_bt1, off_tiles,
-      off_packed, off_spare, off_F;
+      off_packed, off_spare, off_F, off_src, off_efail, off_pm;
   int Rmax, nchunks;
   long long Tmax;
 };
@@ -76,7 +79,8 @@ struct WsSizes {
 // up holding the state after round 1.  Later passes read the state `cur`,
 // write changed tiles into `scratch`, and the apply pass copies them back
 // into `cur`.
-void launch_setup(const Plan &p, const int *colour, int row_words, bool dense, hipStream_t s);
+enum SetupMode : int { SETUP_BITSET = 0, SETUP_DENSE = 1, SETUP_CSR = 2 };
+void launch_setup(const Plan &p, const int *colour, int row_words, SetupMode mode, hipStream_t s);
 void launch_rank(const Plan &p, const int *colour, hipStream_t s);
 void launch_pack_dense(const Plan &p, const uint8_t *adj, const int *colour, uint64_t *dst,
                        hipStream_t s);
@@ -87,5 +91,15 @@ void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pas
 void launch_apply(const Plan &p, const uint64_t *scratch, uint64_t *cur, hipStream_t s);
 void launch_unpack_dense(const Plan &p, const int *colour, const uint64_t *cur, uint8_t *vmask,
                          uint8_t *emask, hipStream_t s);
+
+// Sparse path (kz_csr.hip).  State in place: vmask / emask (per entry).
+int csr_words(int k);  // 64-bit words of a class set: 1, 4 or 16 (k <= 1024)
+void launch_csr_validate(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
+                         uint8_t *vmask, uint8_t *emask, hipStream_t s);
+void launch_csr_vertex(const Plan &p, const int64_t *rp, const int32_t *ci, const int *colour, uint8_t *vmask,
+                       const uint8_t *emask, int pass, bool first, hipStream_t s);
+void launch_csr_edge(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
+                     const uint8_t *emask, int pass, bool first, hipStream_t s);
+void launch_csr_apply(const Plan &p, const int32_t *ci, long long nnz, uint8_t *emask, int pass, hipStream_t s);
 
 }  // namespace kzi

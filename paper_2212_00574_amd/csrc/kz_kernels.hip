@@ -69,9 +69,10 @@ __device__ __forceinline__ void tri_decode(long long t, int NB, int &X, int &Y) 
 // One workgroup: zeroes the header, counts the classes (stage-1 colour
 // checks), scans class and segment offsets and fills the block table.  For
 // dense input it also builds per-chunk class histograms for the stable
-// partition.
+// partition; for CSR input only the header and the colour checks matter.
 __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colour, int row_words,
-                                                         int dense) {
+                                                         int mode) {
+  const bool dense = mode == SETUP_DENSE, bitset = mode == SETUP_BITSET;
   Hdr *h = p.hdr;
   const int t = threadIdx.x, n = p.n, k = p.k;
   __shared__ int sh[kSetupLdsClasses];
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
       atomicAdd(&p.counts[c], 1);
     if (dense)
       atomicAdd(&p.hist[(long long)(u / kRankChunk) * k + c], 1);
-    else if (u > 0 && colour[u - 1] > c)
+    else if (bitset && u > 0 && colour[u - 1] > c)
       s_bad_layout = 1;
   }
   __syncthreads();
@@ -167,8 +168,8 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
   if (t == 0) {
     p.coff[k] = carry_a;
     p.soff[k] = carry_b;
-    int R = carry_b;
-    if (!dense && R != row_words) s_bad_layout = 1;
+    int R = bitset || dense ? carry_b : 0;
+    if (bitset && R != row_words) s_bad_layout = 1;
     if (s_bad_layout) {
       h->bad_layout = 1;
       R = row_words;
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
     h->R = R;
   }
   __syncthreads();
-  if (s_bad_layout) return;
+  if (s_bad_layout || mode == SETUP_CSR) return;
   // each thread reads back only the entries it wrote itself above
   for (int c = t; c < k; c += kSetupThreads) {
     const int s = p.counts[c];
@@ -669,8 +670,8 @@ inline unsigned grid_for(long long work, int threads, long long cap) {
 
 }  // namespace
 
-void launch_setup(const Plan &p, const int *colour, int row_words, bool dense, hipStream_t s) {
-  hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, p, colour, row_words, dense ? 1 : 0);
+void launch_setup(const Plan &p, const int *colour, int row_words, SetupMode mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupThreads), 0, s, p, colour, row_words, (int)mode);
 }
 
 void launch_rank(const Plan &p, const int *colour, hipStream_t s) {

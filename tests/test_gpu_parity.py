@@ -17,7 +17,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from oracle import kernelize_bitset, kernelize_dense  # noqa: E402
+from oracle import kernelize_bitset, kernelize_csr, kernelize_dense  # noqa: E402
 from paper_2212_00574_amd import inputs  # noqa: E402
 from paper_2212_00574_amd.binding import Kernelizer, KzError  # noqa: E402
 
@@ -63,7 +63,16 @@ def run_bitset(kz, rows, colour, k, ctx=""):
     return res, vm.cpu().numpy(), em.cpu().numpy().view(np.uint64)
 
 
+def run_csr(kz, rp, ci, colour, k, ctx=""):
+    say("csr", ctx, len(rp) - 1, len(ci), "k=%d" % k)
+    vm, em, res = kz.kernelize_csr(torch.from_numpy(rp).to(DEV), torch.from_numpy(ci).to(DEV),
+                                   torch.from_numpy(colour).to(DEV), k)
+    torch.cuda.synchronize()
+    return res, vm.cpu().numpy(), em.cpu().numpy()
+
+
 def both_formats(kz, g, k, ctx):
+    """Dense, bitset and CSR runs of one graph, each against the oracle."""
     adj, colour = g.dense()
     ref = kernelize_dense(adj, colour, k)
     res, vm, em = run_dense(kz, adj, colour, k, ctx)
@@ -72,6 +81,10 @@ def both_formats(kz, g, k, ctx):
     refb = kernelize_bitset(rows, scol, k)
     resb, vmb, emb = run_bitset(kz, rows, scol, k, ctx)
     check_same(resb, refb, vmb, emb, ctx + " bitset")
+    rp, ci = inputs.dense_to_csr(adj)
+    refc = kernelize_csr(rp, ci, colour, k)
+    resc, vmc, emc = run_csr(kz, rp, ci, colour, k, ctx)
+    check_same(resc, refc, vmc, emc, ctx + " csr")
     return ref
 
 
@@ -225,6 +238,43 @@ def test_bitset_validation(kz):
     assert got == -1
 
 
+def test_csr_validation(kz):
+    g = inputs.make_graph([20, 30, 25], 0.4, seed=3, gid=5)
+    adj, colour = g.dense()
+    rp, ci = inputs.dense_to_csr(adj)
+    row = int(np.argmax(np.diff(rp)))          # a row with several entries
+    b = int(rp[row])
+    cases = {}
+    bad = ci.copy(); bad[b], bad[b + 1] = bad[b + 1], bad[b]
+    cases["unsorted"] = (rp, bad)
+    bad = ci.copy(); bad[b] = len(colour) + 3
+    cases["range"] = (rp, bad)
+    bad_rp = rp.copy(); bad_rp[-1] -= 1
+    cases["row_ptr"] = (bad_rp, ci)
+    a = adj.copy(); a[4, 4] = 1
+    cases["loop"] = inputs.dense_to_csr(a)
+    a = adj.copy(); other = int(np.nonzero(colour != colour[0])[0][0]); a[0, other] ^= 1
+    cases["asym"] = inputs.dense_to_csr(a)
+    same = np.nonzero(colour == colour[0])[0]
+    a = adj.copy(); a[same[0], same[1]] = a[same[1], same[0]] = 1
+    cases["intra"] = inputs.dense_to_csr(a)
+    for name, (r, c) in cases.items():
+        want = kernelize_csr(r, c, colour, 3)["status"]
+        got = status_of(kz, lambda: run_csr(kz, r, c, colour, 3, name))
+        assert want != 0 and got == want, (name, got, want)
+    # k above the CSR limit is rejected on the host
+    assert status_of(kz, lambda: run_csr(kz, rp, ci, colour, 2000, "k")) == -1
+
+
+def test_csr_sparse_generator_graphs(kz):
+    """Uneven classes and uniform sparse pairs (the large sparse workload's shape, scaled down)."""
+    for seed, (n, k, m) in enumerate([(3000, 8, 9000), (5000, 30, 125000), (2000, 5, 30000)]):
+        sg = inputs.make_sparse(n, k, m, seed=seed)
+        ref = kernelize_csr(sg.row_ptr, sg.col_idx, sg.colour, k)
+        res, vm, em = run_csr(kz, sg.row_ptr, sg.col_idx, sg.colour, k, "sparse%d" % seed)
+        check_same(res, ref, vm, em, "sparse%d" % seed)
+
+
 def test_workspace_too_small(kz):
     adj = torch.zeros((10, 10), dtype=torch.uint8, device=DEV)
     colour = torch.zeros(10, dtype=torch.int32, device=DEV)
@@ -242,6 +292,14 @@ def test_workspace_too_small(kz):
 
 
 # ------------------------------------------------ full-size bench workload
+def test_config3b_full_size(kz):
+    """Large sparse workload: n=100000, k=30 multinomial classes, 2.5M edges, CSR."""
+    sg = inputs.config3b(0)
+    res, vm, em = run_csr(kz, sg.row_ptr, sg.col_idx, sg.colour, 30, "config3b")
+    ref = kernelize_csr(sg.row_ptr, sg.col_idx, sg.colour, 30)
+    check_same(res, ref, vm, em, "config3b")
+
+
 def test_config2_full_size(kz):
     """The benchmark's workload (k=10 x 300, p=0.6, planted 10-clique) against the full oracle."""
     g = inputs.config2(0)
