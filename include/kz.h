@@ -49,7 +49,8 @@ extern "C" {
 #define KZ_EWORKSPACE (-6)  /* workspace smaller than kz_workspace_bytes()       */
 #define KZ_ENOMEM     (-7)  /* host staging allocation failed                    */
 #define KZ_EHIP       (-8)  /* a HIP runtime call failed                         */
-#define KZ_EAGAIN     (-9)  /* reserved                                          */
+#define KZ_EAGAIN     (-9)  /* serving: no slot or memory free yet               */
+#define KZ_ETOOLARGE  (-10) /* batch: graph beyond the batched path's limits     */
 
 /* Input validation happens in two stages and reports one code:
  *   1. colours: any colour outside [0,k) -> KZ_ECOLOUR; otherwise, for the
@@ -147,6 +148,60 @@ int kz_workspace_bytes(const kz_ctx *ctx, const kz_graph *g, int32_t k, size_t *
 int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k,
                  void *ws, size_t ws_bytes, uint8_t *vmask, void *emask,
                  void *stream, kz_result *res);
+
+/* ------------------------------------------------------------ batches
+ * Many small graphs kernelized together in one persistent launch: every
+ * workgroup takes the next graph from a device queue and runs that graph's
+ * synchronous rounds to the fixpoint (same results as kz_kernelize on each
+ * graph alone).  All graphs use the KZ_BITSET_U64 layout and sit in shared
+ * arenas:
+ *   rows   (uint64): graph g's n*row_words words start at rows + row_offset;
+ *   colour (int32) and vmask (uint8): graph g's n entries start at
+ *          vertex_offset;
+ *   emask  (uint64): same layout as rows (must not overlap it).
+ * Limits of the batched path: k <= 64, row_words <= 512, n <= 4096; a graph
+ * beyond them gets status KZ_ETOOLARGE in its result (run it through
+ * kz_kernelize).  The call is asynchronous: it enqueues the work on the
+ * stream and returns; results[g] (device memory) is valid in stream order.
+ * It performs no host synchronisation, so a caller may capture it in a
+ * hipGraph and replay it. */
+typedef struct kz_batch_graph {
+  int32_t n, k, row_words, reserved;
+  int64_t row_offset;     /* in uint64 words */
+  int64_t vertex_offset;  /* in vertices */
+} kz_batch_graph;
+
+typedef struct kz_batch_config {
+  int32_t waves;       /* waves per workgroup: 4, 8 or 16                 */
+  int32_t chunk;       /* third classes staged per step: 4 or 8 (4 when
+                          waves is 16)                                     */
+  int32_t lpt;         /* 1: largest graphs first; 0: given order         */
+  int32_t workgroups;  /* persistent workgroups (0 = fill the device)     */
+} kz_batch_config;
+
+/* Workspace bytes kz_kernelize_batch needs for these graphs (host array),
+ * large enough for every configuration the autotuner may pick. */
+int kz_batch_workspace_bytes(const kz_ctx *ctx, const kz_batch_graph *graphs, int32_t G, size_t *bytes);
+
+/* Kernelizes G graphs.  graphs_host and graphs_dev hold the same
+ * descriptors (the host copy sizes the work, the device copy is read by the
+ * kernels).  results: kz_result[G] in device memory. */
+int kz_kernelize_batch(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_batch_graph *graphs_dev,
+                       int32_t G, const uint64_t *rows, const int32_t *colour, void *ws, size_t ws_bytes,
+                       uint8_t *vmask, uint64_t *emask, kz_result *results, void *stream);
+
+/* Times the candidate configurations on this batch (synchronously, on the
+ * stream) and keeps the fastest for later kz_kernelize_batch calls on this
+ * context; *best receives it. */
+int kz_batch_autotune(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_batch_graph *graphs_dev,
+                      int32_t G, const uint64_t *rows, const int32_t *colour, void *ws, size_t ws_bytes,
+                      uint8_t *vmask, uint64_t *emask, kz_result *results, void *stream,
+                      kz_batch_config *best);
+
+/* Sets / reads the configuration kz_kernelize_batch uses (for example one
+ * the autotuner picked in an earlier process). */
+int kz_batch_set_config(kz_ctx *ctx, const kz_batch_config *cfg);
+int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
 
 /* ------------------------------------------------------------ measurement
  * When enabled, kz_kernelize brackets every kernel launch with HIP events

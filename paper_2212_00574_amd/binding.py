@@ -19,7 +19,9 @@ KZ_EWORKSPACE, KZ_ENOMEM, KZ_EHIP, KZ_EAGAIN = -6, -7, -8, -9
 KZ_DENSE_U8, KZ_BITSET_U64, KZ_CSR = 0, 1, 2
 
 EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_kernelize",
-            "kz_profile_enable", "kz_profile_read")
+            "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
+            "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config")
+KZ_ETOOLARGE = -10
 KERNELS = ("setup", "pack", "vertex", "edge", "apply", "unpack")
 
 
@@ -38,6 +40,23 @@ class kz_result(C.Structure):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
+class kz_batch_config(C.Structure):
+    _fields_ = [("waves", C.c_int32), ("chunk", C.c_int32), ("lpt", C.c_int32), ("workgroups", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+# numpy layouts of kz_batch_graph and kz_result (device arrays are filled from / read into these)
+import numpy as np  # noqa: E402
+
+BATCH_GRAPH_DTYPE = np.dtype([("n", "<i4"), ("k", "<i4"), ("row_words", "<i4"), ("reserved", "<i4"),
+                              ("row_offset", "<i8"), ("vertex_offset", "<i8")])
+RESULT_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("equals_input", "<i4"), ("passes", "<i4"),
+                         ("surviving_vertices", "<i8"), ("surviving_edges", "<i8"), ("input_edges", "<i8"),
+                         ("edge_tests", "<i8")])
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libkz.so is not built (run __graft_entry__.build()); there is no fallback")
@@ -54,6 +73,17 @@ def _load() -> C.CDLL:
     lib.kz_kernelize.restype = C.c_int
     lib.kz_kernelize.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, C.c_size_t, vp, vp, vp,
                                  C.POINTER(kz_result)]
+    lib.kz_batch_workspace_bytes.restype = C.c_int
+    lib.kz_batch_workspace_bytes.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.kz_kernelize_batch.restype = C.c_int
+    lib.kz_kernelize_batch.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, C.c_size_t, vp, vp, vp, vp]
+    lib.kz_batch_autotune.restype = C.c_int
+    lib.kz_batch_autotune.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, C.c_size_t, vp, vp, vp, vp,
+                                      C.POINTER(kz_batch_config)]
+    lib.kz_batch_set_config.restype = C.c_int
+    lib.kz_batch_set_config.argtypes = [vp, C.POINTER(kz_batch_config)]
+    lib.kz_batch_get_config.restype = C.c_int
+    lib.kz_batch_get_config.argtypes = [vp, C.POINTER(kz_batch_config)]
     lib.kz_profile_enable.restype = C.c_int
     lib.kz_profile_enable.argtypes = [vp, C.c_int]
     lib.kz_profile_read.restype = C.c_int
@@ -116,6 +146,44 @@ def kz_profile_read(ctx: int, kernel: int) -> tuple[float, int]:
     if st != KZ_OK:
         raise KzError(st, "kz_profile_read")
     return float(ms.value), int(n.value)
+
+
+def kz_batch_workspace_bytes(ctx: int, graphs_host: np.ndarray) -> int:
+    b = C.c_size_t(0)
+    st = LIB.kz_batch_workspace_bytes(ctx, graphs_host.ctypes.data, len(graphs_host), C.byref(b))
+    if st != KZ_OK:
+        raise KzError(st, "kz_batch_workspace_bytes")
+    return int(b.value)
+
+
+def kz_kernelize_batch(ctx: int, graphs_host: np.ndarray, graphs_dev: int, G: int, rows: int, colour: int,
+                       ws: int, ws_bytes: int, vmask: int, emask: int, results: int, stream: int) -> int:
+    return int(LIB.kz_kernelize_batch(ctx, graphs_host.ctypes.data, graphs_dev, G, rows, colour, ws, ws_bytes,
+                                      vmask, emask, results, stream))
+
+
+def kz_batch_autotune(ctx: int, graphs_host: np.ndarray, graphs_dev: int, G: int, rows: int, colour: int,
+                      ws: int, ws_bytes: int, vmask: int, emask: int, results: int, stream: int) -> dict:
+    best = kz_batch_config()
+    st = LIB.kz_batch_autotune(ctx, graphs_host.ctypes.data, graphs_dev, G, rows, colour, ws, ws_bytes,
+                               vmask, emask, results, stream, C.byref(best))
+    if st != KZ_OK:
+        raise KzError(st, "kz_batch_autotune")
+    return best.as_dict()
+
+
+def kz_batch_set_config(ctx: int, cfg: dict) -> None:
+    st = LIB.kz_batch_set_config(ctx, C.byref(kz_batch_config(**cfg)))
+    if st != KZ_OK:
+        raise KzError(st, "kz_batch_set_config")
+
+
+def kz_batch_get_config(ctx: int) -> dict:
+    cfg = kz_batch_config()
+    st = LIB.kz_batch_get_config(ctx, C.byref(cfg))
+    if st != KZ_OK:
+        raise KzError(st, "kz_batch_get_config")
+    return cfg.as_dict()
 
 
 # ----------------------------------------------------------- tensor helpers
@@ -216,3 +284,83 @@ class Kernelizer:
         emask = torch.empty_like(rows)
         res = self.run(graph_bitset(rows), colour, k, vmask, emask, **kw)
         return vmask, emask, res
+
+
+class Batch:
+    """Arenas, descriptors and results of one batch of bit-row graphs on a device.
+
+    ``graphs`` is a list of (rows uint64 [n, R], colour int32 [n], k).
+    """
+
+    def __init__(self, graphs, device):
+        self.device = torch.device(device)
+        G = len(graphs)
+        desc = np.zeros(G, BATCH_GRAPH_DTYPE)
+        ro, vo = 0, 0
+        for i, (rows, colour, k) in enumerate(graphs):
+            n, R = (rows.shape[0], rows.shape[1]) if rows.ndim == 2 else (len(colour), 0)
+            desc[i] = (n, k, R, 0, ro, vo)
+            ro += n * R
+            vo += n
+        self.G = G
+        self.desc = desc
+        rows_all = np.zeros(max(ro, 1), np.uint64)
+        col_all = np.zeros(max(vo, 1), np.int32)
+        for i, (rows, colour, k) in enumerate(graphs):
+            n, R = int(desc[i]["n"]), int(desc[i]["row_words"])
+            a, b = int(desc[i]["row_offset"]), int(desc[i]["vertex_offset"])
+            rows_all[a:a + n * R] = np.asarray(rows, np.uint64).reshape(-1)
+            col_all[b:b + n] = colour
+        self.rows = torch.from_numpy(rows_all.view(np.int64)).to(self.device)
+        self.colour = torch.from_numpy(col_all).to(self.device)
+        self.desc_dev = torch.from_numpy(desc.view(np.uint8)).to(self.device)
+        self.vmask = torch.empty(max(vo, 1), dtype=torch.uint8, device=self.device)
+        self.emask = torch.empty_like(self.rows)
+        self.results = torch.zeros(max(G, 1) * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+
+    def args(self):
+        return (self.desc, self.desc_dev.data_ptr(), self.G, self.rows.data_ptr(), self.colour.data_ptr())
+
+    def outputs(self):
+        return self.vmask.data_ptr(), self.emask.data_ptr(), self.results.data_ptr()
+
+    def read_results(self) -> np.ndarray:
+        return self.results.cpu().numpy()[:self.G * RESULT_DTYPE.itemsize].view(RESULT_DTYPE)
+
+    def masks(self, i):
+        """(vmask u8[n], emask uint64 [n, R]) of graph i (host copies)."""
+        d = self.desc[i]
+        n, R = int(d["n"]), int(d["row_words"])
+        a, b = int(d["row_offset"]), int(d["vertex_offset"])
+        vm = self.vmask[b:b + n].cpu().numpy()
+        em = self.emask[a:a + n * R].cpu().numpy().view(np.uint64).reshape(n, R)
+        return vm, em
+
+
+class BatchKernelizer:
+    """kz_kernelize_batch on one device with a reusable workspace."""
+
+    def __init__(self, kz: Kernelizer):
+        self.kz = kz
+        self._ws = None
+
+    def workspace(self, batch: Batch) -> torch.Tensor:
+        need = kz_batch_workspace_bytes(self.kz.ctx, batch.desc)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=batch.device)
+        return self._ws
+
+    def run(self, batch: Batch, stream: torch.cuda.Stream | None = None) -> None:
+        """Enqueues the batch on the stream (asynchronous)."""
+        ws = self.workspace(batch)
+        s = stream if stream is not None else torch.cuda.current_stream(batch.device)
+        st = kz_kernelize_batch(self.kz.ctx, *batch.args(), ws.data_ptr(), ws.numel(), *batch.outputs(),
+                                s.cuda_stream)
+        if st != KZ_OK:
+            raise KzError(st, "kz_kernelize_batch")
+
+    def autotune(self, batch: Batch) -> dict:
+        ws = self.workspace(batch)
+        s = torch.cuda.current_stream(batch.device)
+        return kz_batch_autotune(self.kz.ctx, *batch.args(), ws.data_ptr(), ws.numel(), *batch.outputs(),
+                                 s.cuda_stream)

@@ -25,6 +25,10 @@ struct kz_ctx {
   std::vector<Pending> pending;
   double total_ms[KZ_KERNEL_COUNT];
   int64_t launches[KZ_KERNEL_COUNT];
+  // batched path
+  kzi::BatchConfig batch_cfg;
+  bool batch_cfg_set;
+  int cus;  // compute units of the device
 };
 
 namespace {
@@ -169,6 +173,90 @@ int finish(kz_result *res, const kz_result &r) {
   return r.status;
 }
 
+// ---- batched path
+constexpr int kBatchMaxWorkgroups = 1024;
+
+struct BatchWs {
+  size_t off_queue, off_order, off_scratch, total;
+  long long scratch_words, list_offset;
+};
+
+bool batch_fits(const kz_batch_graph &g) {
+  return g.n >= 0 && g.k >= 1 && g.row_words >= 0 && g.k <= kzi::kBatchK && g.row_words <= kzi::kBatchR &&
+         g.n <= kzi::kBatchN;
+}
+
+BatchWs batch_ws(const kz_batch_graph *graphs, int32_t G) {
+  BatchWs w{};
+  long long max_nr = 0, max_t = 0;
+  for (int32_t i = 0; i < G; ++i) {
+    const kz_batch_graph &g = graphs[i];
+    if (!batch_fits(g)) continue;
+    const long long nr = (long long)g.n * g.row_words;
+    const long long t = (long long)g.row_words * (g.row_words - 1) / 2;
+    if (nr > max_nr) max_nr = nr;
+    if (t > max_t) max_t = t;
+  }
+  w.list_offset = (max_nr + 31) / 32 * 32;
+  w.scratch_words = (w.list_offset + (max_t + 1) / 2 + 1 + 31) / 32 * 32;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  w.off_queue = take(sizeof(int));
+  w.off_order = take(sizeof(int) * (size_t)G);
+  w.off_scratch = take(sizeof(uint64_t) * (size_t)w.scratch_words * kBatchMaxWorkgroups);
+  w.total = o;
+  return w;
+}
+
+int batch_workgroups(const kz_ctx *ctx, const kzi::BatchConfig &cfg, int32_t G) {
+  int wg = cfg.workgroups > 0 ? cfg.workgroups : ctx->cus * (16 / cfg.waves);
+  if (wg > kBatchMaxWorkgroups) wg = kBatchMaxWorkgroups;
+  if (wg > G) wg = G;
+  return wg < 1 ? 1 : wg;
+}
+
+bool batch_cfg_ok(const kzi::BatchConfig &c) {
+  return (c.waves == 4 || c.waves == 8 || c.waves == 16) && (c.chunk == 4 || c.chunk == 8) &&
+         !(c.waves == 16 && c.chunk == 8) &&
+         (c.lpt == 0 || c.lpt == 1) && c.workgroups >= 0 && c.workgroups <= kBatchMaxWorkgroups;
+}
+
+int batch_launch(kz_ctx *ctx, const kzi::BatchConfig &cfg, const kz_batch_graph *graphs_host,
+                 const kz_batch_graph *graphs_dev, int32_t G, const uint64_t *rows, const int32_t *colour,
+                 void *ws, size_t ws_bytes, uint8_t *vmask, uint64_t *emask, kz_result *results,
+                 hipStream_t s) {
+  if (!ctx || G < 0 || (G > 0 && (!graphs_host || !graphs_dev || !rows || !colour || !ws || !vmask ||
+                                  !emask || !results)))
+    return KZ_EINVAL;
+  if (G == 0) return KZ_OK;
+  if ((uintptr_t)ws % kAlign) return KZ_EINVAL;
+  const BatchWs w = batch_ws(graphs_host, G);
+  if (ws_bytes < w.total) return KZ_EWORKSPACE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return KZ_EHIP;
+  char *base = (char *)ws;
+  kzi::BatchArgs a{};
+  a.graphs = graphs_dev;
+  a.G = G;
+  a.order = (int *)(base + w.off_order);
+  a.queue = (int *)(base + w.off_queue);
+  a.rows = rows;
+  a.colour = colour;
+  a.emask = emask;
+  a.vmask = vmask;
+  a.results = results;
+  a.scratch = (uint64_t *)(base + w.off_scratch);
+  a.scratch_words = w.scratch_words;
+  a.list_offset = w.list_offset;
+  kzi::BatchConfig c = cfg;
+  c.workgroups = batch_workgroups(ctx, cfg, G);
+  kzi::launch_batch(a, c, s);
+  return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
+}
+
 // Sparse path: state in place in vmask / emask; every pass is vertex test,
 // edge test, apply, then the counter readback.
 int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, char *base,
@@ -265,6 +353,9 @@ int kz_create(kz_ctx **out, int device) {
   c->device = device;
   c->pinned = nullptr;
   c->prof = false;
+  c->batch_cfg_set = false;
+  c->batch_cfg = kzi::BatchConfig{8, 8, 1, 0};
+  c->cus = 256;
   for (int i = 0; i < KZ_KERNEL_COUNT; ++i) {
     c->total_ms[i] = 0.0;
     c->launches[i] = 0;
@@ -275,6 +366,9 @@ int kz_create(kz_ctx **out, int device) {
     return KZ_EHIP;
   }
 
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->cus = cus;
   *out = c;
   return KZ_OK;
 }
@@ -289,6 +383,81 @@ void kz_destroy(kz_ctx *ctx) {
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
+}
+
+int kz_batch_workspace_bytes(const kz_ctx *ctx, const kz_batch_graph *graphs, int32_t G, size_t *bytes) {
+  if (!ctx || !bytes || G < 0 || (G > 0 && !graphs)) return KZ_EINVAL;
+  *bytes = batch_ws(graphs, G).total;
+  return KZ_OK;
+}
+
+int kz_kernelize_batch(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_batch_graph *graphs_dev,
+                       int32_t G, const uint64_t *rows, const int32_t *colour, void *ws, size_t ws_bytes,
+                       uint8_t *vmask, uint64_t *emask, kz_result *results, void *stream) {
+  if (!ctx) return KZ_EINVAL;
+  return batch_launch(ctx, ctx->batch_cfg, graphs_host, graphs_dev, G, rows, colour, ws, ws_bytes, vmask, emask,
+                      results, (hipStream_t)stream);
+}
+
+int kz_batch_set_config(kz_ctx *ctx, const kz_batch_config *cfg) {
+  if (!ctx || !cfg) return KZ_EINVAL;
+  const kzi::BatchConfig c{cfg->waves, cfg->chunk, cfg->lpt, cfg->workgroups};
+  if (!batch_cfg_ok(c)) return KZ_EINVAL;
+  ctx->batch_cfg = c;
+  ctx->batch_cfg_set = true;
+  return KZ_OK;
+}
+
+int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg) {
+  if (!ctx || !cfg) return KZ_EINVAL;
+  cfg->waves = ctx->batch_cfg.waves;
+  cfg->chunk = ctx->batch_cfg.chunk;
+  cfg->lpt = ctx->batch_cfg.lpt;
+  cfg->workgroups = ctx->batch_cfg.workgroups;
+  return KZ_OK;
+}
+
+int kz_batch_autotune(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_batch_graph *graphs_dev,
+                      int32_t G, const uint64_t *rows, const int32_t *colour, void *ws, size_t ws_bytes,
+                      uint8_t *vmask, uint64_t *emask, kz_result *results, void *stream,
+                      kz_batch_config *best) {
+  if (!ctx || !best) return KZ_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  static const kzi::BatchConfig cands[] = {{4, 4, 1, 0}, {4, 8, 1, 0}, {8, 4, 1, 0}, {8, 8, 1, 0},
+                                           {16, 4, 1, 0}, {8, 4, 0, 0}};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KZ_EHIP;
+  int st = KZ_OK;
+  float best_ms = 0.f;
+  kzi::BatchConfig pick = ctx->batch_cfg;
+  for (const kzi::BatchConfig &c : cands) {
+    st = batch_launch(ctx, c, graphs_host, graphs_dev, G, rows, colour, ws, ws_bytes, vmask, emask, results, s);
+    if (st != KZ_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = KZ_EHIP; break; }
+    for (int rep = 0; rep < 2 && st == KZ_OK; ++rep)
+      st = batch_launch(ctx, c, graphs_host, graphs_dev, G, rows, colour, ws, ws_bytes, vmask, emask, results, s);
+    if (st != KZ_OK) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = KZ_EHIP;
+      break;
+    }
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != KZ_OK) return st;
+  ctx->batch_cfg = pick;
+  ctx->batch_cfg_set = true;
+  best->waves = pick.waves;
+  best->chunk = pick.chunk;
+  best->lpt = pick.lpt;
+  best->workgroups = pick.workgroups;
+  return KZ_OK;
 }
 
 int kz_profile_enable(kz_ctx *ctx, int on) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kz.h"
+
 namespace kzi {
 
 constexpr int kWave = 64;          // CDNA wavefront
@@ -101,5 +103,33 @@ void launch_csr_vertex(const Plan &p, const int64_t *rp, const int32_t *ci, cons
 void launch_csr_edge(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
                      const uint8_t *emask, int pass, bool first, hipStream_t s);
 void launch_csr_apply(const Plan &p, const int32_t *ci, long long nnz, uint8_t *emask, int pass, hipStream_t s);
+
+// Batched path (kz_batch.hip).
+constexpr int kBatchK = 64;          // classes
+constexpr int kBatchR = 512;         // words per row (blocks)
+constexpr int kBatchN = 4096;        // vertices
+constexpr int kBatchSortMax = 8192;  // graphs ordered by work on the device up to this count
+constexpr int kBatchTooLarge = KZ_ETOOLARGE;
+
+struct BatchArgs {
+  const kz_batch_graph *graphs;
+  int G;
+  int *order;     // [G]
+  int *queue;     // next graph to take
+  const uint64_t *rows;
+  const int *colour;
+  uint64_t *emask;
+  uint8_t *vmask;
+  kz_result *results;
+  uint64_t *scratch;        // per workgroup: changed words (n*R) then the changed-tile list
+  long long scratch_words;  // words per workgroup
+  long long list_offset;    // words before the changed-tile list
+};
+
+struct BatchConfig {
+  int waves, chunk, lpt, workgroups;
+};
+
+void launch_batch(const BatchArgs &a, const BatchConfig &cfg, hipStream_t s);
 
 }  // namespace kzi

@@ -25,8 +25,10 @@ def lib():
 
 
 def test_header_declares_the_entry_points():
-    assert declared() == ["kz_create", "kz_destroy", "kz_kernelize", "kz_profile_enable", "kz_profile_read",
-                          "kz_strerror", "kz_workspace_bytes"]
+    assert declared() == ["kz_batch_autotune", "kz_batch_get_config", "kz_batch_set_config",
+                          "kz_batch_workspace_bytes", "kz_create", "kz_destroy", "kz_kernelize",
+                          "kz_kernelize_batch", "kz_profile_enable", "kz_profile_read", "kz_strerror",
+                          "kz_workspace_bytes"]
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -62,3 +64,12 @@ def test_product_does_not_reference_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "kz_oracle" not in text and "kzo_" not in text, f
+
+
+def test_struct_layouts_match_the_header():
+    import ctypes as C
+    from paper_2212_00574_amd import binding as b
+    assert C.sizeof(b.kz_result) == b.RESULT_DTYPE.itemsize == 48
+    assert b.BATCH_GRAPH_DTYPE.itemsize == 32
+    assert C.sizeof(b.kz_graph) == 56
+    assert C.sizeof(b.kz_batch_config) == 16
