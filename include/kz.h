@@ -150,21 +150,25 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
                  void *stream, kz_result *res);
 
 /* ------------------------------------------------------------ batches
- * Many small graphs kernelized together in one persistent launch: every
- * workgroup takes the next graph from a device queue and runs that graph's
- * synchronous rounds to the fixpoint (same results as kz_kernelize on each
- * graph alone).  All graphs use the KZ_BITSET_U64 layout and sit in shared
+ * Many small graphs kernelized together in one persistent launch (same
+ * results as kz_kernelize on each graph alone).  Each graph is a job of
+ * synchronous passes; a workgroup takes the next graph from a device queue
+ * and runs its passes; once the queue is empty, workgroups without a graph
+ * claim items (vertex chunks, block tiles) of the passes still running, and
+ * whichever workgroup finishes a pass carries the graph on (nobody waits for
+ * anybody).  All graphs use the KZ_BITSET_U64 layout and sit in shared
  * arenas:
  *   rows   (uint64): graph g's n*row_words words start at rows + row_offset;
  *   colour (int32) and vmask (uint8): graph g's n entries start at
  *          vertex_offset;
  *   emask  (uint64): same layout as rows (must not overlap it).
- * Limits of the batched path: k <= 64, row_words <= 512, n <= 4096; a graph
- * beyond them gets status KZ_ETOOLARGE in its result (run it through
- * kz_kernelize).  The call is asynchronous: it enqueues the work on the
- * stream and returns; results[g] (device memory) is valid in stream order.
- * It performs no host synchronisation, so a caller may capture it in a
- * hipGraph and replay it. */
+ * The graphs' row ranges must not overlap.  Limits of the batched path:
+ * k <= 64, row_words <= 128 (n <= 4096 and k <= 64 never need more), n <=
+ * 4096; a graph beyond them gets status KZ_ETOOLARGE in its result (run it
+ * through kz_kernelize); negative offsets give KZ_EINVAL.  The call is
+ * asynchronous: it enqueues the work on the stream and returns; results[g]
+ * (device memory) is valid in stream order.  It performs no host
+ * synchronisation, so a caller may capture it in a hipGraph and replay it. */
 typedef struct kz_batch_graph {
   int32_t n, k, row_words, reserved;
   int64_t row_offset;     /* in uint64 words */
@@ -177,10 +181,17 @@ typedef struct kz_batch_config {
                           waves is 16)                                     */
   int32_t lpt;         /* 1: largest graphs first; 0: given order         */
   int32_t workgroups;  /* persistent workgroups (0 = fill the device)     */
+  int32_t share;       /* 0: a pass with more items than the workgroup has
+                          waves is shared once the queue is empty;
+                          1: every pass is shared (tests the cross-
+                          workgroup path); 2: never (one workgroup per
+                          graph)                                           */
 } kz_batch_config;
 
 /* Workspace bytes kz_kernelize_batch needs for these graphs (host array),
- * large enough for every configuration the autotuner may pick. */
+ * the same for every configuration: the queue, a job record per graph
+ * (about 2.3 KB), and per row word one next-state word and two list ints
+ * up to the highest row_offset + n*row_words. */
 int kz_batch_workspace_bytes(const kz_ctx *ctx, const kz_batch_graph *graphs, int32_t G, size_t *bytes);
 
 /* Kernelizes G graphs.  graphs_host and graphs_dev hold the same
@@ -223,6 +234,24 @@ int kz_profile_enable(kz_ctx *ctx, int on);
 
 /* Accumulated milliseconds and launch count of one kernel family. */
 int kz_profile_read(const kz_ctx *ctx, int kernel, double *total_ms, int64_t *launches);
+
+/* ------------------------------------------------------------ synthetic inputs
+ * Not part of the method: materialises a seeded random legally coloured
+ * graph in the KZ_BITSET_U64 layout directly in device memory (for
+ * benchmarks and servers that must not generate large graphs on the host).
+ * Class c holds sizes[c] vertices (class-major slots); an inter-class slot
+ * pair {a < b} is an edge iff
+ *   splitmix64(splitmix64((seed << 32) | gid) ^ ((a << 32) | b)) < floor(p * 2^64)
+ * (splitmix64 = the output function of Steele, Lea and Flood's SplitMix64,
+ * OOPSLA 2014); pairs inside a class never are.  planted (host, k slot ids,
+ * one per class, or NULL) forces a k-clique on those slots.
+ *   k: 1..64; sizes: host int32[k], >= 0; p in [0, 1];
+ *   rows: device uint64[n * row_words], row_words = sum ceil(sizes[c]/64)
+ *         (KZ_EINVAL otherwise);
+ *   colour: device int32[n] receiving the sorted colours, or NULL.
+ * Asynchronous on the stream. */
+int kz_gen_bitset(kz_ctx *ctx, int32_t k, const int32_t *sizes, double p, uint32_t seed, uint32_t gid,
+                  const int32_t *planted, uint64_t *rows, int32_t row_words, int32_t *colour, void *stream);
 
 #ifdef __cplusplus
 }

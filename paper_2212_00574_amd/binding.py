@@ -20,7 +20,7 @@ KZ_DENSE_U8, KZ_BITSET_U64, KZ_CSR = 0, 1, 2
 
 EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_kernelize",
             "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
-            "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config")
+            "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset")
 KZ_ETOOLARGE = -10
 KERNELS = ("setup", "pack", "vertex", "edge", "apply", "unpack")
 
@@ -41,7 +41,8 @@ class kz_result(C.Structure):
 
 
 class kz_batch_config(C.Structure):
-    _fields_ = [("waves", C.c_int32), ("chunk", C.c_int32), ("lpt", C.c_int32), ("workgroups", C.c_int32)]
+    _fields_ = [("waves", C.c_int32), ("chunk", C.c_int32), ("lpt", C.c_int32), ("workgroups", C.c_int32),
+                ("share", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -88,6 +89,8 @@ def _load() -> C.CDLL:
     lib.kz_profile_enable.argtypes = [vp, C.c_int]
     lib.kz_profile_read.restype = C.c_int
     lib.kz_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.kz_gen_bitset.restype = C.c_int
+    lib.kz_gen_bitset.argtypes = [vp, C.c_int32, vp, C.c_double, C.c_uint32, C.c_uint32, vp, vp, C.c_int32, vp, vp]
     return lib
 
 
@@ -184,6 +187,17 @@ def kz_batch_get_config(ctx: int) -> dict:
     if st != KZ_OK:
         raise KzError(st, "kz_batch_get_config")
     return cfg.as_dict()
+
+
+def kz_gen_bitset(ctx: int, sizes, p: float, seed: int, gid: int, planted, rows: int, row_words: int,
+                  colour: int | None, stream: int | None) -> None:
+    """Materialises a seeded random graph's bit rows on the device (see kz.h)."""
+    sz = np.ascontiguousarray(np.asarray(sizes, np.int32))
+    pl = None if planted is None else np.ascontiguousarray(np.asarray(planted, np.int32))
+    st = LIB.kz_gen_bitset(ctx, len(sz), sz.ctypes.data, float(p), int(seed), int(gid),
+                           None if pl is None else pl.ctypes.data, rows, int(row_words), colour, stream)
+    if st != KZ_OK:
+        raise KzError(st, "kz_gen_bitset")
 
 
 # ----------------------------------------------------------- tensor helpers

@@ -177,28 +177,25 @@ int finish(kz_result *res, const kz_result &r) {
 constexpr int kBatchMaxWorkgroups = 1024;
 
 struct BatchWs {
-  size_t off_queue, off_order, off_scratch, total;
-  long long scratch_words, list_offset;
+  size_t off_queue, off_finished, off_board, off_order, off_jobs, off_next, off_lists, total;
 };
 
 bool batch_fits(const kz_batch_graph &g) {
-  return g.n >= 0 && g.k >= 1 && g.row_words >= 0 && g.k <= kzi::kBatchK && g.row_words <= kzi::kBatchR &&
-         g.n <= kzi::kBatchN;
+  return g.n >= 0 && g.k >= 1 && g.row_words >= 0 && g.row_offset >= 0 && g.vertex_offset >= 0 &&
+         g.k <= kzi::kBatchK && g.row_words <= kzi::kBatchR && g.n <= kzi::kBatchN;
 }
 
+// Arenas indexed like rows: the next-state words (one word per row word) and
+// the tile lists (two ints per row word).
 BatchWs batch_ws(const kz_batch_graph *graphs, int32_t G) {
   BatchWs w{};
-  long long max_nr = 0, max_t = 0;
+  long long extent = 0;
   for (int32_t i = 0; i < G; ++i) {
     const kz_batch_graph &g = graphs[i];
     if (!batch_fits(g)) continue;
-    const long long nr = (long long)g.n * g.row_words;
-    const long long t = (long long)g.row_words * (g.row_words - 1) / 2;
-    if (nr > max_nr) max_nr = nr;
-    if (t > max_t) max_t = t;
+    const long long end = g.row_offset + (long long)g.n * g.row_words;
+    if (end > extent) extent = end;
   }
-  w.list_offset = (max_nr + 31) / 32 * 32;
-  w.scratch_words = (w.list_offset + (max_t + 1) / 2 + 1 + 31) / 32 * 32;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
     size_t at = o;
@@ -206,23 +203,28 @@ BatchWs batch_ws(const kz_batch_graph *graphs, int32_t G) {
     return at;
   };
   w.off_queue = take(sizeof(int));
+  w.off_finished = take(sizeof(int));
+  w.off_board = take(sizeof(int) * kzi::kBatchBoard);
   w.off_order = take(sizeof(int) * (size_t)G);
-  w.off_scratch = take(sizeof(uint64_t) * (size_t)w.scratch_words * kBatchMaxWorkgroups);
+  w.off_jobs = take(sizeof(kzi::BatchJob) * (size_t)G);
+  w.off_next = take(sizeof(uint64_t) * (size_t)extent);
+  w.off_lists = take(2 * sizeof(int) * (size_t)extent);
   w.total = o;
   return w;
 }
 
-int batch_workgroups(const kz_ctx *ctx, const kzi::BatchConfig &cfg, int32_t G) {
+// Persistent workgroups: as many as fit on the device at once (also for
+// small batches: workgroups without a graph help with the running ones).
+int batch_workgroups(const kz_ctx *ctx, const kzi::BatchConfig &cfg) {
   int wg = cfg.workgroups > 0 ? cfg.workgroups : ctx->cus * (16 / cfg.waves);
   if (wg > kBatchMaxWorkgroups) wg = kBatchMaxWorkgroups;
-  if (wg > G) wg = G;
   return wg < 1 ? 1 : wg;
 }
 
 bool batch_cfg_ok(const kzi::BatchConfig &c) {
   return (c.waves == 4 || c.waves == 8 || c.waves == 16) && (c.chunk == 4 || c.chunk == 8) &&
-         !(c.waves == 16 && c.chunk == 8) &&
-         (c.lpt == 0 || c.lpt == 1) && c.workgroups >= 0 && c.workgroups <= kBatchMaxWorkgroups;
+         !(c.waves == 16 && c.chunk == 8) && (c.lpt == 0 || c.lpt == 1) && c.workgroups >= 0 &&
+         c.workgroups <= kBatchMaxWorkgroups && c.share >= 0 && c.share <= 2;
 }
 
 int batch_launch(kz_ctx *ctx, const kzi::BatchConfig &cfg, const kz_batch_graph *graphs_host,
@@ -241,18 +243,21 @@ int batch_launch(kz_ctx *ctx, const kzi::BatchConfig &cfg, const kz_batch_graph 
   kzi::BatchArgs a{};
   a.graphs = graphs_dev;
   a.G = G;
+  a.share = cfg.share;
   a.order = (int *)(base + w.off_order);
   a.queue = (int *)(base + w.off_queue);
+  a.finished = (int *)(base + w.off_finished);
+  a.board = (int *)(base + w.off_board);
+  a.jobs = (kzi::BatchJob *)(base + w.off_jobs);
   a.rows = rows;
   a.colour = colour;
   a.emask = emask;
   a.vmask = vmask;
   a.results = results;
-  a.scratch = (uint64_t *)(base + w.off_scratch);
-  a.scratch_words = w.scratch_words;
-  a.list_offset = w.list_offset;
+  a.next = (uint64_t *)(base + w.off_next);
+  a.lists = (int *)(base + w.off_lists);
   kzi::BatchConfig c = cfg;
-  c.workgroups = batch_workgroups(ctx, cfg, G);
+  c.workgroups = batch_workgroups(ctx, cfg);
   kzi::launch_batch(a, c, s);
   return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
 }
@@ -354,7 +359,7 @@ int kz_create(kz_ctx **out, int device) {
   c->pinned = nullptr;
   c->prof = false;
   c->batch_cfg_set = false;
-  c->batch_cfg = kzi::BatchConfig{8, 8, 1, 0};
+  c->batch_cfg = kzi::BatchConfig{8, 8, 1, 0, 0};
   c->cus = 256;
   for (int i = 0; i < KZ_KERNEL_COUNT; ++i) {
     c->total_ms[i] = 0.0;
@@ -401,7 +406,7 @@ int kz_kernelize_batch(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_
 
 int kz_batch_set_config(kz_ctx *ctx, const kz_batch_config *cfg) {
   if (!ctx || !cfg) return KZ_EINVAL;
-  const kzi::BatchConfig c{cfg->waves, cfg->chunk, cfg->lpt, cfg->workgroups};
+  const kzi::BatchConfig c{cfg->waves, cfg->chunk, cfg->lpt, cfg->workgroups, cfg->share};
   if (!batch_cfg_ok(c)) return KZ_EINVAL;
   ctx->batch_cfg = c;
   ctx->batch_cfg_set = true;
@@ -414,6 +419,7 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg) {
   cfg->chunk = ctx->batch_cfg.chunk;
   cfg->lpt = ctx->batch_cfg.lpt;
   cfg->workgroups = ctx->batch_cfg.workgroups;
+  cfg->share = ctx->batch_cfg.share;
   return KZ_OK;
 }
 
@@ -423,8 +429,8 @@ int kz_batch_autotune(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_b
                       kz_batch_config *best) {
   if (!ctx || !best) return KZ_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  static const kzi::BatchConfig cands[] = {{4, 4, 1, 0}, {4, 8, 1, 0}, {8, 4, 1, 0}, {8, 8, 1, 0},
-                                           {16, 4, 1, 0}, {8, 4, 0, 0}};
+  static const kzi::BatchConfig cands[] = {{4, 4, 1, 0, 0}, {4, 8, 1, 0, 0}, {8, 4, 1, 0, 0},
+                                           {8, 8, 1, 0, 0}, {16, 4, 1, 0, 0}, {8, 4, 0, 0, 0}};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return KZ_EHIP;
   int st = KZ_OK;
@@ -457,7 +463,56 @@ int kz_batch_autotune(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_b
   best->chunk = pick.chunk;
   best->lpt = pick.lpt;
   best->workgroups = pick.workgroups;
+  best->share = pick.share;
   return KZ_OK;
+}
+
+int kz_gen_bitset(kz_ctx *ctx, int32_t k, const int32_t *sizes, double p, uint32_t seed, uint32_t gid,
+                  const int32_t *planted, uint64_t *rows, int32_t row_words, int32_t *colour, void *stream) {
+  if (!ctx || k < 1 || k > kzi::kGenK || !sizes || !(p >= 0.0 && p <= 1.0)) return KZ_EINVAL;
+  kzi::GenArgs g{};
+  g.k = k;
+  long long n = 0, R = 0;
+  for (int c = 0; c < k; ++c) {
+    if (sizes[c] < 0) return KZ_EINVAL;
+    g.coff[c] = (int)n;
+    g.soff[c] = (int)R;
+    n += sizes[c];
+    R += (sizes[c] + 63) / 64;
+    if (n > INT32_MAX / 2) return KZ_EINVAL;
+  }
+  g.coff[k] = (int)n;
+  g.soff[k] = (int)R;
+  if (R != row_words || (n > 0 && !rows)) return KZ_EINVAL;
+  g.n = (int)n;
+  g.R = (int)R;
+  g.planted = planted != nullptr;
+  for (int c = 0; planted && c < k; ++c) {
+    if (planted[c] < g.coff[c] || planted[c] >= g.coff[c + 1]) return KZ_EINVAL;
+    g.pl[c] = planted[c];
+  }
+  // floor(p * 2^64) from the exact binary value of p
+  if (p <= 0.0) {
+    g.thr = 0;
+  } else if (p >= 1.0) {
+    g.thr = ~0ull;
+  } else {
+    int ex = 0;
+    const double f = frexp(p, &ex);  // p = f * 2^ex, f in [0.5, 1)
+    const unsigned long long mant = (unsigned long long)ldexp(f, 53);  // exact
+    const int sh = ex + 11;          // p * 2^64 = mant * 2^(ex + 11)
+    g.thr = sh >= 0 ? mant << sh : (-sh >= 64 ? 0ull : mant >> -sh);
+  }
+  auto mix = [](unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  g.base = mix(((unsigned long long)seed << 32) | gid);
+  if (hipSetDevice(ctx->device) != hipSuccess) return KZ_EHIP;
+  kzi::launch_gen_rows(g, rows, colour, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
 }
 
 int kz_profile_enable(kz_ctx *ctx, int on) {

@@ -1,24 +1,44 @@
-// Batched kernelization (gfx950): many small graphs in one persistent launch.
+// Batched kernelization (gfx950): many graphs in one persistent launch.
 //
-// Every workgroup repeatedly takes the next graph from an atomic queue and
-// runs that graph's synchronous rounds to the fixpoint on its own, using
-// workgroup barriers as the per-graph round barriers (no workgroup ever waits
-// for another, so the launch cannot deadlock).  Within a workgroup the waves
-// take 64x64 block tiles one at a time (one wave per tile).
+// Each graph is a job: a sequence of synchronous passes (Definition 4.2.1's
+// vertex and edge colour-index tests, applied to a snapshot), and each pass
+// is a list of items: 64-vertex chunks for the vertex test and 64x64 block
+// tiles (X < Y) for the edge test.  A workgroup takes the next graph from an
+// atomic queue, sets it up and lists its first pass; its waves split the
+// items.  The workgroup that finishes the last item of a pass carries the
+// job on: it applies the tiles that changed and either ends the job or lists
+// the next pass.
+//
+// While the queue still holds graphs a pass belongs to the workgroup that
+// listed it ("solo": no other workgroup touches the job, so no cross-
+// workgroup fences are needed).  Once the queue is empty, a pass with more
+// items than the workgroup has waves is "shared": it is published on a
+// board, and workgroups left without work claim runs of its items with a
+// compare-and-swap on the job's claim word, keep their counts and touched
+// bits in LDS, and merge them into the job's state in HBM before they report
+// the run finished.  The run that completes the pass makes its workgroup the
+// carrier.  Nobody waits for anybody: a pass is continued by whoever
+// finishes it, so the launch cannot deadlock, and a workgroup with nothing
+// to do leaves once every graph is finished (or after a few milliseconds
+// without finding work).
 //
 // Graph g's rows follow the bit-row layout of the single-graph path
 // (class-major slots; class c's segment has ceil(s_c/64) words) and sit at
 // word offset row_offset[g] of the rows arena; its colours and vertex mask at
-// vertex_offset[g].  The state is kept in the emask arena (same layout);
-// changed words of a round are staged in the workgroup's slice of scratch.
-// Graphs too large for this path (k > kBatchK, row words > kBatchR, or
-// n > kBatchN) get status KZ_ETOOLARGE in their result and are left to the
-// single-graph path.
+// vertex_offset[g].  The state is kept in the emask arena (same layout); the
+// changed words of a pass go to the next-state arena (same layout); the
+// changed-tile list and the item list sit at int offset 2*row_offset[g] of
+// the list arena.  Graphs too large for this path (k > kBatchK, row words >
+// kBatchR, or n > kBatchN) get status KZ_ETOOLARGE in their result and are
+// left to the single-graph path.
 #include "kz_internal.h"
 
 namespace kzi {
 
 namespace {
+
+constexpr int kVertexItem = 1 << 30;                 // item = kVertexItem | chunk, else X | Y << 8
+constexpr unsigned long long kIdleTicks = 2000000;   // 20 ms of the 100 MHz wall clock
 
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long x, int lane) {
   const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, lane);
@@ -32,85 +52,415 @@ __device__ __forceinline__ int bsum(int x) {
   return x;
 }
 
-__device__ __forceinline__ void tri(long long t, int NB, int &X, int &Y) {
-  auto start = [NB](long long x) { return x * (2LL * NB - x - 1) / 2; };
-  double d = 2.0 * NB - 1.0;
-  long long x = (long long)((d - sqrt(d * d - 8.0 * (double)t)) * 0.5);
-  if (x < 0) x = 0;
-  if (x > NB - 2) x = NB - 2;
-  while (x > 0 && start(x) > t) --x;
-  while (x < NB - 2 && start(x + 1) <= t) ++x;
-  X = (int)x;
-  Y = (int)(t - start(x) + x + 1);
-}
-
 __device__ __forceinline__ bool tbit(const unsigned *b, int i) { return (b[i >> 5] >> (i & 31)) & 1u; }
 
-struct BatchShared {
+__device__ __forceinline__ unsigned long long lanes_below(int lane) {
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Agent-scope relaxed accesses to the job's shared words.
+template <typename T>
+__device__ __forceinline__ T ald(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void ast(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// What a workgroup keeps in LDS about the job it works on.
+struct BatchLds {
   int coff[kBatchK + 1], soff[kBatchK + 1];
   short bcls[kBatchR];
-  int bstart[kBatchR];
+  unsigned short bstart[kBatchR];
   unsigned char blen[kBatchR];
-  unsigned touched[2][kBatchN / 32];
-  unsigned btouched[2][kBatchR / 32];
-  int gi, bad_colour, bad_layout, prio, next_item, nchanged;
+  unsigned tc[kBatchN / 32], tn[kBatchN / 32];    // vertices touched in the previous / this pass
+  unsigned btc[kBatchR / 32], btn[kBatchR / 32];  // blocks touched in the previous / this pass
+  int job, pass;       // the job and pass the copies above belong to
+  int shared, opener;  // the pass is shared; this workgroup listed it
+  int got, base, cnt, nitems, next_item, last, reload;
+  int prio, nchanged;  // this run (solo: this pass)
   unsigned long long removed_v, removed_e, tests;
+  int gi, queue_empty, bad_colour, bad_layout, pick, quit, end, status;
 };
 
-// One graph, one workgroup.  NW waves, CH third classes per staging chunk.
+struct GView {
+  int g, n, k, R;
+  const uint64_t *rows;
+  uint64_t *cur, *nxt;
+  const int *colour;
+  uint8_t *valive;
+  int *changed, *items;
+  BatchJob *J;
+};
+
+__device__ __forceinline__ GView gview(const BatchArgs &a, int g) {
+  const kz_batch_graph G = a.graphs[g];
+  GView v;
+  v.g = g;
+  v.n = G.n;
+  v.k = G.k;
+  v.R = G.row_words;
+  v.rows = a.rows + G.row_offset;
+  v.cur = a.emask + G.row_offset;
+  v.nxt = a.next + G.row_offset;
+  v.colour = a.colour + G.vertex_offset;
+  v.valive = a.vmask + G.vertex_offset;
+  const long long T = (long long)v.R * (v.R - 1) / 2;
+  v.changed = a.lists + 2 * G.row_offset;
+  v.items = v.changed + T;
+  v.J = a.jobs + g;
+  return v;
+}
+
+// ---- vertex test on 64 vertices (one wave): vertex v fails when some other
+// class holds none of its neighbours; pass 1 also validates the rows.
+__device__ void vertex_chunk(const GView &V, BatchLds &S, int v0, bool first, int lane) {
+  const int n = V.n, k = V.k, R = V.R;
+  const uint64_t *src = V.cur;
+  const int v = v0 + lane;
+  const bool act = v < n && (first || (V.valive[v] && tbit(S.tc, v)));
+  if (!__ballot(act)) return;
+  const uint64_t *row = src + (long long)(act ? v : v0) * R;
+  const int cv = act ? V.colour[v] : -1;
+  bool fail = false;
+  int pr = 0;
+  for (int c = 0; c < k; ++c) {
+    const int w0 = S.soff[c], w1 = S.soff[c + 1];
+    const int s = S.coff[c + 1] - S.coff[c];
+    if (!act) continue;
+    if (w1 == w0) {
+      fail |= c != cv;
+      continue;
+    }
+    if (first && (s & 63) && (row[w1 - 1] >> (s & 63))) pr = max(pr, P_EINVAL);
+    if (c == cv) {
+      if (!first) continue;
+      const int jv = v - S.coff[c];
+      for (int w = w0; w < w1; ++w) {
+        unsigned long long y = row[w];
+        if (w == w1 - 1 && (s & 63)) y &= (1ull << (s & 63)) - 1;
+        while (y) {
+          const int b = __builtin_ctzll(y);
+          y &= y - 1;
+          const int t = S.coff[c] + (w - w0) * 64 + b;
+          if (t == v) pr = max(pr, P_ESELFLOOP);
+          else
+            pr = max(pr, ((src[(long long)t * R + w0 + (jv >> 6)] >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL
+                                                                                         : (int)P_EASYM);
+        }
+      }
+      continue;
+    }
+    bool nz = false;
+    for (int w = w0; w < w1 && !nz; ++w) nz = row[w] != 0;
+    fail |= !nz;
+  }
+  if (pr) atomicMax(&S.prio, pr);
+  fail = fail && act;
+  if (act) {
+    if (first) V.valive[v] = fail ? 0 : 1;
+    else if (fail) V.valive[v] = 0;
+  }
+  const int nf = bsum(fail ? 1 : 0);
+  if (lane == 0 && nf) atomicAdd(&S.removed_v, (unsigned long long)nf);
+}
+
+// ---- edge test on tile (X, Y) (one wave): edge (u, v) fails when some third
+// class holds no common neighbour.  Only pairs with a touched endpoint are
+// tested again after pass 1; the others keep their outcome.
+template <int CH>
+__device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int lane,
+                     unsigned long long (*sU)[kBlk], unsigned long long (*sU2)[kBlk], unsigned long long *sPw) {
+  const int R = V.R;
+  const uint64_t *src = V.cur;
+  const int cx = S.bcls[X], cy = S.bcls[Y];
+  const int xs = S.bstart[X], xl = S.blen[X], ys = S.bstart[Y], yl = S.blen[Y];
+  const unsigned long long ymask = yl == 64 ? ~0ull : ((1ull << yl) - 1);
+  const unsigned long long xmask = xl == 64 ? ~0ull : ((1ull << xl) - 1);
+  const uint64_t *rowu_l = src + (long long)(xs + (lane < xl ? lane : 0)) * R;  // lane as row u
+  const uint64_t *rowv = src + (long long)(ys + (lane < yl ? lane : 0)) * R;    // lane as row v
+  const unsigned long long Eu = lane < xl ? (rowu_l[Y] & ymask) : 0ull;          // E(u) of row u = lane
+  const unsigned long long ET = lane < yl ? rowv[X] : 0ull;
+  const unsigned long long TU = first ? ~0ull : __ballot(lane < xl && tbit(S.tc, xs + lane));
+  const unsigned long long TV = first ? ~0ull : __ballot(lane < yl && tbit(S.tc, ys + lane));
+  sPw[lane] = Eu;
+  const int nthird = V.k - 2;
+  for (int q = 0; q < nthird; q += CH) {
+    // stage the first two words of each third-class segment: row u's in LDS
+    // (read as broadcasts), row v's in registers
+    unsigned long long vv[CH], vv2[CH];
+    int w2[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int i = q + j;
+      if (i < nthird) {
+        int c = i;
+        if (c >= cx) ++c;
+        if (c >= cy) ++c;
+        const int w0 = S.soff[c], w1 = S.soff[c + 1];
+        const bool has = w1 > w0, two = w1 > w0 + 1;
+        sU[j][lane] = (has && lane < xl) ? rowu_l[w0] : 0ull;
+        sU2[j][lane] = (two && lane < xl) ? rowu_l[w0 + 1] : 0ull;
+        vv[j] = (has && lane < yl) ? rowv[w0] : 0ull;
+        vv2[j] = (two && lane < yl) ? rowv[w0 + 1] : 0ull;
+        w2[j] = w0 + 2 < w1 ? w0 + 2 : -1;
+      } else {
+        sU[j][lane] = ~0ull;
+        sU2[j][lane] = 0ull;
+        vv[j] = ~0ull;
+        vv2[j] = 0ull;
+        w2[j] = -1;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int u = 0; u < xl; ++u) {
+      unsigned long long P = bcast64(sPw[lane], u);
+      const unsigned long long Pt = P & (((TU >> u) & 1ull) ? ~0ull : TV);
+      if (!Pt) continue;
+      unsigned long long all = ~0ull;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) all &= __ballot((sU[j][u] & vv[j]) != 0ull);
+      if (!(Pt & ~all)) continue;
+      // level 2: the first two words
+      all = ~0ull;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) all &= __ballot(((sU[j][u] & vv[j]) | (sU2[j][u] & vv2[j])) != 0ull);
+      if (!(Pt & ~all)) continue;
+      // level 3: scan the rest of the segment in memory
+      const uint64_t *rowu = src + (long long)(xs + u) * R;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        unsigned long long miss = Pt & ~__ballot(((sU[j][u] & vv[j]) | (sU2[j][u] & vv2[j])) != 0ull);
+        if (!miss) continue;
+        if (w2[j] >= 0) {
+          int c = q + j;
+          if (c >= cx) ++c;
+          if (c >= cy) ++c;
+          for (int w = w2[j]; w < S.soff[c + 1] && miss; ++w) {
+            const unsigned long long x = rowu[w];
+            const unsigned long long y = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
+            miss &= ~__ballot((x & y) != 0ull);
+          }
+        }
+        P &= ~miss;
+      }
+      if (lane == u) sPw[lane] = P;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  const unsigned long long Pu = sPw[lane];
+  // transposes: lane v gathers bit v of P(u) and, in pass 1, of E(u) to check
+  // that the rows are symmetric
+  unsigned long long newET = 0, trE = 0;
+  for (int u = 0; u < xl; ++u) {
+    newET |= ((bcast64(Pu, u) >> lane) & 1ull) << u;
+    if (first) trE |= ((bcast64(Eu, u) >> lane) & 1ull) << u;
+  }
+  if (first && lane < yl && ((trE ^ ET) & xmask)) atomicMax(&S.prio, P_EASYM);
+  const bool chU = lane < xl && Eu != Pu;
+  const bool chV = lane < yl && (ET & xmask) != newET;
+  const unsigned long long bu = __ballot(chU), bv = __ballot(chV);
+  if (bu | bv) {
+    if (lane < xl) V.nxt[(long long)(xs + lane) * R + Y] = Pu;
+    if (lane < yl) V.nxt[(long long)(ys + lane) * R + X] = newET;
+    if (chU) atomicOr(&S.tn[(xs + lane) >> 5], 1u << ((xs + lane) & 31));
+    if (chV) atomicOr(&S.tn[(ys + lane) >> 5], 1u << ((ys + lane) & 31));
+    const int rem = bsum(lane < xl ? __popcll(Eu & ~Pu) : 0);
+    if (lane == 0) {
+      if (bu) atomicOr(&S.btn[X >> 5], 1u << (X & 31));
+      if (bv) atomicOr(&S.btn[Y >> 5], 1u << (Y & 31));
+      const int at = S.shared ? atomicAdd(&V.J->nchanged, 1) : atomicAdd(&S.nchanged, 1);
+      V.changed[at] = X | (Y << 8);
+      atomicAdd(&S.removed_e, (unsigned long long)rem);
+    }
+  }
+  const int cnt = bsum(lane < xl ? __popcll(Eu & (((TU >> lane) & 1ull) ? ~0ull : TV)) : 0);
+  if (lane == 0 && cnt) atomicAdd(&S.tests, (unsigned long long)cnt);
+}
+
+// The waves of the workgroup take the items of the claimed run one by one.
 template <int NW, int CH>
-__device__ void batch_graph(const BatchArgs &a, BatchShared &S, unsigned long long (*sU)[CH][kBlk],
-                            unsigned long long (*sU2)[CH][kBlk], unsigned long long (*sPw)[kBlk], int g) {
+__device__ void run_items(const GView &V, BatchLds &S, unsigned long long (*sU)[CH][kBlk],
+                          unsigned long long (*sU2)[CH][kBlk], unsigned long long (*sPw)[kBlk]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool first = S.pass == 1;
+  const int cnt = S.cnt, base = S.base;
+  for (;;) {
+    int i = 0;
+    if (lane == 0) i = atomicAdd(&S.next_item, 1);
+    i = __builtin_amdgcn_readfirstlane(i);
+    if (i >= cnt) break;
+    const int it = V.items[base + i];
+    if (it & kVertexItem) vertex_chunk(V, S, (it & 0xffff) * kWave, first, lane);
+    else tile<CH>(V, S, it & 0xff, (it >> 8) & 0xff, first, lane, sU[wid], sU2[wid], sPw[wid]);
+  }
+  __syncthreads();
+}
+
+__device__ void write_result(const BatchArgs &a, int g, const kz_result &r) {
+  a.results[g] = r;
+  atomicAdd(a.finished, 1);
+}
+
+// Ends job g with an input error (thread 0).
+__device__ void fail_job(const BatchArgs &a, int g, int status) {
+  kz_result r{};
+  r.status = status;
+  write_result(a, g, r);
+}
+
+// Ends job g after `passes` passes (thread 0).
+__device__ void end_job(const BatchArgs &a, const GView &V, int passes) {
+  BatchJob *J = V.J;
+  const int rounds = ald(&J->rounds);
+  const long long m = ald(&J->m);
+  kz_result r{};
+  r.status = 0;
+  r.rounds = rounds;
+  r.equals_input = rounds == 0;
+  r.passes = passes;
+  r.surviving_vertices = V.n - ald(&J->tot_removed_v);
+  r.surviving_edges = m - ald(&J->tot_removed_e);
+  r.input_edges = m;
+  r.edge_tests = ald(&J->tot_tests);
+  write_result(a, V.g, r);
+}
+
+// Lists the items of pass S.pass (the touched sets are in S.tc / S.btc) and
+// opens it: solo (the whole list is this workgroup's run) or shared
+// (published, this workgroup's first run taken).  Returns false when the
+// pass has nothing to test: the job is then finished.
+template <int NW>
+__device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int n = V.n, R = V.R, p = S.pass;
+  const int nw = (n + 31) >> 5, nbw = (R + 31) >> 5;
+  if (tid == 0) S.nitems = 0;
+  __syncthreads();
+  // vertex chunks holding a touched vertex
+  const int nvc = (n + 63) >> 6;
+  for (int c0 = wid * kWave; c0 < nvc; c0 += NW * kWave) {
+    const int c = c0 + lane;
+    bool want = false;
+    if (c < nvc) want = (S.tc[2 * c] | (2 * c + 1 < nw ? S.tc[2 * c + 1] : 0u)) != 0u;
+    const unsigned long long b = __ballot(want);
+    int at = 0;
+    if (lane == 0 && b) at = atomicAdd(&S.nitems, __popcll(b));
+    at = __builtin_amdgcn_readfirstlane(at);
+    if (want) V.items[at + __popcll(b & lanes_below(lane))] = kVertexItem | c;
+  }
+  // tiles of two classes with a touched block: a wave per row X, lanes over Y
+  for (int X = wid; X < R; X += NW) {
+    const int cx = S.bcls[X];
+    const bool tx = tbit(S.btc, X);
+    for (int y0 = X + 1; y0 < R; y0 += kWave) {
+      const int Y = y0 + lane;
+      const bool want = Y < R && S.bcls[Y] != cx && (tx || tbit(S.btc, Y));
+      const unsigned long long b = __ballot(want);
+      int at = 0;
+      if (lane == 0 && b) at = atomicAdd(&S.nitems, __popcll(b));
+      at = __builtin_amdgcn_readfirstlane(at);
+      if (want) V.items[at + __popcll(b & lanes_below(lane))] = X | (Y << 8);
+    }
+  }
+  __syncthreads();
+  const int ni = S.nitems;
+  if (ni == 0) {
+    if (tid == 0) end_job(a, V, p);
+    __syncthreads();
+    return false;
+  }
+  if (tid == 0) {
+    bool shared = a.share == 1;
+    if (a.share == 0 && ni > NW)
+      shared = __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.G;
+    S.shared = shared;
+    S.opener = 1;
+    S.base = 0;
+    S.cnt = shared ? min(ni, NW) : ni;
+    S.next_item = 0;
+    S.nchanged = 0;
+    S.got = 1;
+    if (shared) {
+      BatchJob *J = V.J;
+      ast(&J->removed_v, 0ull);
+      ast(&J->removed_e, 0ull);
+      ast(&J->tests, 0ull);
+      ast(&J->prio, 0);
+      ast(&J->nchanged, 0);
+      ast(&J->done, 0u);
+    }
+  }
+  __syncthreads();
+  if (S.shared) {
+    BatchJob *J = V.J;
+    for (int i = tid; i < nw; i += NW * kWave) {
+      ast(&J->touched[p & 1][i], S.tc[i]);
+      ast(&J->touched[(p + 1) & 1][i], 0u);
+    }
+    for (int i = tid; i < nbw; i += NW * kWave) {
+      ast(&J->btouched[p & 1][i], S.btc[i]);
+      ast(&J->btouched[(p + 1) & 1][i], 0u);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned long long cw =
+          ((unsigned long long)p << 32) | ((unsigned long long)ni << 16) | (unsigned long long)S.cnt;
+      __hip_atomic_exchange(&J->claim, cw, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.board[V.g & (kBatchBoard - 1)], V.g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  return true;
+}
+
+// Sets up graph g (validation, layout, state) and opens its first pass.
+// Returns false when the graph needs no pass (error, empty graph).
+template <int NW>
+__device__ bool start_job(const BatchArgs &a, BatchLds &S, int g) {
+  const int tid = threadIdx.x;
   const kz_batch_graph G = a.graphs[g];
   const int n = G.n, k = G.k, R = G.row_words;
-  const uint64_t *rows = a.rows + G.row_offset;
-  uint64_t *cur = a.emask + G.row_offset;
-  const int *colour = a.colour + G.vertex_offset;
-  uint8_t *valive = a.vmask + G.vertex_offset;
-  kz_result res{};
-  res.status = 0;
-  if (n < 0 || k < 1 || R < 0) {
-    res.status = KZ_EINVAL;
-  } else if (k > kBatchK || R > kBatchR || n > kBatchN) {
-    res.status = kBatchTooLarge;
-  }
-  if (res.status != 0 || n == 0) {
+  int st = 0;
+  if (n < 0 || k < 1 || R < 0 || G.row_offset < 0 || G.vertex_offset < 0) st = KZ_EINVAL;
+  else if (k > kBatchK || R > kBatchR || n > kBatchN) st = kBatchTooLarge;
+  if (st != 0 || n == 0) {
     if (tid == 0) {
-      res.equals_input = res.status == 0;
-      a.results[g] = res;
+      if (st) {
+        fail_job(a, g, st);
+      } else {
+        kz_result r{};
+        r.equals_input = 1;
+        write_result(a, g, r);
+      }
     }
-    return;
+    return false;
   }
-  uint64_t *scratch = a.scratch + (long long)blockIdx.x * a.scratch_words;
-  int *changed = (int *)(scratch + a.list_offset);
-
-  // ---- layout: colours are sorted class by class; class c starts at the
-  // first vertex whose colour is >= c (binary search)
+  const GView V = gview(a, g);
+  // layout: colours are sorted class by class; class c starts at the first
+  // vertex whose colour is >= c (binary search)
   if (tid == 0) {
     S.bad_colour = 0;
     S.bad_layout = 0;
-    S.prio = 0;
   }
   __syncthreads();
   for (int v = tid; v < n; v += NW * kWave) {
-    const int c = colour[v];
+    const int c = V.colour[v];
     if (c < 0 || c >= k) S.bad_colour = 1;
-    else if (v > 0 && colour[v - 1] > c) S.bad_layout = 1;
+    else if (v > 0 && V.colour[v - 1] > c) S.bad_layout = 1;
   }
   __syncthreads();
   if (S.bad_colour | S.bad_layout) {
-    if (tid == 0) {
-      res.status = S.bad_colour ? KZ_ECOLOUR : KZ_EINVAL;
-      a.results[g] = res;
-    }
-    return;
+    if (tid == 0) fail_job(a, g, S.bad_colour ? KZ_ECOLOUR : KZ_EINVAL);
+    __syncthreads();
+    return false;
   }
   for (int c = tid; c <= k; c += NW * kWave) {
     int lo = 0, hi = n;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (colour[mid] < c) lo = mid + 1;
+      if (V.colour[mid] < c) lo = mid + 1;
       else hi = mid;
     }
     S.coff[c] = lo;
@@ -123,7 +473,7 @@ __device__ void batch_graph(const BatchArgs &a, BatchShared &S, unsigned long lo
       const int s = S.coff[c + 1] - S.coff[c];
       for (int b = 0; 64 * b < s && w + b < kBatchR; ++b) {
         S.bcls[w + b] = (short)c;
-        S.bstart[w + b] = S.coff[c] + 64 * b;
+        S.bstart[w + b] = (unsigned short)(S.coff[c] + 64 * b);
         S.blen[w + b] = (unsigned char)min(64, s - 64 * b);
       }
       w += (s + 63) / 64;
@@ -133,278 +483,346 @@ __device__ void batch_graph(const BatchArgs &a, BatchShared &S, unsigned long lo
   }
   __syncthreads();
   if (S.bad_layout) {
-    if (tid == 0) {
-      res.status = KZ_EINVAL;
-      a.results[g] = res;
-    }
-    return;
+    if (tid == 0) fail_job(a, g, KZ_EINVAL);
+    __syncthreads();
+    return false;
   }
-  // ---- state: copy the rows, everything alive and touched
-  for (long long i = tid; i < (long long)n * R; i += NW * kWave) cur[i] = rows[i];
+  // the layout goes to the job too (helpers load it from there)
+  BatchJob *J = V.J;
+  for (int c = tid; c <= k; c += NW * kWave) {
+    J->coff[c] = S.coff[c];
+    J->soff[c] = S.soff[c];
+  }
+  for (int b = tid; b < R; b += NW * kWave) {
+    J->bcls[b] = S.bcls[b];
+    J->bstart[b] = S.bstart[b];
+    J->blen[b] = S.blen[b];
+  }
+  // state: the rows, every vertex and block touched
+  for (long long i = tid; i < (long long)n * R; i += NW * kWave) V.cur[i] = V.rows[i];
   for (int i = tid; i < kBatchN / 32; i += NW * kWave) {
-    S.touched[0][i] = 0;
-    S.touched[1][i] = ~0u;
+    S.tc[i] = ~0u;
+    S.tn[i] = 0;
   }
   for (int i = tid; i < kBatchR / 32; i += NW * kWave) {
-    S.btouched[0][i] = 0;
-    S.btouched[1][i] = ~0u;
+    S.btc[i] = ~0u;
+    S.btn[i] = 0;
+  }
+  if (tid == 0) {
+    ast(&J->rounds, 0);
+    ast(&J->tot_removed_v, 0ll);
+    ast(&J->tot_removed_e, 0ll);
+    ast(&J->tot_tests, 0ll);
+    ast(&J->m, 0ll);
+    S.job = g;
+    S.pass = 1;
+    S.prio = 0;
+    S.removed_v = 0;
+    S.removed_e = 0;
+    S.tests = 0;
   }
   __syncthreads();
+  return open_pass<NW>(a, V, S);
+}
 
-  long long removed_v = 0, removed_e = 0, tests = 0, m = 0;
-  int rounds = 0, pass = 0;
-  for (;;) {
-    ++pass;
-    const bool first = pass == 1;
-    const int tc = pass & 1, tn = tc ^ 1;
+// Claims a run of unclaimed items of job g (thread 0; S.got = 0: none left).
+// A workgroup joining a pass it did not list loads the job's layout and
+// touched sets after an acquire fence.
+template <int NW>
+__device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
+  const int tid = threadIdx.x;
+  BatchJob *J = a.jobs + g;
+  if (tid == 0) {
+    unsigned long long old = __hip_atomic_load(&J->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int got = 0, cp = 0;
+    for (int tries = 0; tries < 64; ++tries) {
+      const unsigned ni = (unsigned)(old >> 16) & 0xffffu, nx = (unsigned)old & 0xffffu;
+      if (nx >= ni) break;
+      const unsigned c = min(ni - nx, (unsigned)NW);
+      if (__hip_atomic_compare_exchange_strong(&J->claim, &old, old + c, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        got = 1;
+        cp = (int)(old >> 32);
+        S.base = (int)nx;
+        S.cnt = (int)c;
+        S.nitems = (int)ni;
+        break;
+      }
+    }
+    S.reload = 0;
+    if (got) {
+      if (!(S.job == g && S.pass == cp)) {
+        __threadfence();  // acquire: the pass was listed by another workgroup
+        S.reload = S.job != g ? 2 : 1;
+        S.job = g;
+        S.pass = cp;
+        S.opener = 0;
+        S.shared = 1;
+      }
+      S.next_item = 0;
+    }
+    S.got = got;
+  }
+  __syncthreads();
+  if (S.got && S.reload) {
+    const kz_batch_graph G = a.graphs[g];
+    const int p = S.pass, nw = (G.n + 31) >> 5, nbw = (G.row_words + 31) >> 5;
+    if (S.reload == 2) {
+      for (int c = tid; c <= G.k; c += NW * kWave) {
+        S.coff[c] = J->coff[c];
+        S.soff[c] = J->soff[c];
+      }
+      for (int b = tid; b < G.row_words; b += NW * kWave) {
+        S.bcls[b] = J->bcls[b];
+        S.bstart[b] = J->bstart[b];
+        S.blen[b] = J->blen[b];
+      }
+    }
+    for (int i = tid; i < nw; i += NW * kWave) {
+      S.tc[i] = ald(&J->touched[p & 1][i]);
+      S.tn[i] = 0;
+    }
+    for (int i = tid; i < nbw; i += NW * kWave) {
+      S.btc[i] = ald(&J->btouched[p & 1][i]);
+      S.btn[i] = 0;
+    }
     if (tid == 0) {
+      S.prio = 0;
       S.removed_v = 0;
       S.removed_e = 0;
       S.tests = 0;
-      S.next_item = 0;
-      S.nchanged = 0;
     }
-    for (int i = tid; i < kBatchN / 32; i += NW * kWave) S.touched[tn][i] = 0;
-    for (int i = tid; i < kBatchR / 32; i += NW * kWave) S.btouched[tn][i] = 0;
     __syncthreads();
-    const uint64_t *src = first ? rows : cur;
+  }
+}
 
-    // ---- vertex test: lane v of a wave = vertex 64*i + v
-    for (int v0 = wid * kWave; v0 < n; v0 += NW * kWave) {
-      const int v = v0 + lane;
-      const bool act = v < n && (first || (valive[v] && tbit(S.touched[tc], v)));
-      if (!__ballot(act)) continue;
-      const uint64_t *row = src + (long long)(act ? v : v0) * R;
-      const int cv = act ? colour[v] : -1;
-      bool fail = false;
-      int pr = 0;
-      for (int c = 0; c < k; ++c) {
-        const int w0 = S.soff[c], w1 = S.soff[c + 1];
-        const int s = S.coff[c + 1] - S.coff[c];
-        if (!act) continue;
-        if (w1 == w0) {
-          fail |= c != cv;
-          continue;
-        }
-        if (first && (s & 63) && (row[w1 - 1] >> (s & 63))) pr = max(pr, P_EINVAL);
-        if (c == cv) {
-          if (!first) continue;
-          const int jv = v - S.coff[c];
-          for (int w = w0; w < w1; ++w) {
-            unsigned long long y = row[w];
-            if (w == w1 - 1 && (s & 63)) y &= (1ull << (s & 63)) - 1;
-            while (y) {
-              const int b = __builtin_ctzll(y);
-              y &= y - 1;
-              const int t = S.coff[c] + (w - w0) * 64 + b;
-              if (t == v) pr = max(pr, P_ESELFLOOP);
-              else
-                pr = max(pr, ((src[(long long)t * R + w0 + (jv >> 6)] >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL
-                                                                                             : (int)P_EASYM);
-            }
-          }
-          continue;
-        }
-        bool nz = false;
-        for (int w = w0; w < w1 && !nz; ++w) nz = row[w] != 0;
-        fail |= !nz;
-      }
-      if (pr) atomicMax(&S.prio, pr);
-      fail = fail && act;
-      if (act) {
-        if (first) valive[v] = fail ? 0 : 1;
-        else if (fail) valive[v] = 0;
-      }
-      const int nf = bsum(fail ? 1 : 0);
-      if (lane == 0 && nf) atomicAdd(&S.removed_v, (unsigned long long)nf);
-    }
-
-    // ---- edge test: waves take tiles (X < Y)
-    const long long T = (long long)R * (R - 1) / 2;
-    const int nthird = k - 2;
-    for (;;) {
-      int t = 0;
-      if (lane == 0) t = atomicAdd(&S.next_item, 1);
-      t = __builtin_amdgcn_readfirstlane(t);
-      if (t >= T) break;
-      int X, Y;
-      tri(t, R, X, Y);
-      const int cx = S.bcls[X], cy = S.bcls[Y];
-      if (cx == cy) continue;
-      if (!first && !(tbit(S.btouched[tc], X) || tbit(S.btouched[tc], Y))) continue;
-      const int xs = S.bstart[X], xl = S.blen[X], ys = S.bstart[Y], yl = S.blen[Y];
-      const unsigned long long ymask = yl == 64 ? ~0ull : ((1ull << yl) - 1);
-      const unsigned long long xmask = xl == 64 ? ~0ull : ((1ull << xl) - 1);
-      const uint64_t *rowu_l = src + (long long)(xs + (lane < xl ? lane : 0)) * R;  // lane as row u
-      const uint64_t *rowv = src + (long long)(ys + (lane < yl ? lane : 0)) * R;    // lane as row v
-      const unsigned long long Eu = lane < xl ? (rowu_l[Y] & ymask) : 0ull;          // E(u) of row u = lane
-      const unsigned long long ET = lane < yl ? rowv[X] : 0ull;
-      sPw[wid][lane] = Eu;
-      for (int q = 0; q < nthird; q += CH) {
-        // stage the first two words of each third-class segment: row u's in
-        // LDS (read as broadcasts), row v's in registers
-        unsigned long long vv[CH], vv2[CH];
-        int w2[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-          const int i = q + j;
-          if (i < nthird) {
-            int c = i;
-            if (c >= cx) ++c;
-            if (c >= cy) ++c;
-            const int w0 = S.soff[c], w1 = S.soff[c + 1];
-            const bool has = w1 > w0, two = w1 > w0 + 1;
-            sU[wid][j][lane] = (has && lane < xl) ? rowu_l[w0] : 0ull;
-            sU2[wid][j][lane] = (two && lane < xl) ? rowu_l[w0 + 1] : 0ull;
-            vv[j] = (has && lane < yl) ? rowv[w0] : 0ull;
-            vv2[j] = (two && lane < yl) ? rowv[w0 + 1] : 0ull;
-            w2[j] = w0 + 2 < w1 ? w0 + 2 : -1;
-          } else {
-            sU[wid][j][lane] = ~0ull;
-            sU2[wid][j][lane] = 0ull;
-            vv[j] = ~0ull;
-            vv2[j] = 0ull;
-            w2[j] = -1;
-          }
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int u = 0; u < xl; ++u) {
-          unsigned long long P = bcast64(sPw[wid][lane], u);
-          if (!P) continue;
-          unsigned long long all = ~0ull;
-#pragma unroll
-          for (int j = 0; j < CH; ++j) all &= __ballot((sU[wid][j][u] & vv[j]) != 0ull);
-          if (!(P & ~all)) continue;
-          // level 2: the first two words
-          all = ~0ull;
-#pragma unroll
-          for (int j = 0; j < CH; ++j)
-            all &= __ballot(((sU[wid][j][u] & vv[j]) | (sU2[wid][j][u] & vv2[j])) != 0ull);
-          if (!(P & ~all)) continue;
-          // level 3: scan the rest of the segment in memory
-          const uint64_t *rowu = src + (long long)(xs + u) * R;
-#pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            unsigned long long miss =
-                P & ~__ballot(((sU[wid][j][u] & vv[j]) | (sU2[wid][j][u] & vv2[j])) != 0ull);
-            if (!miss) continue;
-            if (w2[j] >= 0) {
-              const int i = q + j;
-              int c = i;
-              if (c >= cx) ++c;
-              if (c >= cy) ++c;
-              for (int w = w2[j]; w < S.soff[c + 1] && miss; ++w) {
-                const unsigned long long x = rowu[w];
-                const unsigned long long y = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
-                miss &= ~__ballot((x & y) != 0ull);
-              }
-            }
-            P &= ~miss;
-          }
-          if (lane == u) sPw[wid][lane] = P;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-      const unsigned long long Pu = sPw[wid][lane];
-      unsigned long long newET = 0, trE = 0;
-      for (int u = 0; u < xl; ++u) {
-        const unsigned long long P = bcast64(Pu, u);
-        newET |= ((P >> lane) & 1ull) << u;
-        if (first) trE |= ((bcast64(Eu, u) >> lane) & 1ull) << u;
-      }
-      if (first && lane < yl && ((trE ^ ET) & xmask)) atomicMax(&S.prio, P_EASYM);
-      const bool chU = lane < xl && Eu != Pu;
-      const bool chV = lane < yl && (ET & xmask) != newET;
-      const unsigned long long bu = __ballot(chU), bv = __ballot(chV);
-      if (bu | bv) {
-        if (lane < xl) scratch[(long long)(xs + lane) * R + Y] = Pu;
-        if (lane < yl) scratch[(long long)(ys + lane) * R + X] = newET;
-        if (chU) atomicOr(&S.touched[tn][(xs + lane) >> 5], 1u << ((xs + lane) & 31));
-        if (chV) atomicOr(&S.touched[tn][(ys + lane) >> 5], 1u << ((ys + lane) & 31));
-        const int rem = bsum(lane < xl ? __popcll(Eu & ~Pu) : 0);
-        if (lane == 0) {
-          if (bu) atomicOr(&S.btouched[tn][X >> 5], 1u << (X & 31));
-          if (bv) atomicOr(&S.btouched[tn][Y >> 5], 1u << (Y & 31));
-          changed[atomicAdd(&S.nchanged, 1)] = t;
-          atomicAdd(&S.removed_e, (unsigned long long)rem);
-        }
-      }
-      int cnt;
-      if (first) {
-        cnt = bsum(lane < xl ? __popcll(Eu) : 0);
-      } else {
-        const bool tU = lane < xl && tbit(S.touched[tc], xs + lane);
-        const unsigned long long TV = __ballot(lane < yl && tbit(S.touched[tc], ys + lane));
-        cnt = bsum(lane < xl ? __popcll(Eu & (tU ? ~0ull : TV)) : 0);
-      }
-      if (lane == 0 && cnt) atomicAdd(&S.tests, (unsigned long long)cnt);
-    }
+// Reports a finished run.  Solo: the run was the pass.  Shared: merge the
+// run's counts and touched bits into the job, then count the run done (a
+// run by a workgroup that did not list the pass also adds 1 << 16); the run
+// that completes the pass returns true, after an acquire fence.
+__device__ bool retire(const GView &V, BatchLds &S) {
+  const int tid = threadIdx.x;
+  if (!S.shared) {
+    if (tid == 0) S.got = 0;
     __syncthreads();
-    // ---- apply: copy changed tiles into the state
-    const int nch = S.nchanged;
-    for (int i = wid; i < nch; i += NW) {
-      int X, Y;
-      tri(changed[i], R, X, Y);
-      const int xs = S.bstart[X], xl = S.blen[X], ys = S.bstart[Y], yl = S.blen[Y];
-      if (lane < xl) cur[(long long)(xs + lane) * R + Y] = scratch[(long long)(xs + lane) * R + Y];
-      if (lane < yl) cur[(long long)(ys + lane) * R + X] = scratch[(long long)(ys + lane) * R + X];
+    return true;
+  }
+  BatchJob *J = V.J;
+  const int tnx = (S.pass + 1) & 1;
+  const int nw = (V.n + 31) >> 5, nbw = (V.R + 31) >> 5;
+  for (int i = tid; i < nw; i += blockDim.x) {
+    const unsigned x = S.tn[i];
+    if (x) {
+      atomicOr(&J->touched[tnx][i], x);
+      S.tn[i] = 0;
     }
-    __syncthreads();
-    if (first && S.prio) {
-      if (tid == 0) {
-        res.status = S.prio == P_EINVAL ? KZ_EINVAL
-                     : S.prio == P_ESELFLOOP ? KZ_ESELFLOOP
-                     : S.prio == P_EASYM ? KZ_EASYM
-                                         : KZ_EILLEGAL;
-        a.results[g] = res;
-      }
-      return;
+  }
+  for (int i = tid; i < nbw; i += blockDim.x) {
+    const unsigned x = S.btn[i];
+    if (x) {
+      atomicOr(&J->btouched[tnx][i], x);
+      S.btn[i] = 0;
     }
-    const long long rv = (long long)S.removed_v, re = (long long)S.removed_e;
-    if (first) m = (long long)S.tests;
-    tests += (long long)S.tests;
-    removed_v += rv;
-    removed_e += re;
-    __syncthreads();  // everyone has read the counters before they are reset
-    if (rv + re == 0) break;
-    ++rounds;
   }
   if (tid == 0) {
-    res.rounds = rounds;
-    res.equals_input = rounds == 0;
-    res.passes = pass;
-    res.surviving_vertices = n - removed_v;
-    res.surviving_edges = m - removed_e;
-    res.input_edges = m;
-    res.edge_tests = tests;
-    a.results[g] = res;
+    if (S.removed_v) atomicAdd(&J->removed_v, S.removed_v);
+    if (S.removed_e) atomicAdd(&J->removed_e, S.removed_e);
+    if (S.tests) atomicAdd(&J->tests, S.tests);
+    if (S.prio) atomicMax(&J->prio, S.prio);
+    S.removed_v = 0;
+    S.removed_e = 0;
+    S.tests = 0;
+    S.prio = 0;
   }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned add = (unsigned)S.cnt | (S.opener ? 0u : 0x10000u);
+    const unsigned now = __hip_atomic_fetch_add(&J->done, add, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + add;
+    S.last = (int)(now & 0xffffu) == S.nitems;
+    // acquire what the other workgroups wrote (and drop this CU's cached
+    // copies of the job's merged state)
+    if (S.last) __threadfence();
+    S.got = 0;
+  }
+  __syncthreads();
+  return S.last;
+}
+
+// The carrier: applies the changed tiles, closes the pass, and ends the job
+// or opens the next pass.  Returns true when a next pass is open.
+template <int NW>
+__device__ bool carry(const BatchArgs &a, const GView &V, BatchLds &S) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  BatchJob *J = V.J;
+  const int p = S.pass, R = V.R;
+  const int nw = (V.n + 31) >> 5, nbw = (R + 31) >> 5;
+  if (S.shared) {
+    const int tnx = (p + 1) & 1;
+    for (int i = tid; i < nw; i += NW * kWave) S.tn[i] = ald(&J->touched[tnx][i]);
+    for (int i = tid; i < nbw; i += NW * kWave) S.btn[i] = ald(&J->btouched[tnx][i]);
+    if (tid == 0) {
+      S.removed_v = ald(&J->removed_v);
+      S.removed_e = ald(&J->removed_e);
+      S.tests = ald(&J->tests);
+      S.prio = ald(&J->prio);
+      S.nchanged = ald(&J->nchanged);
+    }
+    __syncthreads();
+  }
+  // apply: copy the changed tiles into the state
+  const int nch = S.nchanged;
+  for (int i = wid; i < nch; i += NW) {
+    const int it = V.changed[i];
+    const int X = it & 0xff, Y = (it >> 8) & 0xff;
+    const int xs = S.bstart[X], xl = S.blen[X], ys = S.bstart[Y], yl = S.blen[Y];
+    if (lane < xl) V.cur[(long long)(xs + lane) * R + Y] = V.nxt[(long long)(xs + lane) * R + Y];
+    if (lane < yl) V.cur[(long long)(ys + lane) * R + X] = V.nxt[(long long)(ys + lane) * R + X];
+  }
+  if (tid == 0) {
+    const long long rv = (long long)S.removed_v, re = (long long)S.removed_e;
+    S.status = 0;
+    if (p == 1 && S.prio)
+      S.status = S.prio == P_EINVAL      ? KZ_EINVAL
+                 : S.prio == P_ESELFLOOP ? KZ_ESELFLOOP
+                 : S.prio == P_EASYM     ? KZ_EASYM
+                                         : KZ_EILLEGAL;
+    if (p == 1) ast(&J->m, (long long)S.tests);
+    ast(&J->tot_tests, ald(&J->tot_tests) + (long long)S.tests);
+    ast(&J->tot_removed_v, ald(&J->tot_removed_v) + rv);
+    ast(&J->tot_removed_e, ald(&J->tot_removed_e) + re);
+    if (!S.status && rv + re > 0) ast(&J->rounds, ald(&J->rounds) + 1);
+    S.end = S.status != 0 || rv + re == 0;
+  }
+  __syncthreads();
+  if (S.end) {
+    if (tid == 0) {
+      if (S.status) fail_job(a, V.g, S.status);
+      else end_job(a, V, p);
+    }
+    __syncthreads();
+    return false;
+  }
+  // next pass: what this pass touched is what the next one tests
+  for (int i = tid; i < kBatchN / 32; i += NW * kWave) {
+    S.tc[i] = i < nw ? S.tn[i] : 0u;
+    S.tn[i] = 0;
+  }
+  for (int i = tid; i < kBatchR / 32; i += NW * kWave) {
+    S.btc[i] = i < nbw ? S.btn[i] : 0u;
+    S.btn[i] = 0;
+  }
+  if (tid == 0) {
+    S.pass = p + 1;
+    S.prio = 0;
+    S.removed_v = 0;
+    S.removed_e = 0;
+    S.tests = 0;
+  }
+  __syncthreads();
+  return open_pass<NW>(a, V, S);
+}
+
+// Looks on the board for a shared pass with unclaimed items (the one with
+// most of them); -1 if there is none.
+__device__ int find_job(const BatchArgs &a, BatchLds &S) {
+  const int tid = threadIdx.x;
+  if (tid < kWave) {
+    int gs[kBatchBoard / kWave];
+#pragma unroll
+    for (int j = 0; j < kBatchBoard / kWave; ++j)
+      gs[j] = __hip_atomic_load(&a.board[j * kWave + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long key = 0;
+#pragma unroll
+    for (int j = 0; j < kBatchBoard / kWave; ++j) {
+      if (gs[j] < 0) continue;
+      const unsigned long long cw =
+          __hip_atomic_load(&a.jobs[gs[j]].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned ni = (unsigned)(cw >> 16) & 0xffffu, nx = (unsigned)cw & 0xffffu;
+      if (nx < ni) key = max(key, ((unsigned long long)(ni - nx) << 32) | (unsigned)(gs[j] + 1));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = (unsigned long long)__shfl_xor((long long)key, off, kWave);
+      key = max(key, o);
+    }
+    if (tid == 0) S.pick = key ? (int)(key & 0xffffffffu) - 1 : -1;
+  }
+  __syncthreads();
+  return S.pick;
 }
 
 template <int NW, int CH>
 __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
-  __shared__ BatchShared S;
+  __shared__ BatchLds S;
   __shared__ unsigned long long sU[NW][CH][kBlk];
   __shared__ unsigned long long sU2[NW][CH][kBlk];
   __shared__ unsigned long long sPw[NW][kBlk];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    S.job = -1;
+    S.pass = 0;
+    S.got = 0;
+    S.queue_empty = 0;
+  }
+  __syncthreads();
+  int job = -1;
+  unsigned long long idle0 = 0;  // thread 0: when this workgroup ran out of work
   for (;;) {
-    if (threadIdx.x == 0) S.gi = atomicAdd(a.queue, 1);
+    if (job >= 0) {
+      if (!S.got) claim<NW>(a, S, job);
+      if (S.got) {
+        const GView V = gview(a, job);
+        run_items<NW, CH>(V, S, sU, sU2, sPw);
+        if (retire(V, S) && !carry<NW>(a, V, S)) job = -1;
+        continue;
+      }
+      job = -1;
+    }
+    if (!S.queue_empty) {
+      __syncthreads();
+      if (tid == 0) {
+        const int t = atomicAdd(a.queue, 1);
+        S.gi = t < a.G ? a.order[t] : -1;
+        if (t >= a.G) S.queue_empty = 1;
+      }
+      __syncthreads();
+      const int g = S.gi;
+      if (g >= 0) {
+        if (start_job<NW>(a, S, g)) job = g;
+        idle0 = 0;
+        continue;
+      }
+    }
+    job = find_job(a, S);
+    if (job >= 0) {
+      idle0 = 0;
+      continue;
+    }
+    if (tid == 0) {
+      const unsigned long long now = wall_clock64();
+      if (!idle0) idle0 = now;
+      S.quit = __hip_atomic_load(a.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.G ||
+               now - idle0 > kIdleTicks;
+    }
     __syncthreads();
-    const int gi = S.gi;
-    __syncthreads();
-    if (gi >= a.G) break;
-    batch_graph<NW, CH>(a, S, sU, sU2, sPw, a.order[gi]);
-    __syncthreads();
+    if (S.quit) break;
+    __builtin_amdgcn_s_sleep(8);
   }
 }
 
 // Orders the graphs by an estimate of their work, largest first (so the
-// persistent workgroups finish together), or keeps the given order.  One
-// workgroup, bitonic sort in LDS for up to kBatchSortMax graphs.
+// persistent workgroups finish together), or keeps the given order; resets
+// the queue, the finished count and the board.  One workgroup, bitonic sort
+// in LDS for up to kBatchSortMax graphs.
 __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a, int lpt) {
   __shared__ unsigned long long key[kBatchSortMax];
   const int t = threadIdx.x, G = a.G;
-  if (t == 0) *a.queue = 0;
+  if (t == 0) {
+    *a.queue = 0;
+    *a.finished = 0;
+  }
+  for (int i = t; i < kBatchBoard; i += 1024) a.board[i] = -1;
   if (!lpt || G > kBatchSortMax) {
     for (int i = t; i < G; i += 1024) a.order[i] = i;
     return;

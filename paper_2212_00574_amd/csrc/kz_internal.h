@@ -106,30 +106,66 @@ void launch_csr_apply(const Plan &p, const int32_t *ci, long long nnz, uint8_t *
 
 // Batched path (kz_batch.hip).
 constexpr int kBatchK = 64;          // classes
-constexpr int kBatchR = 512;         // words per row (blocks)
+constexpr int kBatchR = 128;         // words per row (blocks); n <= 4096 and k <= 64 give at most 127
 constexpr int kBatchN = 4096;        // vertices
 constexpr int kBatchSortMax = 8192;  // graphs ordered by work on the device up to this count
+constexpr int kBatchBoard = 256;     // board of shared passes (job g posts at g mod kBatchBoard)
 constexpr int kBatchTooLarge = KZ_ETOOLARGE;
+
+// One graph's job state in device memory.  Every word other workgroups
+// update with atomics is only ever accessed with (agent-scope) atomics, and
+// those words sit on cache lines of their own: a plain store to such a word
+// could linger dirty in one XCD's L2 and overwrite atomic updates made
+// meanwhile when it is written back.
+struct alignas(128) BatchJob {
+  // shared-pass control and merged counts (atomics only)
+  unsigned long long claim;  // (pass << 32) | (items << 16) | next unclaimed item of a shared pass
+  unsigned done;             // items finished in the shared pass (+ 1 << 16 per helper run)
+  int prio, nchanged, pad0;
+  unsigned long long removed_v, removed_e, tests;
+  unsigned touched[2][kBatchN / 32];                  // per pass parity: touched vertices
+  unsigned btouched[2][kBatchR / 32];                 // and blocks
+  // totals, kept by the carriers (atomic loads and stores)
+  alignas(128) long long tot_removed_v, tot_removed_e, tot_tests, m;
+  int rounds;
+  // layout, written when the job starts, read by helpers (plain)
+  alignas(128) int coff[kBatchK + 1], soff[kBatchK + 1];
+  short bcls[kBatchR];
+  unsigned short bstart[kBatchR];
+  unsigned char blen[kBatchR];
+};
 
 struct BatchArgs {
   const kz_batch_graph *graphs;
   int G;
+  int share;      // 0: share passes once the queue is empty; 1: share every pass; 2: never
   int *order;     // [G]
   int *queue;     // next graph to take
+  int *finished;  // graphs finished
+  int *board;     // [kBatchBoard] jobs with a shared pass
+  BatchJob *jobs; // [G]
   const uint64_t *rows;
   const int *colour;
   uint64_t *emask;
   uint8_t *vmask;
   kz_result *results;
-  uint64_t *scratch;        // per workgroup: changed words (n*R) then the changed-tile list
-  long long scratch_words;  // words per workgroup
-  long long list_offset;    // words before the changed-tile list
+  uint64_t *next;  // next-state words, same layout as rows
+  int *lists;      // changed tiles and items: graph g's at int offset 2*row_offset
 };
 
 struct BatchConfig {
-  int waves, chunk, lpt, workgroups;
+  int waves, chunk, lpt, workgroups, share;
 };
 
 void launch_batch(const BatchArgs &a, const BatchConfig &cfg, hipStream_t s);
+
+// Synthetic input materialiser (kz_gen.hip).
+constexpr int kGenK = 64;
+struct GenArgs {
+  int n, k, R, planted;
+  unsigned long long base, thr;  // splitmix64((seed << 32) | gid), floor(p * 2^64)
+  int coff[kGenK + 1], soff[kGenK + 1], pl[kGenK];
+};
+void launch_gen_rows(const GenArgs &g, uint64_t *rows, int *colour, hipStream_t s);
 
 }  // namespace kzi

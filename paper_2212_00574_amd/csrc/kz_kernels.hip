@@ -448,6 +448,10 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
   }
   __syncthreads();  // sE/sP are read by every wave, also when there is no third class
   const uint64_t *rowv = src + (long long)(ys + (lane < yl ? lane : 0)) * R;
+  // pairs to re-test: those with a touched endpoint (all of them in pass 1);
+  // the others keep their outcome, so masks and rounds equal full sweeps
+  const unsigned long long TU = FIRST ? ~0ull : __ballot(lane < xl && p.touched[cur][xs + lane]);
+  const unsigned long long TV = FIRST ? ~0ull : __ballot(lane < yl && p.touched[cur][ys + lane]);
   const ulonglong2 *F = (const ulonglong2 *)p.F;
 
   const int nthird = k - 2;
@@ -504,7 +508,8 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
       const int u = wid * kRowsPerWave + ui;
       if (u >= xl) break;
       unsigned long long P = uniform64(sP[u]);
-      if (!P) continue;
+      const unsigned long long Pt = P & (((TU >> u) & 1ull) ? ~0ull : TV);
+      if (!Pt) continue;
       unsigned long long all = ~0ull;
       {
         unsigned long long a[CH];
@@ -513,20 +518,20 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
 #pragma unroll
         for (int j = 0; j < CH; ++j) all &= __ballot((a[j] & vv[j]) != 0ull);
       }
-      if (!(P & ~all)) continue;
+      if (!(Pt & ~all)) continue;
       // level 2: the first two words (re-read from LDS; rare)
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
         const ulonglong2 a = sU[j][u];
         all &= __ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
       }
-      if (!(P & ~all)) continue;
+      if (!(Pt & ~all)) continue;
       // level 3: class by class, scanning the rest of the segment
       const uint64_t *rowu = src + (long long)(xs + u) * R;
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
         const ulonglong2 a = sU[j][u];
-        unsigned long long miss = P & ~__ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
+        unsigned long long miss = Pt & ~__ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
         const int w1 = sW[j][1];
         for (int w = sW[j][0] + 2; w < w1 && miss; ++w) {
           const unsigned long long x = rowu[w];

@@ -26,9 +26,9 @@ def lib():
 
 def test_header_declares_the_entry_points():
     assert declared() == ["kz_batch_autotune", "kz_batch_get_config", "kz_batch_set_config",
-                          "kz_batch_workspace_bytes", "kz_create", "kz_destroy", "kz_kernelize",
-                          "kz_kernelize_batch", "kz_profile_enable", "kz_profile_read", "kz_strerror",
-                          "kz_workspace_bytes"]
+                          "kz_batch_workspace_bytes", "kz_create", "kz_destroy", "kz_gen_bitset",
+                          "kz_kernelize", "kz_kernelize_batch", "kz_profile_enable", "kz_profile_read",
+                          "kz_strerror", "kz_workspace_bytes"]
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -72,4 +72,4 @@ def test_struct_layouts_match_the_header():
     assert C.sizeof(b.kz_result) == b.RESULT_DTYPE.itemsize == 48
     assert b.BATCH_GRAPH_DTYPE.itemsize == 32
     assert C.sizeof(b.kz_graph) == 56
-    assert C.sizeof(b.kz_batch_config) == 16
+    assert C.sizeof(b.kz_batch_config) == 20

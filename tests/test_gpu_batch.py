@@ -168,3 +168,40 @@ def test_batch_autotune_keeps_results(kz):
     with pytest.raises(Exception):
         kz_batch_set_config(kz.ctx, {"waves": 16, "chunk": 8, "lpt": 1, "workgroups": 0})
     kz_batch_set_config(kz.ctx, before)
+
+
+def cascade_graphs():
+    """Three graphs of the batching workload whose fixpoints take 28 to 77
+    rounds (seed 0, ids 0, 2826, 4063), among small ones: once the queue is
+    empty their passes are shared with the idle workgroups."""
+    specs = inputs.config4_specs(0, graphs=4096)
+    heavy = []
+    for gid in (4063, 2826, 0):
+        rows, col, lay = inputs.config4_graph(specs[gid], 0, gid).bitset()
+        heavy.append((rows, col, specs[gid].k))
+    return heavy + mixed_graphs(24, seed=8, small=True)
+
+
+@pytest.mark.parametrize("share", [0, 1, 2])
+def test_batch_share_modes(kz, share):
+    """Passes shared across workgroups (also every pass, share=1) or kept by
+    one workgroup (share=2) give the same masks, rounds and counts."""
+    graphs = mixed_graphs(40, seed=9, small=True) + mixed_graphs(8, seed=10)
+    before = kz_batch_get_config(kz.ctx)
+    try:
+        for waves, chunk in ((8, 8), (16, 4), (4, 4)):
+            kz_batch_set_config(kz.ctx, {"waves": waves, "chunk": chunk, "lpt": 1, "workgroups": 0, "share": share})
+            check_batch(kz, graphs, "share%d-%dx%d" % (share, waves, chunk))
+    finally:
+        kz_batch_set_config(kz.ctx, before)
+
+
+@pytest.mark.parametrize("share", [0, 1])
+def test_batch_cascades_with_helpers(kz, share):
+    before = kz_batch_get_config(kz.ctx)
+    try:
+        kz_batch_set_config(kz.ctx, {"waves": 8, "chunk": 8, "lpt": 1, "workgroups": 0, "share": share})
+        b, res = check_batch(kz, cascade_graphs(), "cascades-share%d" % share)
+        assert min(int(res[i]["rounds"]) for i in range(3)) >= 28
+    finally:
+        kz_batch_set_config(kz.ctx, before)
