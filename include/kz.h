@@ -163,9 +163,9 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
  *          vertex_offset;
  *   emask  (uint64): same layout as rows (must not overlap it).
  * The graphs' row ranges must not overlap.  Limits of the batched path:
- * k <= 64, row_words <= 128 (n <= 4096 and k <= 64 never need more), n <=
- * 4096; a graph beyond them gets status KZ_ETOOLARGE in its result (run it
- * through kz_kernelize); negative offsets give KZ_EINVAL.  The call is
+ * k <= 64, row_words <= 512, n <= 32768; a graph beyond them gets status
+ * KZ_ETOOLARGE in its result (run it through kz_kernelize); negative offsets
+ * give KZ_EINVAL.  The call is
  * asynchronous: it enqueues the work on the stream and returns; results[g]
  * (device memory) is valid in stream order.  It performs no host
  * synchronisation, so a caller may capture it in a hipGraph and replay it. */
@@ -190,7 +190,7 @@ typedef struct kz_batch_config {
 
 /* Workspace bytes kz_kernelize_batch needs for these graphs (host array),
  * the same for every configuration: the queue, a job record per graph
- * (about 2.3 KB), and per row word one next-state word and two list ints
+ * (about 11 KB), and per row word one next-state word and two list ints
  * up to the highest row_offset + n*row_words. */
 int kz_batch_workspace_bytes(const kz_ctx *ctx, const kz_batch_graph *graphs, int32_t G, size_t *bytes);
 

@@ -9,14 +9,15 @@
 // job on: it applies the tiles that changed and either ends the job or lists
 // the next pass.
 //
-// While the queue still holds graphs a pass belongs to the workgroup that
-// listed it ("solo": no other workgroup touches the job, so no cross-
-// workgroup fences are needed).  Once the queue is empty, a pass with more
-// items than the workgroup has waves is "shared": it is published on a
-// board, and workgroups left without work claim runs of its items with a
-// compare-and-swap on the job's claim word, keep their counts and touched
-// bits in LDS, and merge them into the job's state in HBM before they report
-// the run finished.  The run that completes the pass makes its workgroup the
+// A pass normally belongs to the workgroup that listed it ("solo": no other
+// workgroup touches the job, so no cross-workgroup fences are needed).  A
+// pass with more items than the workgroup has waves is "shared" once the
+// queue is empty, or earlier when it is very large: it is published on a
+// board, and workgroups claim runs of its
+// items with a compare-and-swap on the job's claim word (a workgroup looking
+// for work prefers a well-stocked shared pass to a new graph), keep their
+// counts and touched bits in LDS, and merge them into the job's state in HBM
+// before they report the run finished.  The run that completes the pass makes its workgroup the
 // carrier.  Nobody waits for anybody: a pass is continued by whoever
 // finishes it, so the launch cannot deadlock, and a workgroup with nothing
 // to do leaves once every graph is finished (or after a few milliseconds
@@ -37,8 +38,14 @@ namespace kzi {
 
 namespace {
 
-constexpr int kVertexItem = 1 << 30;                 // item = kVertexItem | chunk, else X | Y << 8
+constexpr int kVertexItem = 1 << 30;                 // item = kVertexItem | chunk, else X | Y << kYShift
+constexpr int kYShift = 9, kXMask = (1 << kYShift) - 1;
 constexpr unsigned long long kIdleTicks = 2000000;   // 20 ms of the 100 MHz wall clock
+// Claim word: pass (24 bits) | items (20 bits) | next unclaimed item (20 bits).
+constexpr int kItemBits = 20;
+constexpr unsigned kItemMask = (1u << kItemBits) - 1;
+// A pass is shared once the queue is empty, or early when it is very large.
+constexpr int kShareBig = 2048;   // items
 
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long x, int lane) {
   const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, lane);
@@ -77,7 +84,7 @@ struct BatchLds {
   unsigned tc[kBatchN / 32], tn[kBatchN / 32];    // vertices touched in the previous / this pass
   unsigned btc[kBatchR / 32], btn[kBatchR / 32];  // blocks touched in the previous / this pass
   int job, pass;       // the job and pass the copies above belong to
-  int shared, opener;  // the pass is shared; this workgroup listed it
+  int shared;          // the pass is shared
   int got, base, cnt, nitems, next_item, last, reload;
   int prio, nchanged;  // this run (solo: this pass)
   unsigned long long removed_v, removed_e, tests;
@@ -271,7 +278,7 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
       if (bu) atomicOr(&S.btn[X >> 5], 1u << (X & 31));
       if (bv) atomicOr(&S.btn[Y >> 5], 1u << (Y & 31));
       const int at = S.shared ? atomicAdd(&V.J->nchanged, 1) : atomicAdd(&S.nchanged, 1);
-      V.changed[at] = X | (Y << 8);
+      V.changed[at] = X | (Y << kYShift);
       atomicAdd(&S.removed_e, (unsigned long long)rem);
     }
   }
@@ -293,7 +300,7 @@ __device__ void run_items(const GView &V, BatchLds &S, unsigned long long (*sU)[
     if (i >= cnt) break;
     const int it = V.items[base + i];
     if (it & kVertexItem) vertex_chunk(V, S, (it & 0xffff) * kWave, first, lane);
-    else tile<CH>(V, S, it & 0xff, (it >> 8) & 0xff, first, lane, sU[wid], sU2[wid], sPw[wid]);
+    else tile<CH>(V, S, it & kXMask, (it >> kYShift) & kXMask, first, lane, sU[wid], sU2[wid], sPw[wid]);
   }
   __syncthreads();
 }
@@ -361,7 +368,7 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
       int at = 0;
       if (lane == 0 && b) at = atomicAdd(&S.nitems, __popcll(b));
       at = __builtin_amdgcn_readfirstlane(at);
-      if (want) V.items[at + __popcll(b & lanes_below(lane))] = X | (Y << 8);
+      if (want) V.items[at + __popcll(b & lanes_below(lane))] = X | (Y << kYShift);
     }
   }
   __syncthreads();
@@ -374,9 +381,8 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
   if (tid == 0) {
     bool shared = a.share == 1;
     if (a.share == 0 && ni > NW)
-      shared = __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.G;
+      shared = ni >= kShareBig || __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.G;
     S.shared = shared;
-    S.opener = 1;
     S.base = 0;
     S.cnt = shared ? min(ni, NW) : ni;
     S.next_item = 0;
@@ -406,8 +412,8 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
-      const unsigned long long cw =
-          ((unsigned long long)p << 32) | ((unsigned long long)ni << 16) | (unsigned long long)S.cnt;
+      const unsigned long long cw = ((unsigned long long)p << (2 * kItemBits)) |
+                                    ((unsigned long long)ni << kItemBits) | (unsigned long long)S.cnt;
       __hip_atomic_exchange(&J->claim, cw, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&a.board[V.g & (kBatchBoard - 1)], V.g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -536,13 +542,15 @@ __device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
     unsigned long long old = __hip_atomic_load(&J->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int got = 0, cp = 0;
     for (int tries = 0; tries < 64; ++tries) {
-      const unsigned ni = (unsigned)(old >> 16) & 0xffffu, nx = (unsigned)old & 0xffffu;
+      const unsigned ni = (unsigned)(old >> kItemBits) & kItemMask, nx = (unsigned)old & kItemMask;
       if (nx >= ni) break;
-      const unsigned c = min(ni - nx, (unsigned)NW);
+      // guided run length: a share of what is left, between NW and 8*NW items
+      const unsigned rem = ni - nx;
+      const unsigned c = min(rem, max((unsigned)NW, min(8u * NW, rem / (2u * gridDim.x))));
       if (__hip_atomic_compare_exchange_strong(&J->claim, &old, old + c, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)) {
         got = 1;
-        cp = (int)(old >> 32);
+        cp = (int)(old >> (2 * kItemBits));
         S.base = (int)nx;
         S.cnt = (int)c;
         S.nitems = (int)ni;
@@ -556,7 +564,6 @@ __device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
         S.reload = S.job != g ? 2 : 1;
         S.job = g;
         S.pass = cp;
-        S.opener = 0;
         S.shared = 1;
       }
       S.next_item = 0;
@@ -597,9 +604,9 @@ __device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
 }
 
 // Reports a finished run.  Solo: the run was the pass.  Shared: merge the
-// run's counts and touched bits into the job, then count the run done (a
-// run by a workgroup that did not list the pass also adds 1 << 16); the run
-// that completes the pass returns true, after an acquire fence.
+// run's counts and touched bits into the job, then count the run's items
+// done; the run that completes the pass returns true, after an acquire
+// fence.
 __device__ bool retire(const GView &V, BatchLds &S) {
   const int tid = threadIdx.x;
   if (!S.shared) {
@@ -637,9 +644,9 @@ __device__ bool retire(const GView &V, BatchLds &S) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) {
-    const unsigned add = (unsigned)S.cnt | (S.opener ? 0u : 0x10000u);
+    const unsigned add = (unsigned)S.cnt;
     const unsigned now = __hip_atomic_fetch_add(&J->done, add, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + add;
-    S.last = (int)(now & 0xffffu) == S.nitems;
+    S.last = (int)now == S.nitems;
     // acquire what the other workgroups wrote (and drop this CU's cached
     // copies of the job's merged state)
     if (S.last) __threadfence();
@@ -674,7 +681,7 @@ __device__ bool carry(const BatchArgs &a, const GView &V, BatchLds &S) {
   const int nch = S.nchanged;
   for (int i = wid; i < nch; i += NW) {
     const int it = V.changed[i];
-    const int X = it & 0xff, Y = (it >> 8) & 0xff;
+    const int X = it & kXMask, Y = (it >> kYShift) & kXMask;
     const int xs = S.bstart[X], xl = S.blen[X], ys = S.bstart[Y], yl = S.blen[Y];
     if (lane < xl) V.cur[(long long)(xs + lane) * R + Y] = V.nxt[(long long)(xs + lane) * R + Y];
     if (lane < yl) V.cur[(long long)(ys + lane) * R + X] = V.nxt[(long long)(ys + lane) * R + X];
@@ -723,9 +730,9 @@ __device__ bool carry(const BatchArgs &a, const GView &V, BatchLds &S) {
   return open_pass<NW>(a, V, S);
 }
 
-// Looks on the board for a shared pass with unclaimed items (the one with
-// most of them); -1 if there is none.
-__device__ int find_job(const BatchArgs &a, BatchLds &S) {
+// Looks on the board for the shared pass with the most unclaimed items, if
+// it has at least `least` of them; -1 otherwise.
+__device__ int find_job(const BatchArgs &a, BatchLds &S, unsigned least) {
   const int tid = threadIdx.x;
   if (tid < kWave) {
     int gs[kBatchBoard / kWave];
@@ -738,8 +745,8 @@ __device__ int find_job(const BatchArgs &a, BatchLds &S) {
       if (gs[j] < 0) continue;
       const unsigned long long cw =
           __hip_atomic_load(&a.jobs[gs[j]].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned ni = (unsigned)(cw >> 16) & 0xffffu, nx = (unsigned)cw & 0xffffu;
-      if (nx < ni) key = max(key, ((unsigned long long)(ni - nx) << 32) | (unsigned)(gs[j] + 1));
+      const unsigned ni = (unsigned)(cw >> kItemBits) & kItemMask, nx = (unsigned)cw & kItemMask;
+      if (nx < ni && ni - nx >= least) key = max(key, ((unsigned long long)(ni - nx) << 32) | (unsigned)(gs[j] + 1));
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -779,7 +786,10 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
       }
       job = -1;
     }
+    // a shared pass with plenty of unclaimed items comes before a new graph
     if (!S.queue_empty) {
+      job = find_job(a, S, 2u * NW);
+      if (job >= 0) continue;
       __syncthreads();
       if (tid == 0) {
         const int t = atomicAdd(a.queue, 1);
@@ -794,7 +804,7 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
         continue;
       }
     }
-    job = find_job(a, S);
+    job = find_job(a, S, 1u);
     if (job >= 0) {
       idle0 = 0;
       continue;

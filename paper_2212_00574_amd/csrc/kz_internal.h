@@ -106,8 +106,8 @@ void launch_csr_apply(const Plan &p, const int32_t *ci, long long nnz, uint8_t *
 
 // Batched path (kz_batch.hip).
 constexpr int kBatchK = 64;          // classes
-constexpr int kBatchR = 128;         // words per row (blocks); n <= 4096 and k <= 64 give at most 127
-constexpr int kBatchN = 4096;        // vertices
+constexpr int kBatchR = 512;         // words per row (blocks)
+constexpr int kBatchN = 32768;       // vertices
 constexpr int kBatchSortMax = 8192;  // graphs ordered by work on the device up to this count
 constexpr int kBatchBoard = 256;     // board of shared passes (job g posts at g mod kBatchBoard)
 constexpr int kBatchTooLarge = KZ_ETOOLARGE;
@@ -119,8 +119,8 @@ constexpr int kBatchTooLarge = KZ_ETOOLARGE;
 // meanwhile when it is written back.
 struct alignas(128) BatchJob {
   // shared-pass control and merged counts (atomics only)
-  unsigned long long claim;  // (pass << 32) | (items << 16) | next unclaimed item of a shared pass
-  unsigned done;             // items finished in the shared pass (+ 1 << 16 per helper run)
+  unsigned long long claim;  // (pass << 40) | (items << 20) | next unclaimed item of a shared pass
+  unsigned done;             // items finished in the shared pass
   int prio, nchanged, pad0;
   unsigned long long removed_v, removed_e, tests;
   unsigned touched[2][kBatchN / 32];                  // per pass parity: touched vertices

@@ -97,9 +97,9 @@ def test_batch_edge_cases_and_errors(kz):
 
 def test_batch_too_large_graph_is_flagged(kz):
     small = mixed_graphs(3, seed=4, small=True)
-    big = inputs.make_graph([1100] * 4, 0.1, seed=4, gid=9, shuffle=False)   # n = 4400 > batch limit
+    big = inputs.make_graph([1] * 65, 0.5, seed=4, gid=9, shuffle=False)   # k = 65 > batch limit
     rows, col, lay = big.bitset()
-    b = Batch(small + [(rows, col, 4)], DEV)
+    b = Batch(small + [(rows, col, 65)], DEV)
     BatchKernelizer(kz).run(b)
     torch.cuda.synchronize()
     res = b.read_results()
@@ -205,3 +205,14 @@ def test_batch_cascades_with_helpers(kz, share):
         assert min(int(res[i]["rounds"]) for i in range(3)) >= 28
     finally:
         kz_batch_set_config(kz.ctx, before)
+
+
+def test_batch_large_graphs(kz):
+    """Graphs beyond 4096 vertices and 128 row words (up to the path's
+    32768 / 512 limits) next to small ones; their passes are shared."""
+    graphs = []
+    for gid, (sizes, p) in ((0, ([700] * 8, 0.06)), (3, ([2100] * 4, 0.05))):   # 4-round cascades, R = 88 / 132
+        g = inputs.make_graph(sizes, p, seed=12, gid=gid, plant=True, shuffle=False)
+        rows, col, lay = g.bitset()
+        graphs.append((rows, col, len(sizes)))
+    check_batch(kz, graphs + mixed_graphs(12, seed=13, small=True), "large")
