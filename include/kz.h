@@ -214,6 +214,66 @@ int kz_batch_autotune(kz_ctx *ctx, const kz_batch_graph *graphs_host, const kz_b
 int kz_batch_set_config(kz_ctx *ctx, const kz_batch_config *cfg);
 int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
 
+/* ------------------------------------------------------------ serving
+ * A server admits requests one at a time and runs them with continuous
+ * batching: each launch of the batched path (the job runtime above) takes
+ * every admitted request that is waiting, and at most two launches are in
+ * flight on the server's stream (one running, one queued behind it).  A
+ * request is a KZ_BITSET_U64 graph in caller-owned device buffers; results
+ * are the same as kz_kernelize on the graph alone.  The server takes a
+ * fixed part of a caller-provided device arena for its launch records and
+ * carves each admitted request's scratch from the rest (first fit); it
+ * admits a request only when a slot and its scratch are free, else
+ * KZ_EAGAIN.  It allocates no device memory of its own; it allocates pinned
+ * host memory for descriptors and results when it is created.  A server
+ * belongs to one host thread. */
+typedef struct kz_server kz_server;
+
+typedef struct kz_request {
+  int32_t n, k, row_words, reserved;
+  const uint64_t *rows;   /* device, n*row_words words (layout of KZ_BITSET_U64) */
+  const int32_t *colour;  /* device, n colours sorted class by class            */
+  uint8_t *vmask;         /* device output, n bytes                             */
+  uint64_t *emask;        /* device output, n*row_words words (not overlapping
+                             rows); all four buffers must stay valid and
+                             unchanged until the request is done               */
+} kz_request;
+
+/* Fixed arena bytes of a server with max_slots slots (1..4096); the arena
+ * must be larger by the scratch of the requests it is to hold at once. */
+size_t kz_server_fixed_bytes(int32_t max_slots);
+
+/* Arena bytes an admitted request holds until it is done (its next-state
+ * words and tile lists: 16 bytes per row word, 256-byte aligned). */
+size_t kz_server_request_bytes(const kz_request *req);
+
+/* Creates a server on ctx's device.  arena: device memory, 256-byte aligned,
+ * arena_bytes > kz_server_fixed_bytes(max_slots), owned by the caller and
+ * not touched by it until kz_server_destroy returns.  stream: the stream all
+ * work is ordered on (NULL = the null stream); inputs a caller writes on this
+ * stream before kz_server_submit are ordered before the request's launch. */
+int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_slots, void *stream,
+                     kz_server **out);
+
+/* Admits a request: KZ_OK and *ticket, KZ_EAGAIN (no slot or scratch now:
+ * retry after kz_server_progress), KZ_EINVAL (bad arguments), or
+ * KZ_ETOOLARGE (beyond the batched path's limits). */
+int kz_server_submit(kz_server *srv, const kz_request *req, uint64_t *ticket);
+
+/* Retires finished launches (freeing their scratch) and launches waiting
+ * requests when a launch slot is free.  Returns the number of admitted
+ * requests not yet retired by kz_server_poll (a request holds its slot
+ * until then), or a negative status. */
+int kz_server_progress(kz_server *srv);
+
+/* 1: the request is done; *res (if not NULL) receives its result and the
+ * ticket is retired.  0: not done yet.  KZ_EINVAL: unknown ticket.  Calls
+ * kz_server_progress first. */
+int kz_server_poll(kz_server *srv, uint64_t ticket, kz_result *res);
+
+/* Waits for the launches in flight and releases the server. */
+void kz_server_destroy(kz_server *srv);
+
 /* ------------------------------------------------------------ measurement
  * When enabled, kz_kernelize brackets every kernel launch with HIP events
  * recorded on the caller's stream and accumulates the elapsed time per

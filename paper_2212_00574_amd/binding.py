@@ -20,7 +20,10 @@ KZ_DENSE_U8, KZ_BITSET_U64, KZ_CSR = 0, 1, 2
 
 EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_kernelize",
             "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
-            "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset")
+            "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
+            "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
+            "kz_server_progress", "kz_server_poll", "kz_server_destroy")
+KZ_EAGAIN = -9
 KZ_ETOOLARGE = -10
 KERNELS = ("setup", "pack", "vertex", "edge", "apply", "unpack")
 
@@ -38,6 +41,11 @@ class kz_result(C.Structure):
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class kz_request(C.Structure):
+    _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("row_words", C.c_int32), ("reserved", C.c_int32),
+                ("rows", C.c_void_p), ("colour", C.c_void_p), ("vmask", C.c_void_p), ("emask", C.c_void_p)]
 
 
 class kz_batch_config(C.Structure):
@@ -89,6 +97,20 @@ def _load() -> C.CDLL:
     lib.kz_profile_enable.argtypes = [vp, C.c_int]
     lib.kz_profile_read.restype = C.c_int
     lib.kz_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.kz_server_fixed_bytes.restype = C.c_size_t
+    lib.kz_server_fixed_bytes.argtypes = [C.c_int32]
+    lib.kz_server_request_bytes.restype = C.c_size_t
+    lib.kz_server_request_bytes.argtypes = [C.POINTER(kz_request)]
+    lib.kz_server_create.restype = C.c_int
+    lib.kz_server_create.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp, C.POINTER(vp)]
+    lib.kz_server_submit.restype = C.c_int
+    lib.kz_server_submit.argtypes = [vp, C.POINTER(kz_request), C.POINTER(C.c_uint64)]
+    lib.kz_server_progress.restype = C.c_int
+    lib.kz_server_progress.argtypes = [vp]
+    lib.kz_server_poll.restype = C.c_int
+    lib.kz_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(kz_result)]
+    lib.kz_server_destroy.restype = None
+    lib.kz_server_destroy.argtypes = [vp]
     lib.kz_gen_bitset.restype = C.c_int
     lib.kz_gen_bitset.argtypes = [vp, C.c_int32, vp, C.c_double, C.c_uint32, C.c_uint32, vp, vp, C.c_int32, vp, vp]
     return lib
@@ -198,6 +220,53 @@ def kz_gen_bitset(ctx: int, sizes, p: float, seed: int, gid: int, planted, rows:
                            None if pl is None else pl.ctypes.data, rows, int(row_words), colour, stream)
     if st != KZ_OK:
         raise KzError(st, "kz_gen_bitset")
+
+
+def kz_server_fixed_bytes(max_slots: int) -> int:
+    return int(LIB.kz_server_fixed_bytes(int(max_slots)))
+
+
+def kz_server_request_bytes(req: kz_request) -> int:
+    return int(LIB.kz_server_request_bytes(C.byref(req)))
+
+
+def kz_server_create(ctx: int, arena: int, arena_bytes: int, max_slots: int, stream: int | None) -> int:
+    srv = C.c_void_p()
+    st = LIB.kz_server_create(ctx, arena, int(arena_bytes), int(max_slots), stream, C.byref(srv))
+    if st != KZ_OK:
+        raise KzError(st, "kz_server_create")
+    return srv.value
+
+
+def kz_server_submit(srv: int, req: kz_request) -> int | None:
+    """Ticket, or None when the server cannot admit the request now (KZ_EAGAIN)."""
+    t = C.c_uint64(0)
+    st = LIB.kz_server_submit(srv, C.byref(req), C.byref(t))
+    if st == KZ_EAGAIN:
+        return None
+    if st != KZ_OK:
+        raise KzError(st, "kz_server_submit")
+    return int(t.value)
+
+
+def kz_server_progress(srv: int) -> int:
+    st = LIB.kz_server_progress(srv)
+    if st < 0:
+        raise KzError(st, "kz_server_progress")
+    return st
+
+
+def kz_server_poll(srv: int, ticket: int) -> dict | None:
+    """The request's result once it is done (the ticket is then retired), else None."""
+    r = kz_result()
+    st = LIB.kz_server_poll(srv, int(ticket), C.byref(r))
+    if st < 0:
+        raise KzError(st, "kz_server_poll")
+    return r.as_dict() if st == 1 else None
+
+
+def kz_server_destroy(srv: int) -> None:
+    LIB.kz_server_destroy(srv)
 
 
 # ----------------------------------------------------------- tensor helpers
@@ -378,3 +447,52 @@ class BatchKernelizer:
         s = torch.cuda.current_stream(batch.device)
         return kz_batch_autotune(self.kz.ctx, *batch.args(), ws.data_ptr(), ws.numel(), *batch.outputs(),
                                  s.cuda_stream)
+
+
+class Server:
+    """A kz_server with its arena allocated by torch on one device."""
+
+    def __init__(self, kz: Kernelizer, arena_bytes: int, max_slots: int = 512,
+                 stream: torch.cuda.Stream | None = None):
+        self.kz = kz
+        self.device = kz.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        fixed = kz_server_fixed_bytes(max_slots)
+        self.arena = torch.empty(fixed + int(arena_bytes), dtype=torch.uint8, device=self.device)
+        self.srv = kz_server_create(kz.ctx, self.arena.data_ptr(), self.arena.numel(), max_slots,
+                                    self.stream.cuda_stream)
+        self.keep = {}   # ticket -> tensors that must outlive the request
+
+    @staticmethod
+    def request(rows: torch.Tensor, colour: torch.Tensor, k: int, vmask: torch.Tensor,
+                emask: torch.Tensor) -> kz_request:
+        n = int(colour.numel())
+        R = int(rows.shape[1]) if rows.dim() == 2 else (int(rows.numel()) // n if n else 0)
+        return kz_request(n, int(k), R, 0, _dev_ptr(rows), _dev_ptr(colour), _dev_ptr(vmask), _dev_ptr(emask))
+
+    def submit(self, rows, colour, k, vmask, emask) -> int | None:
+        t = kz_server_submit(self.srv, self.request(rows, colour, k, vmask, emask))
+        if t is not None:
+            self.keep[t] = (rows, colour, vmask, emask)
+        return t
+
+    def progress(self) -> int:
+        return kz_server_progress(self.srv)
+
+    def poll(self, ticket: int) -> dict | None:
+        r = kz_server_poll(self.srv, ticket)
+        if r is not None:
+            self.keep.pop(ticket, None)
+        return r
+
+    def close(self) -> None:
+        if self.srv:
+            kz_server_destroy(self.srv)
+            self.srv = None
+            self.keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,25 +12,6 @@
 #include "kz.h"
 #include "kz_internal.h"
 
-struct kz_ctx {
-  int device;
-  kzi::Hdr *pinned;  // host staging for the per-pass counter readback
-  // optional per-kernel timing (kz_profile_enable)
-  bool prof;
-  struct Pending {
-    hipEvent_t a, b;
-    int kind;
-  };
-  std::vector<hipEvent_t> pool;
-  std::vector<Pending> pending;
-  double total_ms[KZ_KERNEL_COUNT];
-  int64_t launches[KZ_KERNEL_COUNT];
-  // batched path
-  kzi::BatchConfig batch_cfg;
-  bool batch_cfg_set;
-  int cus;  // compute units of the device
-};
-
 namespace {
 
 hipEvent_t take_event(kz_ctx *c) {
@@ -359,7 +340,7 @@ int kz_create(kz_ctx **out, int device) {
   c->pinned = nullptr;
   c->prof = false;
   c->batch_cfg_set = false;
-  c->batch_cfg = kzi::BatchConfig{8, 8, 1, 0, 0};
+  c->batch_cfg = kzi::BatchConfig{16, 4, 1, 0, 0};
   c->cus = 256;
   for (int i = 0; i < KZ_KERNEL_COUNT; ++i) {
     c->total_ms[i] = 0.0;

@@ -108,13 +108,23 @@ __device__ __forceinline__ GView gview(const BatchArgs &a, int g) {
   v.n = G.n;
   v.k = G.k;
   v.R = G.row_words;
-  v.rows = a.rows + G.row_offset;
-  v.cur = a.emask + G.row_offset;
-  v.nxt = a.next + G.row_offset;
-  v.colour = a.colour + G.vertex_offset;
-  v.valive = a.vmask + G.vertex_offset;
   const long long T = (long long)v.R * (v.R - 1) / 2;
-  v.changed = a.lists + 2 * G.row_offset;
+  if (a.ptrs) {
+    const BatchPtrs P = a.ptrs[g];
+    v.rows = P.rows;
+    v.cur = P.emask;
+    v.nxt = P.next;
+    v.colour = P.colour;
+    v.valive = P.vmask;
+    v.changed = P.lists;
+  } else {
+    v.rows = a.rows + G.row_offset;
+    v.cur = a.emask + G.row_offset;
+    v.nxt = a.next + G.row_offset;
+    v.colour = a.colour + G.vertex_offset;
+    v.valive = a.vmask + G.vertex_offset;
+    v.changed = a.lists + 2 * G.row_offset;
+  }
   v.items = v.changed + T;
   v.J = a.jobs + g;
   return v;
@@ -429,7 +439,7 @@ __device__ bool start_job(const BatchArgs &a, BatchLds &S, int g) {
   const kz_batch_graph G = a.graphs[g];
   const int n = G.n, k = G.k, R = G.row_words;
   int st = 0;
-  if (n < 0 || k < 1 || R < 0 || G.row_offset < 0 || G.vertex_offset < 0) st = KZ_EINVAL;
+  if (n < 0 || k < 1 || R < 0 || (!a.ptrs && (G.row_offset < 0 || G.vertex_offset < 0))) st = KZ_EINVAL;
   else if (k > kBatchK || R > kBatchR || n > kBatchN) st = kBatchTooLarge;
   if (st != 0 || n == 0) {
     if (tid == 0) {

@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 #include "kz.h"
@@ -135,8 +137,19 @@ struct alignas(128) BatchJob {
   unsigned char blen[kBatchR];
 };
 
+// Per-graph buffers when graphs do not sit in shared arenas (served requests).
+struct BatchPtrs {
+  const uint64_t *rows;
+  const int *colour;
+  uint8_t *vmask;
+  uint64_t *emask;
+  uint64_t *next;  // n*row_words words
+  int *lists;      // 2*n*row_words ints
+};
+
 struct BatchArgs {
   const kz_batch_graph *graphs;
+  const BatchPtrs *ptrs;  // [G] or null: then the arenas below and the descriptors' offsets
   int G;
   int share;      // 0: share passes once the queue is empty; 1: share every pass; 2: never
   int *order;     // [G]
@@ -169,3 +182,24 @@ struct GenArgs {
 void launch_gen_rows(const GenArgs &g, uint64_t *rows, int *colour, hipStream_t s);
 
 }  // namespace kzi
+
+// ---- the library context (kz_api.hip, kz_server.hip)
+struct kz_ctx {
+  int device;
+  kzi::Hdr *pinned;  // host staging for the per-pass counter readback
+  // optional per-kernel timing (kz_profile_enable)
+  bool prof;
+  struct Pending {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  double total_ms[KZ_KERNEL_COUNT];
+  int64_t launches[KZ_KERNEL_COUNT];
+  // batched path
+  kzi::BatchConfig batch_cfg;
+  bool batch_cfg_set;
+  int cus;  // compute units of the device
+};
+

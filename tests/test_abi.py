@@ -28,6 +28,8 @@ def test_header_declares_the_entry_points():
     assert declared() == ["kz_batch_autotune", "kz_batch_get_config", "kz_batch_set_config",
                           "kz_batch_workspace_bytes", "kz_create", "kz_destroy", "kz_gen_bitset",
                           "kz_kernelize", "kz_kernelize_batch", "kz_profile_enable", "kz_profile_read",
+                          "kz_server_create", "kz_server_destroy", "kz_server_fixed_bytes", "kz_server_poll",
+                          "kz_server_progress", "kz_server_request_bytes", "kz_server_submit",
                           "kz_strerror", "kz_workspace_bytes"]
 
 
@@ -73,3 +75,4 @@ def test_struct_layouts_match_the_header():
     assert b.BATCH_GRAPH_DTYPE.itemsize == 32
     assert C.sizeof(b.kz_graph) == 56
     assert C.sizeof(b.kz_batch_config) == 20
+    assert C.sizeof(b.kz_request) == 48

@@ -1,0 +1,211 @@
+"""Serving on the GPU: requests admitted one by one and run with continuous
+batching give the oracle's masks and counts, the same alone as in a mix;
+admission refuses what does not fit and admits it once space is back."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import kernelize_bitset  # noqa: E402
+from paper_2212_00574_amd import inputs  # noqa: E402
+from paper_2212_00574_amd.binding import (KZ_ETOOLARGE, KzError, Kernelizer, Server, kz_gen_bitset,  # noqa: E402
+                                          kz_request, kz_server_request_bytes)
+
+DEV = torch.device("cuda", 0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def kz():
+    k = Kernelizer(0)
+    yield k
+    k.close()
+
+
+class Req:
+    """A request's device buffers, generated on the host from inputs.py."""
+
+    def __init__(self, sizes, p, seed, gid, plant=False):
+        g = inputs.make_graph(sizes, p, seed=seed, gid=gid, plant=plant and 0 not in list(sizes), shuffle=False)
+        self.rows_np, self.col_np, lay = g.bitset()
+        self.k = len(sizes)
+        self.n, self.R = lay.n, lay.R
+        self.rows = torch.from_numpy(self.rows_np.view(np.int64).reshape(-1).copy()).to(DEV)
+        self.colour = torch.from_numpy(self.col_np).to(DEV)
+        self.vmask = torch.full((max(self.n, 1),), 9, dtype=torch.uint8, device=DEV)
+        self.emask = torch.full((max(self.n * self.R, 1),), -1, dtype=torch.int64, device=DEV)
+
+    def submit(self, srv):
+        return srv.submit(self.rows, self.colour, self.k, self.vmask, self.emask)
+
+    def masks(self):
+        vm = self.vmask.cpu().numpy()[:self.n]
+        em = self.emask.cpu().numpy()[:self.n * self.R].view(np.uint64).reshape(self.n, self.R)
+        return vm, em
+
+
+def mixed_requests(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        k = int(rng.integers(3, 9))
+        sizes = rng.integers(1, 60, size=k)
+        out.append(Req(sizes, float(rng.uniform(0.2, 0.8)), seed, i, plant=bool(rng.random() < 0.2)))
+    return out
+
+
+def run_all(srv, reqs, stagger=0, limit=120.0):
+    """Submits the requests in order (a progress call every `stagger`
+    submissions), polling finished ones whenever admission has to wait (a
+    request holds its slot until polled); returns results in request order."""
+    tickets = [None] * len(reqs)
+    res = [None] * len(reqs)
+    t0 = time.time()
+
+    def collect():
+        for j, t in enumerate(tickets):
+            if t is not None and res[j] is None:
+                res[j] = srv.poll(t)
+
+    for i, r in enumerate(reqs):
+        t = r.submit(srv)
+        while t is None:          # no slot / scratch now: retire finished requests
+            collect()
+            assert time.time() - t0 < limit, "admission did not resume"
+            t = r.submit(srv)
+        tickets[i] = t
+        if stagger and i % stagger == 0:
+            srv.progress()
+    while any(x is None for x in res):
+        collect()
+        assert time.time() - t0 < limit, "requests did not complete"
+    return res
+
+
+def wait(srv, ticket, limit=60.0):
+    t0 = time.time()
+    while True:
+        r = srv.poll(ticket)
+        if r is not None:
+            return r
+        assert time.time() - t0 < limit, "request did not complete"
+
+
+def check(reqs, res, ctx):
+    for i, (r, x) in enumerate(zip(reqs, res)):
+        ref = kernelize_bitset(r.rows_np, r.col_np, r.k)
+        assert x["status"] == ref["status"], (ctx, i)
+        if ref["status"]:
+            continue
+        assert x["rounds"] == ref["rounds"] and x["equals_input"] == ref["equals_input"], (ctx, i)
+        assert x["surviving_vertices"] == ref["surv_vertices"], (ctx, i)
+        assert x["surviving_edges"] == ref["surv_edges"], (ctx, i)
+        assert x["edge_tests"] == ref["edge_tests"], (ctx, i)
+        vm, em = r.masks()
+        assert np.array_equal(vm, ref["vmask"]), (ctx, i)
+        assert np.array_equal(em, ref["emask"]), (ctx, i)
+
+
+def test_server_matches_oracle(kz):
+    say("server: 60 mixed requests")
+    srv = Server(kz, arena_bytes=64 << 20, max_slots=32)
+    reqs = mixed_requests(60, seed=21)
+    res = run_all(srv, reqs, stagger=7)
+    check(reqs, res, "mixed")
+    srv.close()
+
+
+def test_server_alone_equals_in_mix(kz):
+    say("server: alone vs mix")
+    srv = Server(kz, arena_bytes=64 << 20, max_slots=64)
+    mix = mixed_requests(40, seed=22)
+    probe = [Req([50, 45, 60, 40], 0.55, 22, 1000 + i, plant=True) for i in range(3)]
+    alone = [run_all(srv, [p])[0] for p in probe]
+    alone_masks = [p.masks() for p in probe]
+    for p in probe:
+        p.vmask.fill_(9)
+        p.emask.fill_(-1)
+    res = run_all(srv, mix[:20] + probe + mix[20:], stagger=5)
+    inmix = res[20:23]
+    for a, b, p, (vm, em) in zip(alone, inmix, probe, alone_masks):
+        assert a == b
+        vm2, em2 = p.masks()
+        assert np.array_equal(vm, vm2) and np.array_equal(em, em2)
+    check(probe, inmix, "probe")
+    srv.close()
+
+
+def test_server_admission(kz):
+    say("server: admission")
+    big = Req([300] * 6, 0.5, 23, 0)
+    need = kz_server_request_bytes(Server.request(big.rows, big.colour, big.k, big.vmask, big.emask))
+    srv = Server(kz, arena_bytes=need + need // 2, max_slots=2)   # room for one such request
+    t1 = big.submit(srv)
+    assert t1 is not None
+    other = Req([300] * 6, 0.5, 23, 1)
+    assert other.submit(srv) is None            # scratch is held by the first
+    small = Req([10, 10, 10], 0.5, 23, 2)
+    t2 = small.submit(srv)                      # small fits beside it
+    assert t2 is not None
+    assert Req([5, 5], 0.5, 23, 3).submit(srv) is None   # both slots taken
+    res1 = wait(srv, t1)
+    t3 = other.submit(srv)                      # scratch is back
+    assert t3 is not None
+    wait(srv, t2)
+    r3 = wait(srv, t3)
+    check([big, other], [res1, r3], "admission")
+    with pytest.raises(KzError):
+        srv.poll(t1)                            # retired
+    srv.close()
+
+
+def test_server_errors_and_limits(kz):
+    say("server: errors")
+    srv = Server(kz, arena_bytes=16 << 20, max_slots=8)
+    good = Req([20, 20, 20], 0.5, 24, 0)
+    bad = Req([20, 20, 20], 0.5, 24, 1)
+    bad.colour[-1] = 7                          # colour out of range
+    res = run_all(srv, [good, bad])
+    check([good], [res[0]], "good")
+    assert res[1]["status"] == -2
+    r = kz_request(40000, 4, 10, 0, 1, 1, 1, 1)   # n beyond the batched path
+    from paper_2212_00574_amd.binding import kz_server_submit
+    with pytest.raises(KzError) as e:
+        kz_server_submit(srv.srv, r)
+    assert e.value.status == KZ_ETOOLARGE
+    srv.close()
+
+
+def test_server_large_and_generated(kz):
+    """A request larger than 4096 vertices, materialised on the device by
+    kz_gen_bitset on the server's stream, beside small ones."""
+    say("server: generated large request")
+    srv = Server(kz, arena_bytes=512 << 20, max_slots=16)
+    sizes = [700] * 8
+    g = inputs.make_graph(sizes, 0.06, seed=12, gid=0, plant=True, shuffle=False)
+    rows_np, col_np, lay = g.bitset()
+    rows = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+    colour = torch.empty(lay.n, dtype=torch.int32, device=DEV)
+    kz_gen_bitset(kz.ctx, sizes, 0.06, 12, 0, g.planted, rows.data_ptr(), lay.R, colour.data_ptr(),
+                  srv.stream.cuda_stream)
+    vmask = torch.empty(lay.n, dtype=torch.uint8, device=DEV)
+    emask = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+    t = srv.submit(rows, colour, len(sizes), vmask, emask)
+    small = mixed_requests(10, seed=25)
+    res_small = run_all(srv, small)
+    res = wait(srv, t)
+    ref = kernelize_bitset(rows_np, col_np, len(sizes))
+    assert res["rounds"] == ref["rounds"] and res["edge_tests"] == ref["edge_tests"]
+    assert np.array_equal(vmask.cpu().numpy(), ref["vmask"])
+    assert np.array_equal(emask.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R), ref["emask"])
+    check(small, res_small, "small")
+    srv.close()
