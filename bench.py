@@ -34,6 +34,8 @@ WORKLOADS = {
     "c3a": "k=20 classes x 1000 vertices (n=20000), p=0.3, uint64 bit rows",
     "c3b": "k=30 multinomial classes, n=100000, 2.5M uniform inter-class edges (avg degree 50), CSR",
     "c4": "4096 graphs, k~U{4..16}, class sizes~U{8..128}, p~U[0.2,0.8], 10% planted k-clique, uint64 bit rows",
+    "c5": "served requests: n log-uniform [200,20000], k~U{5..30} near-equal classes, p~U[0.1,0.9], Poisson "
+          "arrivals, uint64 bit rows materialised on the device at arrival",
 }
 
 
@@ -47,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="steps of the per-kernel event-timed loop (default: --steps)")
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="c5: requests per phase (a bounded prefix of the 50k-request stream)")
     ap.add_argument("--copy-calibration", type=int, default=None, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (memory-counter calibration)")
     return ap.parse_args()
@@ -290,6 +294,144 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Config 5: continuous-batching server, closed-loop saturation and two
+    Poisson open-loop rates, p50/p99 latency from arrival to completion."""
+    import torch
+
+    from paper_2212_00574_amd import inputs
+    from paper_2212_00574_amd.binding import Kernelizer, Server, kz_gen_bitset
+    N = args.requests
+    specs = inputs.config5_specs(args.seed, requests=N)
+    dev = torch.device("cuda", 0)
+    kz = Kernelizer(0)
+    bufs = []
+    for sp in specs:
+        n, R = int(sp.n), int(((sp.sizes + 63) // 64).sum())
+        bufs.append({"n": n, "R": R, "k": int(sp.k),
+                     "rows": torch.empty(n * R, dtype=torch.int64, device=dev),
+                     "colour": torch.empty(n, dtype=torch.int32, device=dev),
+                     "vmask": torch.empty(n, dtype=torch.uint8, device=dev),
+                     "emask": torch.empty(n * R, dtype=torch.int64, device=dev)})
+    srv = Server(kz, arena_bytes=8 << 30, max_slots=512)
+    sid = srv.stream.cuda_stream
+    gen = [False] * N
+
+    def submit(i):
+        b, sp = bufs[i], specs[i]
+        if not gen[i]:   # materialise the request's rows on the server's stream
+            kz_gen_bitset(kz.ctx, sp.sizes, sp.p, args.seed, i, None, b["rows"].data_ptr(), b["R"],
+                          b["colour"].data_ptr(), sid)
+            gen[i] = True
+        return srv.submit(b["rows"], b["colour"], b["k"], b["vmask"], b["emask"])
+
+    def run(arrivals):
+        """Admits request i at arrivals[i] (seconds; None = as fast as admitted);
+        returns (results, latency seconds, elapsed seconds)."""
+        for i in range(N):
+            gen[i] = False
+        res, lat = [None] * N, np.zeros(N)
+        fifo, backlog = [], []
+        nxt, done, head = 0, 0, 0
+        t0 = time.perf_counter()
+        while done < N:
+            now = time.perf_counter() - t0
+            while nxt < N and (arrivals is None or arrivals[nxt] <= now):
+                backlog.append(nxt)
+                nxt += 1
+            while backlog:
+                t = submit(backlog[0])
+                if t is None:
+                    break
+                fifo.append((t, backlog.pop(0)))
+            srv.progress()
+            # launches complete in admission order: poll from the oldest
+            while head < len(fifo):
+                t, i = fifo[head]
+                r = srv.poll(t)
+                if r is None:
+                    break
+                res[i] = r
+                lat[i] = time.perf_counter() - t0 - (arrivals[i] if arrivals is not None else 0.0)
+                head += 1
+                done += 1
+            if time.perf_counter() - t0 > 300:
+                raise RuntimeError("serving run did not finish")
+        return res, lat, time.perf_counter() - t0
+
+    warm = N
+    N = min(32, warm)
+    run(None)                              # warm-up on the first requests
+    N = warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(srv.stream)
+    res, _, closed_s = run(None)
+    e1.record(srv.stream)
+    torch.cuda.synchronize()
+    gpu_ms = e0.elapsed_time(e1)
+    st = np.array([r["status"] for r in res])
+    assert np.all(st == 0), np.unique(st)
+    S = N / closed_s
+    base_arr = np.array([sp.arrival_s for sp in specs])   # offered rate 1000/s in the specs
+    phases = {}
+    for frac in (0.5, 0.8):
+        rate = frac * S
+        arr = base_arr * (1000.0 / rate)
+        r2, lat, el = run(arr)
+        for i in range(N):
+            assert r2[i]["edge_tests"] == res[i]["edge_tests"] and r2[i]["rounds"] == res[i]["rounds"], i
+        phases["%.1fS" % frac] = {"offered_rps": rate, "achieved_rps": N / el, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                  "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3)}
+        print("phase %.1fS: %s" % (frac, phases["%.1fS" % frac]), file=sys.stderr, flush=True)
+    tests = np.array([r["edge_tests"] for r in res], dtype=np.float64)
+    # full-segment ops: with near-equal classes every segment has R/k words
+    # (to within one), so an edge test costs 4 R (k - 2) / k 32-bit ops
+    ops = float(sum(tests[i] * 4.0 * bufs[i]["R"] * (bufs[i]["k"] - 2) / bufs[i]["k"] for i in range(N)))
+    achieved = ops / (gpu_ms / 1e3) / 1e12
+    # parity spot-check: the three smallest requests against the oracle
+    from oracle import kernelize_bitset
+    for i in sorted(range(N), key=lambda j: bufs[j]["n"] * bufs[j]["R"])[:3]:
+        g = inputs.make_graph(specs[i].sizes, specs[i].p, seed=args.seed, gid=i, shuffle=False)
+        rows, col, lay = g.bitset()
+        ref = kernelize_bitset(rows, col, specs[i].k)
+        assert ref["edge_tests"] == res[i]["edge_tests"] and ref["surv_edges"] == res[i]["surviving_edges"], i
+        assert np.array_equal(bufs[i]["vmask"].cpu().numpy(), ref["vmask"]), i
+    cpu = None
+    if not args.no_cpu_baseline:
+        t_or, done_n, tests_n = 0.0, 0, 0
+        for i in sorted(range(N), key=lambda j: bufs[j]["n"]):
+            g = inputs.make_graph(specs[i].sizes, specs[i].p, seed=args.seed, gid=i, shuffle=False)
+            rows, col, lay = g.bitset()
+            t0 = time.perf_counter()
+            ref = kernelize_bitset(rows, col, specs[i].k)
+            t_or += time.perf_counter() - t0
+            done_n += 1
+            tests_n += ref["edge_tests"]
+            if t_or > 15:
+                break
+        cpu = {"value": tests_n / t_or, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
+               "sample": "the %d smallest of the %d requests, one oracle fixpoint each (%.1f s); the mix would take "
+                         "%.0f s at this rate" % (done_n, N, t_or, tests.sum() / (tests_n / t_or))}
+    out = {
+        "metric": "served requests/s (closed loop)", "value": S, "unit": "requests/s", "n_gpus": 1,
+        "steps": N, "warmup": 32, "ms_per_step": closed_s * 1e3 / N, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "c5: " + WORKLOADS["c5"], "requests": N, "seed": args.seed,
+                   "edge_tests": float(tests.sum()), "max_rounds": int(max(r["rounds"] for r in res)),
+                   "batch_config": None, "parallelism": "single GPU"},
+        "latency": phases,
+        "edge_tests_per_s": float(tests.sum()) / closed_s,
+        "roofline": {"kernel": "k_batch (batch lane) and k_edge (single-graph lane), whole closed loop",
+                     "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": None, "ops": "32-bit VALU ops of the full-segment edge test over the exact worklists",
+                     "gpu_stream_ms": round(gpu_ms, 3)},
+        "cpu_baseline": cpu,
+    }
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(mib):
     """Device-to-device copies of a known size, for scaling memory counters."""
     import torch
@@ -313,6 +455,9 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         bench_batch(args)
+        return
+    if args.workload == "c5":
+        bench_serve(args)
         return
     import torch
 

@@ -218,15 +218,20 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
  * A server admits requests one at a time and runs them with continuous
  * batching: each launch of the batched path (the job runtime above) takes
  * every admitted request that is waiting, and at most two launches are in
- * flight on the server's stream (one running, one queued behind it).  A
- * request is a KZ_BITSET_U64 graph in caller-owned device buffers; results
- * are the same as kz_kernelize on the graph alone.  The server takes a
- * fixed part of a caller-provided device arena for its launch records and
- * carves each admitted request's scratch from the rest (first fit); it
- * admits a request only when a slot and its scratch are free, else
- * KZ_EAGAIN.  It allocates no device memory of its own; it allocates pinned
- * host memory for descriptors and results when it is created.  A server
- * belongs to one host thread. */
+ * flight on the server's stream (one running, one queued behind it).
+ * Requests of 4096 vertices or more (or beyond the batched path's k and
+ * row-word limits) take a second lane instead: a worker
+ * thread runs them one at a time through the single-graph path on a stream
+ * of its own, overlapping the batch launches.  A request is a
+ * KZ_BITSET_U64 graph in caller-owned device buffers; results are the same
+ * as kz_kernelize on the graph alone.  The server takes a fixed part of a
+ * caller-provided device arena for its launch records and carves each
+ * admitted request's scratch from the rest (first fit); it admits a request
+ * only when a slot and its scratch are free, else KZ_EAGAIN.  It allocates
+ * no device memory of its own; when it is created it allocates pinned host
+ * memory for descriptors and results, a second context, a stream and the
+ * worker thread.  A server belongs to one host thread (the worker is
+ * internal). */
 typedef struct kz_server kz_server;
 
 typedef struct kz_request {
@@ -243,9 +248,11 @@ typedef struct kz_request {
  * must be larger by the scratch of the requests it is to hold at once. */
 size_t kz_server_fixed_bytes(int32_t max_slots);
 
-/* Arena bytes an admitted request holds until it is done (its next-state
- * words and tile lists: 16 bytes per row word, 256-byte aligned). */
-size_t kz_server_request_bytes(const kz_request *req);
+/* Arena bytes an admitted request holds until it is done: in the batch
+ * lane its next-state words and tile lists (16 bytes per row word), in the
+ * single-graph lane kz_kernelize's workspace; 256-byte aligned.  0 for an
+ * invalid request. */
+size_t kz_server_request_bytes(const kz_server *srv, const kz_request *req);
 
 /* Creates a server on ctx's device.  arena: device memory, 256-byte aligned,
  * arena_bytes > kz_server_fixed_bytes(max_slots), owned by the caller and
@@ -256,8 +263,8 @@ int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_s
                      kz_server **out);
 
 /* Admits a request: KZ_OK and *ticket, KZ_EAGAIN (no slot or scratch now:
- * retry after kz_server_progress), KZ_EINVAL (bad arguments), or
- * KZ_ETOOLARGE (beyond the batched path's limits). */
+ * retry after kz_server_poll has retired finished requests), or KZ_EINVAL
+ * (bad arguments). */
 int kz_server_submit(kz_server *srv, const kz_request *req, uint64_t *ticket);
 
 /* Retires finished launches (freeing their scratch) and launches waiting

@@ -100,7 +100,7 @@ def _load() -> C.CDLL:
     lib.kz_server_fixed_bytes.restype = C.c_size_t
     lib.kz_server_fixed_bytes.argtypes = [C.c_int32]
     lib.kz_server_request_bytes.restype = C.c_size_t
-    lib.kz_server_request_bytes.argtypes = [C.POINTER(kz_request)]
+    lib.kz_server_request_bytes.argtypes = [vp, C.POINTER(kz_request)]
     lib.kz_server_create.restype = C.c_int
     lib.kz_server_create.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp, C.POINTER(vp)]
     lib.kz_server_submit.restype = C.c_int
@@ -226,8 +226,8 @@ def kz_server_fixed_bytes(max_slots: int) -> int:
     return int(LIB.kz_server_fixed_bytes(int(max_slots)))
 
 
-def kz_server_request_bytes(req: kz_request) -> int:
-    return int(LIB.kz_server_request_bytes(C.byref(req)))
+def kz_server_request_bytes(srv: int, req: kz_request) -> int:
+    return int(LIB.kz_server_request_bytes(srv, C.byref(req)))
 
 
 def kz_server_create(ctx: int, arena: int, arena_bytes: int, max_slots: int, stream: int | None) -> int:

@@ -1,5 +1,6 @@
 // Serving (host code): admission by slot and arena scratch, continuous
-// batching at launch granularity on top of the batched path's job runtime.
+// batching at launch granularity on top of the batched path's job runtime,
+// and a second lane for large requests.
 //
 // The arena starts with two launch records (descriptors, pointer tables,
 // job states, results, queue counters), each able to carry max_slots
@@ -8,11 +9,23 @@
 // tables, copies them to the device, runs the batched kernels and copies
 // the results back, all on the server's stream, and records an event;
 // kz_server_progress retires launches whose event has fired.
+//
+// Requests with at least kSplitN vertices (or beyond the batched path's
+// class and row-word limits) go to a worker thread instead:
+// it runs them one at a time through the single-graph path (kz_kernelize,
+// whose multi-workgroup passes suit large graphs) on a stream of its own,
+// after waiting for an event recorded on the server's stream when the
+// request was admitted (so inputs written there first are complete).  Both
+// lanes overlap on the device.  The two threads share the request table and
+// the arena heap under one mutex.
 #include <string.h>
 
+#include <condition_variable>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -24,6 +37,7 @@ namespace {
 constexpr size_t kSrvAlign = 256;
 constexpr int kSrvMaxSlots = 4096;
 constexpr int kSrvMaxWorkgroups = 1024;
+constexpr int kSplitN = 4096;  // vertices from which a request takes the single-graph lane
 
 size_t up(size_t x) { return (x + kSrvAlign - 1) / kSrvAlign * kSrvAlign; }
 
@@ -93,6 +107,8 @@ struct Req {
   kz_request r;
   size_t at, bytes;  // scratch in the arena
   int state;         // 0 waiting, 1 launched, 2 done
+  bool big;          // single-graph lane
+  hipEvent_t ready;  // big: inputs complete on the server's stream
   kz_result res;
 };
 
@@ -121,11 +137,31 @@ struct kz_server {
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next_ticket;
   int admitted;  // requests admitted and not yet retired by a poll
+  // single-graph lane
+  kz_ctx *wctx;  // the worker's context (its own readback buffer)
+  hipStream_t wstream;
+  std::thread worker;
+  std::mutex mu;  // reqs, heap, big, stop, admitted
+  std::condition_variable cv;
+  std::deque<uint64_t> big;
+  bool stop;
 };
 
 namespace {
 
 void release(kz_server *s) {
+  if (s->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      s->stop = true;
+    }
+    s->cv.notify_all();
+    s->worker.join();
+  }
+  for (auto &kv : s->reqs)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+  if (s->wstream) (void)hipStreamDestroy(s->wstream);
+  if (s->wctx) kz_destroy(s->wctx);
   for (Record &r : s->rec) {
     if (r.done) (void)hipEventDestroy(r.done);
     if (r.graphs_host) (void)hipHostFree(r.graphs_host);
@@ -133,6 +169,45 @@ void release(kz_server *s) {
     if (r.results_host) (void)hipHostFree(r.results_host);
   }
   delete s;
+}
+
+// The single-graph lane: one large request at a time.
+void work(kz_server *s) {
+  (void)hipSetDevice(s->ctx->device);
+  for (;;) {
+    uint64_t t = 0;
+    Req q{};
+    {
+      std::unique_lock<std::mutex> g(s->mu);
+      s->cv.wait(g, [s] { return s->stop || !s->big.empty(); });
+      if (s->stop) return;
+      t = s->big.front();
+      s->big.pop_front();
+      Req &r = s->reqs[t];
+      r.state = 1;
+      q = r;
+    }
+    kz_result res{};
+    res.status = KZ_EHIP;
+    if (hipStreamWaitEvent(s->wstream, q.ready, 0) == hipSuccess) {
+      kz_graph gr{};
+      gr.format = KZ_BITSET_U64;
+      gr.n = q.r.n;
+      gr.rows = q.r.rows;
+      gr.row_words = q.r.row_words;
+      (void)kz_kernelize(s->wctx, &gr, q.r.colour, q.r.k, s->arena + q.at, q.bytes, q.r.vmask, q.r.emask,
+                         s->wstream, &res);
+      if (hipStreamSynchronize(s->wstream) != hipSuccess) res.status = KZ_EHIP;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    Req &r = s->reqs[t];
+    r.res = res;
+    r.state = 2;
+    (void)hipEventDestroy(r.ready);
+    r.ready = nullptr;
+    if (r.bytes) s->heap.give(r.at, r.bytes);
+    r.bytes = 0;
+  }
 }
 
 int launch(kz_server *s, Record &rec) {
@@ -199,10 +274,33 @@ size_t kz_server_fixed_bytes(int32_t max_slots) {
   return 2 * rec_layout(max_slots).total;
 }
 
-size_t kz_server_request_bytes(const kz_request *req) {
-  if (!req || req->n < 0 || req->row_words < 0) return 0;
-  const size_t words = (size_t)req->n * (size_t)req->row_words;
+namespace {
+
+// Scratch of the batch lane: next-state words and tile lists.
+size_t batch_bytes(const kz_request &r) {
+  const size_t words = (size_t)r.n * (size_t)r.row_words;
   return up(words * sizeof(uint64_t)) + up(2 * words * sizeof(int));
+}
+
+// Scratch of the single-graph lane: kz_kernelize's workspace.
+int single_bytes(kz_ctx *ctx, const kz_request &r, size_t *bytes) {
+  kz_graph gr{};
+  gr.format = KZ_BITSET_U64;
+  gr.n = r.n;
+  gr.rows = r.rows;
+  gr.row_words = r.row_words;
+  const int st = kz_workspace_bytes(ctx, &gr, r.k, bytes);
+  *bytes = up(*bytes);
+  return st;
+}
+
+}  // namespace
+
+size_t kz_server_request_bytes(const kz_server *s, const kz_request *req) {
+  if (!s || !req || req->n < 0 || req->k < 1 || req->row_words < 0) return 0;
+  if (req->n < kSplitN && req->k <= kzi::kBatchK && req->row_words <= kzi::kBatchR) return batch_bytes(*req);
+  size_t b = 0;
+  return single_bytes(s->wctx, *req, &b) == KZ_OK ? b : 0;
 }
 
 int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_slots, void *stream,
@@ -224,6 +322,9 @@ int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_s
   s->next_ticket = 1;
   s->admitted = 0;
   s->heap.init(2 * L.total, arena_bytes - 2 * L.total);
+  s->wctx = nullptr;
+  s->wstream = nullptr;
+  s->stop = false;
   for (int i = 0; i < 2; ++i) {
     Record &r = s->rec[i];
     r.dev = s->arena + i * L.total;
@@ -249,6 +350,11 @@ int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_s
       return KZ_EHIP;
     }
   }
+  if (kz_create(&s->wctx, ctx->device) != KZ_OK || hipStreamCreate(&s->wstream) != hipSuccess) {
+    release(s);
+    return KZ_EHIP;
+  }
+  s->worker = std::thread(work, s);
   *out = s;
   return KZ_OK;
 }
@@ -258,27 +364,40 @@ int kz_server_submit(kz_server *s, const kz_request *req, uint64_t *ticket) {
   const kz_request &r = *req;
   if (r.n < 0 || r.k < 1 || r.row_words < 0 || (r.n > 0 && (!r.rows || !r.colour || !r.vmask || !r.emask)))
     return KZ_EINVAL;
-  if (r.k > kzi::kBatchK || r.row_words > kzi::kBatchR || r.n > kzi::kBatchN) return KZ_ETOOLARGE;
+  const bool big = r.n >= kSplitN || r.k > kzi::kBatchK || r.row_words > kzi::kBatchR;
+  size_t bytes = batch_bytes(r);
+  if (big && single_bytes(s->wctx, r, &bytes) != KZ_OK) return KZ_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
   if (s->admitted >= s->slots) return KZ_EAGAIN;
-  const size_t bytes = kz_server_request_bytes(&r);
   size_t at = 0;
   if (bytes && !s->heap.take(bytes, &at)) return KZ_EAGAIN;
-  const uint64_t t = s->next_ticket++;
   Req q{};
   q.r = r;
   q.at = at;
   q.bytes = bytes;
   q.state = 0;
+  q.big = big;
+  q.ready = nullptr;
+  if (big && (hipEventCreateWithFlags(&q.ready, hipEventDisableTiming) != hipSuccess ||
+              hipEventRecord(q.ready, s->stream) != hipSuccess)) {
+    if (q.ready) (void)hipEventDestroy(q.ready);
+    if (bytes) s->heap.give(at, bytes);
+    return KZ_EHIP;
+  }
+  const uint64_t t = s->next_ticket++;
   s->reqs.emplace(t, q);
-  s->waiting.push_back(t);
+  if (big) s->big.push_back(t);
+  else s->waiting.push_back(t);
   ++s->admitted;
   *ticket = t;
+  if (big) s->cv.notify_one();
   return KZ_OK;
 }
 
 int kz_server_progress(kz_server *s) {
   if (!s) return KZ_EINVAL;
   if (hipSetDevice(s->ctx->device) != hipSuccess) return KZ_EHIP;
+  std::lock_guard<std::mutex> g(s->mu);
   for (Record &rec : s->rec) {
     if (!rec.busy) continue;
     const hipError_t e = hipEventQuery(rec.done);
@@ -309,6 +428,7 @@ int kz_server_poll(kz_server *s, uint64_t ticket, kz_result *res) {
   if (!s) return KZ_EINVAL;
   const int st = kz_server_progress(s);
   if (st < 0) return st;
+  std::lock_guard<std::mutex> g(s->mu);
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return KZ_EINVAL;
   if (it->second.state != 2) return 0;
@@ -321,6 +441,11 @@ int kz_server_poll(kz_server *s, uint64_t ticket, kz_result *res) {
 void kz_server_destroy(kz_server *s) {
   if (!s) return;
   (void)hipSetDevice(s->ctx->device);
+  {
+    // let the worker finish what it holds; it takes nothing new once stopped
+    std::unique_lock<std::mutex> g(s->mu);
+    s->big.clear();
+  }
   for (Record &rec : s->rec)
     if (rec.busy) (void)hipEventSynchronize(rec.done);
   release(s);

@@ -14,7 +14,7 @@ if not torch.cuda.is_available():
 
 from oracle import kernelize_bitset  # noqa: E402
 from paper_2212_00574_amd import inputs  # noqa: E402
-from paper_2212_00574_amd.binding import (KZ_ETOOLARGE, KzError, Kernelizer, Server, kz_gen_bitset,  # noqa: E402
+from paper_2212_00574_amd.binding import (KzError, Kernelizer, Server, kz_gen_bitset,  # noqa: E402
                                           kz_request, kz_server_request_bytes)
 
 DEV = torch.device("cuda", 0)
@@ -147,7 +147,10 @@ def test_server_alone_equals_in_mix(kz):
 def test_server_admission(kz):
     say("server: admission")
     big = Req([300] * 6, 0.5, 23, 0)
-    need = kz_server_request_bytes(Server.request(big.rows, big.colour, big.k, big.vmask, big.emask))
+    probe = Server(kz, arena_bytes=1 << 20, max_slots=2)
+    need = kz_server_request_bytes(probe.srv, Server.request(big.rows, big.colour, big.k, big.vmask, big.emask))
+    probe.close()
+    assert need >= 16 * big.n * big.R
     srv = Server(kz, arena_bytes=need + need // 2, max_slots=2)   # room for one such request
     t1 = big.submit(srv)
     assert t1 is not None
@@ -177,35 +180,42 @@ def test_server_errors_and_limits(kz):
     res = run_all(srv, [good, bad])
     check([good], [res[0]], "good")
     assert res[1]["status"] == -2
-    r = kz_request(40000, 4, 10, 0, 1, 1, 1, 1)   # n beyond the batched path
+    wide = Req([3] * 70, 0.6, 24, 2)            # k = 70: beyond the batch lane, runs in the other lane
+    res = run_all(srv, [wide, good])
+    check([wide, good], res, "wide")
     from paper_2212_00574_amd.binding import kz_server_submit
-    with pytest.raises(KzError) as e:
-        kz_server_submit(srv.srv, r)
-    assert e.value.status == KZ_ETOOLARGE
+    with pytest.raises(KzError):
+        kz_server_submit(srv.srv, kz_request(10, 0, 1, 0, 1, 1, 1, 1))   # k = 0
     srv.close()
 
 
 def test_server_large_and_generated(kz):
-    """A request larger than 4096 vertices, materialised on the device by
-    kz_gen_bitset on the server's stream, beside small ones."""
-    say("server: generated large request")
-    srv = Server(kz, arena_bytes=512 << 20, max_slots=16)
-    sizes = [700] * 8
-    g = inputs.make_graph(sizes, 0.06, seed=12, gid=0, plant=True, shuffle=False)
-    rows_np, col_np, lay = g.bitset()
-    rows = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
-    colour = torch.empty(lay.n, dtype=torch.int32, device=DEV)
-    kz_gen_bitset(kz.ctx, sizes, 0.06, 12, 0, g.planted, rows.data_ptr(), lay.R, colour.data_ptr(),
-                  srv.stream.cuda_stream)
-    vmask = torch.empty(lay.n, dtype=torch.uint8, device=DEV)
-    emask = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
-    t = srv.submit(rows, colour, len(sizes), vmask, emask)
+    """Requests larger than 4096 vertices (the single-graph lane), materialised
+    on the device by kz_gen_bitset on the server's stream just before they
+    are submitted, beside small ones in the batch lane."""
+    say("server: generated large requests")
+    srv = Server(kz, arena_bytes=2 << 30, max_slots=16)
+    big = []
+    for sizes, p, gid in (([700] * 8, 0.06, 0), ([2100] * 4, 0.05, 3)):
+        g = inputs.make_graph(sizes, p, seed=12, gid=gid, plant=True, shuffle=False)
+        rows_np, col_np, lay = g.bitset()
+        rows = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+        colour = torch.empty(lay.n, dtype=torch.int32, device=DEV)
+        kz_gen_bitset(kz.ctx, sizes, p, 12, gid, g.planted, rows.data_ptr(), lay.R, colour.data_ptr(),
+                      srv.stream.cuda_stream)
+        vmask = torch.empty(lay.n, dtype=torch.uint8, device=DEV)
+        emask = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+        t = srv.submit(rows, colour, len(sizes), vmask, emask)
+        assert t is not None
+        big.append((t, rows_np, col_np, len(sizes), vmask, emask, lay))
     small = mixed_requests(10, seed=25)
     res_small = run_all(srv, small)
-    res = wait(srv, t)
-    ref = kernelize_bitset(rows_np, col_np, len(sizes))
-    assert res["rounds"] == ref["rounds"] and res["edge_tests"] == ref["edge_tests"]
-    assert np.array_equal(vmask.cpu().numpy(), ref["vmask"])
-    assert np.array_equal(emask.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R), ref["emask"])
+    for t, rows_np, col_np, k, vmask, emask, lay in big:
+        res = wait(srv, t)
+        ref = kernelize_bitset(rows_np, col_np, k)
+        assert res["rounds"] == ref["rounds"] and res["edge_tests"] == ref["edge_tests"]
+        assert res["surviving_edges"] == ref["surv_edges"]
+        assert np.array_equal(vmask.cpu().numpy(), ref["vmask"])
+        assert np.array_equal(emask.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R), ref["emask"])
     check(small, res_small, "small")
     srv.close()
