@@ -119,21 +119,32 @@ def edge_work(w):
     return float(op_bytes), float(ops), int(np.triu(cnt, 1).sum())
 
 
-def source_hash():
+# The kernel whose launches set each workload's roofline, and the sources it
+# is built from (a committed counter summary is used only while they match).
+PROFILED = {
+    "c1": ("k_edge", ("kz_kernels.hip", "kz_internal.h")),
+    "c2": ("k_edge", ("kz_kernels.hip", "kz_internal.h")),
+    "c3a": ("k_edge", ("kz_kernels.hip", "kz_internal.h")),
+    "c3b": ("k_csr_edge", ("kz_csr.hip", "kz_internal.h")),
+    "c4": ("k_batch", ("kz_batch.hip", "kz_internal.h")),
+}
+
+
+def source_hash(workload="c2"):
     h = hashlib.sha256()
-    for f in ("kz_kernels.hip", "kz_internal.h"):
+    for f in PROFILED.get(workload, PROFILED["c2"])[1]:
         h.update(open(os.path.join(ROOT, "paper_2212_00574_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def traffic_from_profile(workload):
-    """HBM bytes per edge-pass launch from the committed counter summary.
-
-    Read from profiles/k_edge_<workload>.md ("- hbm_bytes_per_launch: B" and
-    "- source_sha: S"); None when absent or when the kernels changed since
-    the counters were taken.
+    """HBM bytes per launch of the workload's roofline kernel, from the
+    committed counter summary profiles/<kernel>_<workload>.md ("-
+    hbm_bytes_per_launch: B" and "- source_sha: S"); None when absent or when
+    the kernel's sources changed since the counters were taken.
     """
-    path = os.path.join(ROOT, "profiles", "k_edge_%s.md" % workload)
+    kernel = PROFILED.get(workload, PROFILED["c2"])[0]
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -142,7 +153,7 @@ def traffic_from_profile(workload):
         if line.startswith("- ") and ":" in line:
             key, val = line[2:].split(":", 1)
             vals[key.strip()] = val.strip()
-    if vals.get("source_sha") != source_hash() or "hbm_bytes_per_launch" not in vals:
+    if vals.get("source_sha") != source_hash(workload) or "hbm_bytes_per_launch" not in vals:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
