@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, published
+I8_PEAK_TOPS = 5000.0            # MI355X dense int8 MFMA, published (no sparsity)
 # 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64
 # instruction per SIMD every 4 clocks); bitwise ops have no packed form.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -49,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="steps of the per-kernel event-timed loop (default: --steps)")
+    ap.add_argument("--edge-path", default="bitset", choices=("bitset", "mfma"),
+                    help="edge test of the single-graph path: witness search on bit rows, or int8 MFMA counts")
     ap.add_argument("--requests", type=int, default=2000,
                     help="c5: requests per phase (a bounded prefix of the 50k-request stream)")
     ap.add_argument("--copy-calibration", type=int, default=None, metavar="MIB",
@@ -478,6 +481,12 @@ def main():
     w = make_workload(args.workload, args.seed)
     print("workload %s ready" % args.workload, file=sys.stderr, flush=True)
     kz = Kernelizer(0)
+    mfma = args.edge_path == "mfma"
+    if mfma:
+        if w["fmt"] == "csr":
+            raise SystemExit("the MFMA edge path applies to dense and bit-row input")
+        from paper_2212_00574_amd.binding import KZ_EDGE_MFMA_I8
+        kz.set_edge_path(KZ_EDGE_MFMA_I8)
     colour = torch.from_numpy(w["colour"]).to(dev)
     k = w["k"]
     if w["fmt"] == "dense":
@@ -544,6 +553,24 @@ def main():
                     "traffic": traffic, "alg_bytes_per_launch": bytes_per_launch,
                     "bytes": "4 (deg u + deg v) per tested edge",
                     "avg_launch_ms": round(edge_avg_ms, 5), "launches_per_step": edge_launches / psteps}
+    elif mfma:
+        # int8 MFMA counts: every pair of two classes against every third
+        # class, 2 ops per multiply-accumulate, over the first (full) pass;
+        # later passes recount only tiles with a touched block
+        _, _, m_check = edge_work(w)
+        sizes = np.asarray(w["sizes"], np.float64)
+        n_all = sizes.sum()
+        full = 0.0
+        for a in range(len(sizes)):
+            for b in range(a + 1, len(sizes)):
+                full += 2.0 * sizes[a] * sizes[b] * (n_all - sizes[a] - sizes[b])
+        ops_per_launch = full * (1.0 if res["passes"] == 1 else 1.0 / launches)
+        achieved = ops_per_launch / (edge_avg_ms / 1e3) / 1e12
+        roofline = {"kernel": "k_mfma_count + k_edge epilogue", "bound": "mfma", "achieved": round(achieved, 2),
+                    "peak": I8_PEAK_TOPS, "unit": "TFLOP/s", "frac": round(achieved / I8_PEAK_TOPS, 4),
+                    "traffic": None, "ops": "int8 MFMA ops (2 per multiply-accumulate) of the full-pass count",
+                    "alg_ops_per_launch": ops_per_launch, "avg_launch_ms": round(edge_avg_ms, 5),
+                    "launches_per_step": edge_launches / psteps}
     else:
         op_bytes, ops, m_check = edge_work(w)
         # exact-worklist work over all passes: pass 1 tests every edge; later
@@ -596,6 +623,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "n": int(n), "k": int(k),
+                   "edge_path": args.edge_path,
                    "edges": int(res["input_edges"]), "rounds": res["rounds"], "passes": passes,
                    "surviving_vertices": res["surviving_vertices"], "surviving_edges": res["surviving_edges"],
                    "seed": args.seed, "parallelism": "single GPU"},

@@ -149,6 +149,22 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
                  void *ws, size_t ws_bytes, uint8_t *vmask, void *emask,
                  void *stream, kz_result *res);
 
+/* Edge-test implementation used by kz_kernelize for KZ_DENSE_U8 and
+ * KZ_BITSET_U64 input (CSR always uses its own):
+ *   KZ_EDGE_BITSET  (default) witness search on the bit rows: per third
+ *                   class, the first common neighbour ends the search;
+ *   KZ_EDGE_MFMA_I8 per-class common-neighbour counts of every pair of a
+ *                   tile as int8 x int8 -> int32 MFMA block contractions
+ *                   (exact), an edge failing where some third class counts
+ *                   zero; identical masks, rounds and counts.  Needs 8 bytes
+ *                   per vertex per row word more workspace (query
+ *                   kz_workspace_bytes after setting it) and row_words <=
+ *                   2048 (else KZ_ETOOLARGE).
+ * Applies to later calls on the context; KZ_EINVAL for another value. */
+#define KZ_EDGE_BITSET 0
+#define KZ_EDGE_MFMA_I8 1
+int kz_set_edge_path(kz_ctx *ctx, int32_t path);
+
 /* ------------------------------------------------------------ batches
  * Many small graphs kernelized together in one persistent launch (same
  * results as kz_kernelize on each graph alone).  Each graph is a job of

@@ -22,7 +22,8 @@ EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_
             "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
             "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
-            "kz_server_progress", "kz_server_poll", "kz_server_destroy")
+            "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_set_edge_path")
+KZ_EDGE_BITSET, KZ_EDGE_MFMA_I8 = 0, 1
 KZ_EAGAIN = -9
 KZ_ETOOLARGE = -10
 KERNELS = ("setup", "pack", "vertex", "edge", "apply", "unpack")
@@ -111,6 +112,8 @@ def _load() -> C.CDLL:
     lib.kz_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(kz_result)]
     lib.kz_server_destroy.restype = None
     lib.kz_server_destroy.argtypes = [vp]
+    lib.kz_set_edge_path.restype = C.c_int
+    lib.kz_set_edge_path.argtypes = [vp, C.c_int32]
     lib.kz_gen_bitset.restype = C.c_int
     lib.kz_gen_bitset.argtypes = [vp, C.c_int32, vp, C.c_double, C.c_uint32, C.c_uint32, vp, vp, C.c_int32, vp, vp]
     return lib
@@ -222,6 +225,12 @@ def kz_gen_bitset(ctx: int, sizes, p: float, seed: int, gid: int, planted, rows:
         raise KzError(st, "kz_gen_bitset")
 
 
+def kz_set_edge_path(ctx: int, path: int) -> None:
+    st = LIB.kz_set_edge_path(ctx, int(path))
+    if st != KZ_OK:
+        raise KzError(st, "kz_set_edge_path")
+
+
 def kz_server_fixed_bytes(max_slots: int) -> int:
     return int(LIB.kz_server_fixed_bytes(int(max_slots)))
 
@@ -323,6 +332,11 @@ class Kernelizer:
     def kernel_times(self) -> dict:
         """{kernel family: (total ms, launches)} since profiling was enabled."""
         return {name: kz_profile_read(self.ctx, i) for i, name in enumerate(KERNELS)}
+
+    def set_edge_path(self, path: int) -> None:
+        """KZ_EDGE_BITSET or KZ_EDGE_MFMA_I8 for later calls (workspace sizes are re-queried)."""
+        kz_set_edge_path(self.ctx, path)
+        self._need = {}
 
     def workspace(self, graph: kz_graph, k: int) -> torch.Tensor:
         key = (graph.format, graph.n, graph.row_words, graph.nnz, k)

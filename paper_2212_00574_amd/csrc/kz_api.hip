@@ -93,7 +93,7 @@ kzi::WsSizes plan_sizes_csr(const kz_graph *g, int32_t k) {
   return z;
 }
 
-kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k) {
+kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k, bool mfma) {
   if (g->format == KZ_CSR) return plan_sizes_csr(g, k);
   kzi::WsSizes z{};
   const long long n = g->n;
@@ -132,6 +132,7 @@ kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k) {
   z.off_tiles = take(sizeof(int2) * (size_t)z.Tmax);
   z.off_packed = take(dense ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
   z.off_spare = take(sizeof(uint64_t) * (size_t)n * (size_t)Rmax);
+  z.off_fb = take(mfma ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
   z.off_F = take(2 * sizeof(uint64_t) * (size_t)n * (size_t)k);
   z.total = o;
   return z;
@@ -341,6 +342,7 @@ int kz_create(kz_ctx **out, int device) {
   c->prof = false;
   c->batch_cfg_set = false;
   c->batch_cfg = kzi::BatchConfig{16, 4, 1, 0, 0};
+  c->edge_path = KZ_EDGE_BITSET;
   c->cus = 256;
   for (int i = 0; i < KZ_KERNEL_COUNT; ++i) {
     c->total_ms[i] = 0.0;
@@ -496,6 +498,12 @@ int kz_gen_bitset(kz_ctx *ctx, int32_t k, const int32_t *sizes, double p, uint32
   return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
 }
 
+int kz_set_edge_path(kz_ctx *ctx, int32_t path) {
+  if (!ctx || (path != KZ_EDGE_BITSET && path != KZ_EDGE_MFMA_I8)) return KZ_EINVAL;
+  ctx->edge_path = path;
+  return KZ_OK;
+}
+
 int kz_profile_enable(kz_ctx *ctx, int on) {
   if (!ctx) return KZ_EINVAL;
   ctx->prof = on != 0;
@@ -531,7 +539,7 @@ const char *kz_strerror(int status) {
 
 int kz_workspace_bytes(const kz_ctx *ctx, const kz_graph *g, int32_t k, size_t *bytes) {
   if (!ctx || !bytes || !shape_ok(g, k)) return KZ_EINVAL;
-  *bytes = plan_sizes(g, k).total;
+  *bytes = plan_sizes(g, k, ctx->edge_path == KZ_EDGE_MFMA_I8).total;
   return KZ_OK;
 }
 
@@ -556,7 +564,12 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
     r.equals_input = 1;
     return finish(res, r);
   }
-  const kzi::WsSizes z = plan_sizes(g, k);
+  const bool mfma = ctx->edge_path == KZ_EDGE_MFMA_I8 && !csr;
+  const kzi::WsSizes z = plan_sizes(g, k, mfma);
+  if (mfma && z.Rmax > kzi::kMfMaxWords) {
+    r.status = KZ_ETOOLARGE;
+    return finish(res, r);
+  }
   if (ws_bytes < z.total) {
     r.status = KZ_EWORKSPACE;
     return finish(res, r);
@@ -590,6 +603,7 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   p.packed = (uint64_t *)(base + z.off_packed);
   p.spare = (uint64_t *)(base + z.off_spare);
   p.F = (uint64_t *)(base + z.off_F);
+  p.fb = (uint64_t *)(base + z.off_fb);
   p.n = n;
   p.k = k;
   p.Rmax = z.Rmax;
@@ -629,7 +643,8 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
     }
     {
       ProfScope t(ctx, KZ_KERNEL_EDGE, s);
-      kzi::launch_edge_pass(p, src, first ? cur : scratch, pass, first, s);
+      if (mfma) kzi::launch_edge_pass_mfma(p, src, first ? cur : scratch, p.fb, pass, first, s);
+      else kzi::launch_edge_pass(p, src, first ? cur : scratch, pass, first, s);
     }
     if (!first) {
       ProfScope t(ctx, KZ_KERNEL_APPLY, s);

@@ -14,6 +14,8 @@ namespace kzi {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlk = 64;           // slots per block == bits per word
 constexpr int kEdgeThreads = 256;  // 4 waves per edge tile
+constexpr int kMfThreads = 256;    // MFMA count path: 4 waves per 128x128 group tile
+constexpr int kMfMaxWords = 2048;  // MFMA count path: row words it supports
 constexpr int kRankChunk = 256;    // vertices per stable-partition chunk
 constexpr int kPackLdsWords = 8192;  // dense pack: row assembled in LDS up to this many words
 constexpr int kSetupThreads = 1024;  // the single setup workgroup
@@ -60,6 +62,7 @@ struct Plan {
   uint64_t *spare;   // [n*Rmax] second state buffer
   uint64_t *F;       // [2*k*n] (F[2*(c*n+slot)], F[2*(c*n+slot)+1]): first two words of
                      // the slot's class-c segment (0 where the segment is shorter)
+  uint64_t *fb;      // [n*Rmax] MFMA count path: fail bits of the pairs of a pass
   int32_t *src;      // [nnz] csr: row of every entry
   uint8_t *efail;    // [nnz] csr: entry failed the edge test this pass
   uint64_t *pm;      // [n*KW] csr: classes holding an alive neighbour of each vertex
@@ -71,7 +74,7 @@ struct WsSizes {
   size_t total;
   size_t off_counts, off_coff, off_soff, off_bcls, off_bstart, off_blen, off_hist, off_perm,
       off_inv, off_scls, off_valive, off_touched0, off_touched1, off_bt0, off_bt1, off_tiles,
-      off_packed, off_spare, off_F, off_src, off_efail, off_pm;
+      off_packed, off_spare, off_F, off_fb, off_src, off_efail, off_pm;
   int Rmax, nchunks;
   long long Tmax;
 };
@@ -92,6 +95,10 @@ void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uin
                         bool first, hipStream_t s);
 void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first,
                       hipStream_t s);
+// The int8 MFMA count path of the edge test: fail bits of every pair (into
+// `fb`, n*Rmax words), then the shared tile epilogue.
+void launch_edge_pass_mfma(const Plan &p, const uint64_t *src, uint64_t *dst, uint64_t *fb, int pass, bool first,
+                           hipStream_t s);
 void launch_apply(const Plan &p, const uint64_t *scratch, uint64_t *cur, hipStream_t s);
 void launch_unpack_dense(const Plan &p, const int *colour, const uint64_t *cur, uint8_t *vmask,
                          uint8_t *emask, hipStream_t s);
@@ -200,6 +207,7 @@ struct kz_ctx {
   // batched path
   kzi::BatchConfig batch_cfg;
   bool batch_cfg_set;
-  int cus;  // compute units of the device
+  int cus;        // compute units of the device
+  int edge_path;  // KZ_EDGE_BITSET or KZ_EDGE_MFMA_I8
 };
 

@@ -409,9 +409,12 @@ __device__ __forceinline__ int third_class(int i, int cx, int cy) {
 // drop a lane.  When a bit of the tile changed, both copies of its new bits
 // go to `dst` (pass 1: the output state, which already holds a copy of the
 // input; later passes: scratch, and the tile is listed for the apply pass).
-template <bool FIRST, int CH>
+// MF: the witness search is replaced by the fail bits `fb` of the MFMA
+// count path (k_mfma_count), so both paths share this tile epilogue.
+template <bool FIRST, int CH, bool MF>
 __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *__restrict__ src,
-                                                       uint64_t *__restrict__ dst, int pass) {
+                                                       uint64_t *__restrict__ dst, int pass,
+                                                       const uint64_t *__restrict__ fb) {
   Hdr *h = p.hdr;
   if (stage1_bad(h)) return;
   const int R = h->R, k = p.k;
@@ -454,8 +457,17 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
   const unsigned long long TV = FIRST ? ~0ull : __ballot(lane < yl && p.touched[cur][ys + lane]);
   const ulonglong2 *F = (const ulonglong2 *)p.F;
 
-  const int nthird = k - 2;
+  const int nthird = MF ? 0 : k - 2;
   const int n = p.n;
+  if (MF) {
+    // pairs with a touched endpoint take the MFMA path's outcome; the others
+    // keep theirs
+    if (tid < xl) {
+      const unsigned long long Pt = ((TU >> tid) & 1ull) ? ~0ull : TV;
+      sP[tid] &= ~(fb[(long long)(xs + tid) * R + Y] & Pt);
+    }
+    __syncthreads();
+  }
   const int ur = tid & 63;                      // staging row of this thread
   const int urc = ur < xl ? ur : xl - 1;        // clamped into the block
   const int vrc = lane < yl ? lane : yl - 1;
@@ -620,6 +632,165 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
   if (lane == 0 && cnt) atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][2], (unsigned long long)cnt);
 }
 
+// ---------------------------------------------------------------- MFMA count path
+//
+// count_c(u, v) = sum over w in class c of A[u][w] * A[v][w]: the number of
+// common neighbours of u and v in class c, an int8 x int8 -> int32 block
+// contraction (exact: counts stay below 2^31).  An edge {u, v} fails when
+// some third class c has count_c(u, v) == 0 -- the same test as the witness
+// search, computed for every pair of a tile.  One workgroup takes a group
+// tile of two blocks by two blocks (up to 128 x 128 pairs of two classes);
+// for every word of every third class it expands the 64 bits of each of its
+// 256 rows to bytes in LDS (double-buffered) and each wave accumulates a
+// 64 x 64 quarter with 32x32x32 int8 MFMAs.  A class with a zero count marks
+// the pair in the fail bits `fb` (same layout as the rows; words of block Y
+// and Y+1 in the rows of blocks X and X+1); k_edge<.., true> turns them
+// into the next state with the usual worklist and counter epilogue.
+typedef int mf_v4i __attribute__((ext_vector_type(4)));
+typedef int mf_v16i __attribute__((ext_vector_type(16)));
+constexpr int kMfRows = 128;   // rows per side of a group tile
+constexpr int kMfPitch = 80;   // bytes per staged row: 64 + 16 of padding
+constexpr int kMfAhead = 8;    // words fetched ahead of their staging
+
+// bits 0..3 of x -> bytes 0..3 (0 or 1): the four shifted copies land on
+// distinct bit positions, so the product has no carries
+__device__ __forceinline__ int nib_bytes(unsigned x) { return (int)(((x & 0xFu) * 0x00204081u) & 0x01010101u); }
+
+template <bool FIRST>
+__global__ void __launch_bounds__(kMfThreads) k_mfma_count(Plan p, const uint64_t *__restrict__ src,
+                                                          uint64_t *__restrict__ fb, int pass) {
+  Hdr *h = p.hdr;
+  if (stage1_bad(h)) return;
+  const int R = h->R;
+  int X, Y;
+  tri_decode(xcd_remap(blockIdx.x, gridDim.x), p.Rmax, X, Y);
+  if (Y >= R) return;
+  const int cx = p.bcls[X], cy = p.bcls[Y];
+  if (cx == cy) return;
+  // group heads: the even-numbered blocks of each class
+  if (((X - p.soff[cx]) & 1) || ((Y - p.soff[cy]) & 1)) return;
+  const bool x2 = X + 1 < R && p.bcls[X + 1] == cx;
+  const bool y2 = Y + 1 < R && p.bcls[Y + 1] == cy;
+  const int cur = pass & 1;
+  if (!FIRST && !(p.btouched[cur][X] | (x2 && p.btouched[cur][X + 1]) | p.btouched[cur][Y] |
+                  (y2 && p.btouched[cur][Y + 1])))
+    return;
+  const int xs = p.bstart[X], ul = p.blen[X] + (x2 ? p.blen[X + 1] : 0);
+  const int ys = p.bstart[Y], vl = p.blen[Y] + (y2 ? p.blen[Y + 1] : 0);
+
+  __shared__ __attribute__((aligned(16))) signed char sA[2][kMfRows * kMfPitch];
+  __shared__ __attribute__((aligned(16))) signed char sB[2][kMfRows * kMfPitch];
+  __shared__ short sWord[kMfMaxWords];  // third-class words in order; bit 15: last word of its class
+  __shared__ int sN, sEmpty;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  if (tid == 0) {
+    int nw = 0, empty = 0;
+    for (int c = 0; c < p.k; ++c) {
+      if (c == cx || c == cy) continue;
+      const int w0 = p.soff[c], w1 = p.soff[c + 1];
+      if (w0 == w1) empty = 1;  // an empty third class: no pair has a common neighbour there
+      for (int w = w0; w < w1 && nw < kMfMaxWords; ++w) sWord[nw++] = (short)(w | (w == w1 - 1 ? 0x8000 : 0));
+    }
+    sN = nw;
+    sEmpty = empty;
+  }
+  __syncthreads();
+  const int nwords = sN;
+
+  // staging: thread t < 128 expands row t of the u side, t >= 128 row t-128 of the v side
+  const int sr = tid & (kMfRows - 1);
+  const bool sideB = tid >= kMfRows;
+  const int slen = sideB ? vl : ul;
+  const uint64_t *srow = src + (long long)((sideB ? ys : xs) + (sr < slen ? sr : 0)) * R;
+  auto stage = [&](int buf, unsigned long long word) {
+    mf_v4i *d = (mf_v4i *)((sideB ? sB[buf] : sA[buf]) + sr * kMfPitch);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const unsigned x = (unsigned)(word >> (16 * q));
+      mf_v4i v;
+      v.x = nib_bytes(x);
+      v.y = nib_bytes(x >> 4);
+      v.z = nib_bytes(x >> 8);
+      v.w = nib_bytes(x >> 12);
+      d[q] = v;
+    }
+  };
+  mf_v16i acc[2][2];
+  unsigned fail[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = mf_v16i{};
+      fail[i][j] = sEmpty ? 0xffffu : 0u;
+    }
+  // words are fetched kMfAhead iterations before they are staged, so the
+  // loads' latency hides behind that many words of MFMAs
+  auto fetch = [&](int t) -> unsigned long long {
+    return (t < nwords && sr < slen) ? srow[sWord[t] & 0x7fff] : 0ull;
+  };
+  unsigned long long ring[kMfAhead];  // ring[q]: the word staged at iteration t0 + q
+  if (nwords > 0) stage(0, fetch(0));
+#pragma unroll
+  for (int q = 0; q < kMfAhead; ++q) ring[q] = fetch(q + 1);
+  __syncthreads();
+  const int koff = (lane >> 5) * 16;
+  for (int t0 = 0; t0 < nwords; t0 += kMfAhead) {
+#pragma unroll
+    for (int q = 0; q < kMfAhead; ++q) {
+      const int t = t0 + q;
+      if (t < nwords) {
+        const int buf = t & 1;
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+          mf_v4i a[2], b[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            a[i] = *(const mf_v4i *)(sA[buf] + (64 * wr + 32 * i + (lane & 31)) * kMfPitch + st * 32 + koff);
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            b[j] = *(const mf_v4i *)(sB[buf] + (64 * wc + 32 * j + (lane & 31)) * kMfPitch + st * 32 + koff);
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (sWord[t] & 0x8000) {
+          // end of a third class: a zero count fails the pair
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+#pragma unroll
+              for (int e = 0; e < 16; ++e) fail[i][j] |= (acc[i][j][e] == 0 ? 1u : 0u) << e;
+              acc[i][j] = mf_v16i{};
+            }
+        }
+        if (t + 1 < nwords) stage(buf ^ 1, ring[q]);
+        ring[q] = fetch(t + 1 + kMfAhead);
+        __syncthreads();
+      }
+    }
+  }
+  // fail bits -> words: element e of lane l is pair (row 8*(e/4) + 4*(l/32) +
+  // e%4, column l%32) of a 32x32 quarter, so one ballot per (e, quarter)
+  // gives 32 columns of two rows
+  unsigned long long myword = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const unsigned long long b0 = __ballot((fail[i][0] >> e) & 1u), b1 = __ballot((fail[i][1] >> e) & 1u);
+      const int r0 = 32 * i + 8 * (e >> 2) + (e & 3);
+      if (lane == r0) myword = (b0 & 0xffffffffull) | (b1 << 32);
+      if (lane == r0 + 4) myword = (b0 >> 32) | ((b1 >> 32) << 32);
+    }
+  const int row = 64 * wr + lane;
+  if (row < ul && (wc == 0 || y2)) fb[(long long)(xs + row) * R + Y + wc] = myword;
+}
+
 // Copies the changed tiles of this pass from scratch into the state.
 __global__ void __launch_bounds__(128) k_apply(Plan p, const uint64_t *__restrict__ scratch,
                                                uint64_t *__restrict__ cur) {
@@ -704,16 +875,32 @@ void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pas
   // chunk of third classes: whichever of 6 and 8 pads the k-2 classes least
   const int nthird = p.k > 2 ? p.k - 2 : 0;
   const bool six = (nthird + 5) / 6 * 6 < (nthird + 7) / 8 * 8;
+  const uint64_t *nofb = nullptr;
   if (first) {
     if (six)
-      hipLaunchKernelGGL((k_edge<true, 6>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+      hipLaunchKernelGGL((k_edge<true, 6, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
     else
-      hipLaunchKernelGGL((k_edge<true, 8>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+      hipLaunchKernelGGL((k_edge<true, 8, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
   } else {
     if (six)
-      hipLaunchKernelGGL((k_edge<false, 6>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+      hipLaunchKernelGGL((k_edge<false, 6, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
     else
-      hipLaunchKernelGGL((k_edge<false, 8>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass);
+      hipLaunchKernelGGL((k_edge<false, 8, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
+  }
+}
+
+void launch_edge_pass_mfma(const Plan &p, const uint64_t *src, uint64_t *dst, uint64_t *fb, int pass, bool first,
+                           hipStream_t s) {
+  if (p.Tmax <= 0) return;
+  const dim3 grid((unsigned)p.Tmax);
+  if (first) {
+    hipLaunchKernelGGL((k_mfma_count<true>), grid, dim3(kMfThreads), 0, s, p, src, fb, pass);
+    hipLaunchKernelGGL((k_edge<true, 8, true>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass,
+                       (const uint64_t *)fb);
+  } else {
+    hipLaunchKernelGGL((k_mfma_count<false>), grid, dim3(kMfThreads), 0, s, p, src, fb, pass);
+    hipLaunchKernelGGL((k_edge<false, 8, true>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass,
+                       (const uint64_t *)fb);
   }
 }
 

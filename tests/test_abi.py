@@ -30,7 +30,7 @@ def test_header_declares_the_entry_points():
                           "kz_kernelize", "kz_kernelize_batch", "kz_profile_enable", "kz_profile_read",
                           "kz_server_create", "kz_server_destroy", "kz_server_fixed_bytes", "kz_server_poll",
                           "kz_server_progress", "kz_server_request_bytes", "kz_server_submit",
-                          "kz_strerror", "kz_workspace_bytes"]
+                          "kz_set_edge_path", "kz_strerror", "kz_workspace_bytes"]
 
 
 def test_every_declared_symbol_is_exported(lib):
