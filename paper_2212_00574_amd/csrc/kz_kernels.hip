@@ -532,6 +532,7 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
       }
       if (!(Pt & ~all)) continue;
       // level 2: the first two words (re-read from LDS; rare)
+      all = ~0ull;
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
         const ulonglong2 a = sU[j][u];
