@@ -236,17 +236,17 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
  * every admitted request that is waiting, and at most two launches are in
  * flight on the server's stream (one running, one queued behind it).
  * Requests of 4096 vertices or more (or beyond the batched path's k and
- * row-word limits) take a second lane instead: a worker
- * thread runs them one at a time through the single-graph path on a stream
- * of its own, overlapping the batch launches.  A request is a
+ * row-word limits) take a second lane instead: two worker threads, each
+ * with a stream of its own, run them through the single-graph path, one
+ * request each at a time, overlapping the batch launches.  A request is a
  * KZ_BITSET_U64 graph in caller-owned device buffers; results are the same
  * as kz_kernelize on the graph alone.  The server takes a fixed part of a
  * caller-provided device arena for its launch records and carves each
  * admitted request's scratch from the rest (first fit); it admits a request
  * only when a slot and its scratch are free, else KZ_EAGAIN.  It allocates
  * no device memory of its own; when it is created it allocates pinned host
- * memory for descriptors and results, a second context, a stream and the
- * worker thread.  A server belongs to one host thread (the worker is
+ * memory for descriptors and results, and per worker a context, a stream
+ * and a thread.  A server belongs to one host thread (the worker is
  * internal). */
 typedef struct kz_server kz_server;
 

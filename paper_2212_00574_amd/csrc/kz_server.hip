@@ -11,8 +11,8 @@
 // kz_server_progress retires launches whose event has fired.
 //
 // Requests with at least kSplitN vertices (or beyond the batched path's
-// class and row-word limits) go to a worker thread instead:
-// it runs them one at a time through the single-graph path (kz_kernelize,
+// class and row-word limits) go to kWorkers worker threads instead: each
+// runs them one at a time through the single-graph path (kz_kernelize,
 // whose multi-workgroup passes suit large graphs) on a stream of its own,
 // after waiting for an event recorded on the server's stream when the
 // request was admitted (so inputs written there first are complete).  Both
@@ -38,6 +38,7 @@ constexpr size_t kSrvAlign = 256;
 constexpr int kSrvMaxSlots = 4096;
 constexpr int kSrvMaxWorkgroups = 1024;
 constexpr int kSplitN = 4096;  // vertices from which a request takes the single-graph lane
+constexpr int kWorkers = 2;    // large requests in flight at once (each its own context and stream)
 
 size_t up(size_t x) { return (x + kSrvAlign - 1) / kSrvAlign * kSrvAlign; }
 
@@ -138,9 +139,9 @@ struct kz_server {
   uint64_t next_ticket;
   int admitted;  // requests admitted and not yet retired by a poll
   // single-graph lane
-  kz_ctx *wctx;  // the worker's context (its own readback buffer)
-  hipStream_t wstream;
-  std::thread worker;
+  kz_ctx *wctx[kWorkers];  // each worker's context (its own readback buffer)
+  hipStream_t wstream[kWorkers];
+  std::thread worker[kWorkers];
   std::mutex mu;  // reqs, heap, big, stop, admitted
   std::condition_variable cv;
   std::deque<uint64_t> big;
@@ -150,18 +151,19 @@ struct kz_server {
 namespace {
 
 void release(kz_server *s) {
-  if (s->worker.joinable()) {
-    {
-      std::lock_guard<std::mutex> g(s->mu);
-      s->stop = true;
-    }
-    s->cv.notify_all();
-    s->worker.join();
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
   }
+  s->cv.notify_all();
+  for (std::thread &w : s->worker)
+    if (w.joinable()) w.join();
   for (auto &kv : s->reqs)
     if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
-  if (s->wstream) (void)hipStreamDestroy(s->wstream);
-  if (s->wctx) kz_destroy(s->wctx);
+  for (int i = 0; i < kWorkers; ++i) {
+    if (s->wstream[i]) (void)hipStreamDestroy(s->wstream[i]);
+    if (s->wctx[i]) kz_destroy(s->wctx[i]);
+  }
   for (Record &r : s->rec) {
     if (r.done) (void)hipEventDestroy(r.done);
     if (r.graphs_host) (void)hipHostFree(r.graphs_host);
@@ -171,8 +173,10 @@ void release(kz_server *s) {
   delete s;
 }
 
-// The single-graph lane: one large request at a time.
-void work(kz_server *s) {
+// The single-graph lane: worker `id` runs one large request at a time.
+void work(kz_server *s, int id) {
+  kz_ctx *ctx = s->wctx[id];
+  hipStream_t stream = s->wstream[id];
   (void)hipSetDevice(s->ctx->device);
   for (;;) {
     uint64_t t = 0;
@@ -189,15 +193,15 @@ void work(kz_server *s) {
     }
     kz_result res{};
     res.status = KZ_EHIP;
-    if (hipStreamWaitEvent(s->wstream, q.ready, 0) == hipSuccess) {
+    if (hipStreamWaitEvent(stream, q.ready, 0) == hipSuccess) {
       kz_graph gr{};
       gr.format = KZ_BITSET_U64;
       gr.n = q.r.n;
       gr.rows = q.r.rows;
       gr.row_words = q.r.row_words;
-      (void)kz_kernelize(s->wctx, &gr, q.r.colour, q.r.k, s->arena + q.at, q.bytes, q.r.vmask, q.r.emask,
-                         s->wstream, &res);
-      if (hipStreamSynchronize(s->wstream) != hipSuccess) res.status = KZ_EHIP;
+      (void)kz_kernelize(ctx, &gr, q.r.colour, q.r.k, s->arena + q.at, q.bytes, q.r.vmask, q.r.emask, stream,
+                         &res);
+      if (hipStreamSynchronize(stream) != hipSuccess) res.status = KZ_EHIP;
     }
     std::lock_guard<std::mutex> g(s->mu);
     Req &r = s->reqs[t];
@@ -300,7 +304,7 @@ size_t kz_server_request_bytes(const kz_server *s, const kz_request *req) {
   if (!s || !req || req->n < 0 || req->k < 1 || req->row_words < 0) return 0;
   if (req->n < kSplitN && req->k <= kzi::kBatchK && req->row_words <= kzi::kBatchR) return batch_bytes(*req);
   size_t b = 0;
-  return single_bytes(s->wctx, *req, &b) == KZ_OK ? b : 0;
+  return single_bytes(s->wctx[0], *req, &b) == KZ_OK ? b : 0;
 }
 
 int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_slots, void *stream,
@@ -322,8 +326,10 @@ int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_s
   s->next_ticket = 1;
   s->admitted = 0;
   s->heap.init(2 * L.total, arena_bytes - 2 * L.total);
-  s->wctx = nullptr;
-  s->wstream = nullptr;
+  for (int i = 0; i < kWorkers; ++i) {
+    s->wctx[i] = nullptr;
+    s->wstream[i] = nullptr;
+  }
   s->stop = false;
   for (int i = 0; i < 2; ++i) {
     Record &r = s->rec[i];
@@ -350,11 +356,14 @@ int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_s
       return KZ_EHIP;
     }
   }
-  if (kz_create(&s->wctx, ctx->device) != KZ_OK || hipStreamCreate(&s->wstream) != hipSuccess) {
-    release(s);
-    return KZ_EHIP;
+  for (int i = 0; i < kWorkers; ++i) {
+    if (kz_create(&s->wctx[i], ctx->device) != KZ_OK || hipStreamCreate(&s->wstream[i]) != hipSuccess) {
+      release(s);
+      return KZ_EHIP;
+    }
+    s->wctx[i]->edge_path = ctx->edge_path;
   }
-  s->worker = std::thread(work, s);
+  for (int i = 0; i < kWorkers; ++i) s->worker[i] = std::thread(work, s, i);
   *out = s;
   return KZ_OK;
 }
@@ -366,7 +375,7 @@ int kz_server_submit(kz_server *s, const kz_request *req, uint64_t *ticket) {
     return KZ_EINVAL;
   const bool big = r.n >= kSplitN || r.k > kzi::kBatchK || r.row_words > kzi::kBatchR;
   size_t bytes = batch_bytes(r);
-  if (big && single_bytes(s->wctx, r, &bytes) != KZ_OK) return KZ_EINVAL;
+  if (big && single_bytes(s->wctx[0], r, &bytes) != KZ_OK) return KZ_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
   if (s->admitted >= s->slots) return KZ_EAGAIN;
   size_t at = 0;
