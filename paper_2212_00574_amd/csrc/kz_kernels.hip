@@ -108,14 +108,35 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
       s_bad_colour = 1;
       continue;
     }
+    if (bitset) {
+      // sorted colours: the class sizes come from binary searches below
+      if (u > 0 && colour[u - 1] > c) s_bad_layout = 1;
+      continue;
+    }
     if (lds_hist)
       atomicAdd(&sh[c], 1);
     else
       atomicAdd(&p.counts[c], 1);
-    if (dense)
-      atomicAdd(&p.hist[(long long)(u / kRankChunk) * k + c], 1);
-    else if (bitset && u > 0 && colour[u - 1] > c)
-      s_bad_layout = 1;
+    if (dense) atomicAdd(&p.hist[(long long)(u / kRankChunk) * k + c], 1);
+  }
+  if (bitset) {
+    // class c holds the vertices from the first colour >= c to the first
+    // colour >= c+1 (meaningful only when the colours are sorted; the
+    // layout check above flags them otherwise)
+    auto first_ge = [&](int c) {
+      int lo = 0, hi = n;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (colour[mid] < c) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    for (int c = t; c < k; c += kSetupThreads) {
+      const int cnt = first_ge(c + 1) - first_ge(c);
+      if (lds_hist) sh[c] = cnt;
+      else p.counts[c] = cnt;
+    }
   }
   __syncthreads();
   if (s_bad_colour) {
