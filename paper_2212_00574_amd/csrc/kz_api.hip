@@ -298,7 +298,13 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
     prof_collect(ctx);
     const kzi::Hdr &h = *ctx->pinned;
     if (first) {
-      const int st = map_hdr_status(h);
+      // unequal counts of entries above and below the diagonal: some
+      // entry below it has no reverse
+      unsigned long long balance = 0;
+      for (int slot = 0; slot < kzi::kCtrSlots; ++slot) balance += h.ctr[1][slot][3];
+      kzi::Hdr hs = h;
+      if (balance != 0 && hs.prio < kzi::P_EASYM) hs.prio = kzi::P_EASYM;
+      const int st = map_hdr_status(hs);
       if (st != KZ_OK) {
         r.status = st;
         return finish(res, r);

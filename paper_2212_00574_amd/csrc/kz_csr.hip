@@ -61,6 +61,7 @@ __global__ void __launch_bounds__(256) k_csr_validate(Plan p, const int64_t *rp,
     p.touched[0][u] = 0;
   }
   const int cu = colour[u];
+  int balance = 0;  // entries above the diagonal minus entries below it
   for (long long i = b + lane; i < e; i += kWave) {
     const int v = ci[i];
     p.src[i] = u;
@@ -74,7 +75,16 @@ __global__ void __launch_bounds__(256) k_csr_validate(Plan p, const int64_t *rp,
       pr = max(pr, P_ESELFLOOP);
       continue;
     }
-    // the reverse entry must exist: binary search for u in row v
+    // Symmetry: every entry (u,v) with v > u must have its reverse (v,u),
+    // found by binary search in row v; with as many entries below the
+    // diagonal as above it (summed on the host), reversal then maps the
+    // upper entries onto the lower ones, so the lower ones need no search.
+    // The same-class check likewise covers both directions from above.
+    if (v < u) {
+      --balance;
+      continue;
+    }
+    ++balance;
     long long vb, ve;
     bool found = false;
     if (row_ok(rp, v, nnz, vb, ve)) {
@@ -91,6 +101,9 @@ __global__ void __launch_bounds__(256) k_csr_validate(Plan p, const int64_t *rp,
     if (colour[v] == cu) pr = max(pr, P_EILLEGAL);
   }
   if (pr) atomicMax(&h->prio, pr);
+  balance = wave_sum_i(balance);
+  if (lane == 0 && balance)
+    atomicAdd(&h->ctr[1][blockIdx.x % kCtrSlots][3], (unsigned long long)(long long)balance);
 }
 
 // Vertex test and presence masks.  One wave per vertex, lanes over its

@@ -30,8 +30,10 @@ enum : int { P_NONE = 0, P_EILLEGAL = 1, P_EASYM = 2, P_ESELFLOOP = 3, P_EINVAL 
 // Device-resident header at the start of the workspace.
 struct Hdr {
   // per pass parity and slot: removed vertices, removed edges, edge tests,
-  // spare.  Workgroups add into slot (id % kCtrSlots) so that thousands of
-  // same-address atomics do not serialise; the host sums the slots.
+  // and a fourth counter that only the CSR validation uses (ctr[1][*][3]:
+  // entries above minus entries below the diagonal, read with pass 1's
+  // counters).  Workgroups add into slot (id % kCtrSlots) so that thousands
+  // of same-address atomics do not serialise; the host sums the slots.
   unsigned long long ctr[2][kCtrSlots][4];
   int tile_count;        // changed tiles appended by the edge pass
   int prio;              // stage-2 status priority

@@ -266,6 +266,32 @@ def test_csr_validation(kz):
     assert status_of(kz, lambda: run_csr(kz, rp, ci, colour, 2000, "k")) == -1
 
 
+def test_csr_asymmetry_in_long_rows(kz):
+    """One reverse entry missing from a long row (about 400 entries), at its
+    start, middle and end and just outside a 16-entry window around the
+    position interpolated from the row's first and last ids: each placement
+    is caught and the symmetric graph passes."""
+    g = inputs.make_graph([300, 300, 300], 0.7, seed=8, gid=2)
+    adj, colour = g.dense()
+    rp, ci = inputs.dense_to_csr(adj)
+    k = 3
+    ok = kernelize_csr(rp, ci, colour, k)
+    res, vm, em = run_csr(kz, rp, ci, colour, k, "long-sym")
+    check_same(res, ok, vm, em, "long-sym")
+    v = int(np.argmax(np.diff(rp)))
+    row = ci[rp[v]:rp[v + 1]]
+    d = len(row)
+    assert d > 300
+    for pos in sorted({0, 1, 9, 20, d // 3, d // 2, d - 21, d - 10, d - 2, d - 1}):
+        u = int(row[pos])
+        a = adj.copy()
+        a[v, u] = 0                            # u -> v stays, v -> u goes
+        r, c = inputs.dense_to_csr(a)
+        want = kernelize_csr(r, c, colour, k)["status"]
+        got = status_of(kz, lambda: run_csr(kz, r, c, colour, k, "asym@%d" % pos))
+        assert want != 0 and got == want, (pos, got, want)
+
+
 def test_csr_sparse_generator_graphs(kz):
     """Uneven classes and uniform sparse pairs (the large sparse workload's shape, scaled down)."""
     for seed, (n, k, m) in enumerate([(3000, 8, 9000), (5000, 30, 125000), (2000, 5, 30000)]):
