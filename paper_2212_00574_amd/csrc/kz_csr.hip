@@ -37,8 +37,9 @@ __device__ __forceinline__ bool row_ok(const int64_t *rp, int u, long long nnz, 
   return b >= 0 && b <= e && e <= nnz;
 }
 
-// Structure and stage-2 checks, one wave per row; also records the row of
-// every entry and starts the state (everything alive, everything touched).
+// Colour range (stage 1), structure and stage-2 checks, one wave per row;
+// also records the row of every entry and starts the state (everything
+// alive, everything touched).
 __global__ void __launch_bounds__(256) k_csr_validate(Plan p, const int64_t *rp, const int32_t *ci,
                                                       long long nnz, const int *colour, uint8_t *vmask,
                                                       uint8_t *emask) {
@@ -47,6 +48,9 @@ __global__ void __launch_bounds__(256) k_csr_validate(Plan p, const int64_t *rp,
   const int u = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int n = p.n;
   if (u >= n) return;
+  // stage 1: every colour in [0,k)
+  const int cu = colour[u];
+  if (lane == 0 && (cu < 0 || cu >= p.k)) h->bad_colour = 1;
   int pr = P_NONE;
   if (u == 0 && lane == 0 && rp[0] != 0) pr = P_EINVAL;
   if (u == n - 1 && lane == 0 && rp[n] != nnz) pr = P_EINVAL;
@@ -60,7 +64,6 @@ __global__ void __launch_bounds__(256) k_csr_validate(Plan p, const int64_t *rp,
     p.touched[1][u] = 1;
     p.touched[0][u] = 0;
   }
-  const int cu = colour[u];
   int balance = 0;  // entries above the diagonal minus entries below it
   for (long long i = b + lane; i < e; i += kWave) {
     const int v = ci[i];

@@ -69,7 +69,7 @@ __device__ __forceinline__ void tri_decode(long long t, int NB, int &X, int &Y) 
 // One workgroup: zeroes the header, counts the classes (stage-1 colour
 // checks), scans class and segment offsets and fills the block table.  For
 // dense input it also builds per-chunk class histograms for the stable
-// partition; for CSR input only the header and the colour checks matter.
+// partition; for CSR input it only zeroes the header.
 __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colour, int row_words,
                                                          int mode) {
   const bool dense = mode == SETUP_DENSE, bitset = mode == SETUP_BITSET;
@@ -93,6 +93,8 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
     carry_b = 0;
   }
   for (int i = t; i < 2 * kCtrSlots * 4; i += kSetupThreads) (&h->ctr[0][0][0])[i] = 0;
+  // CSR kernels use no class table; their validation checks the colours
+  if (mode == SETUP_CSR) return;
   for (int c = t; c < k; c += kSetupThreads) {
     if (lds_hist)
       sh[c] = 0;
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
     h->R = R;
   }
   __syncthreads();
-  if (s_bad_layout || mode == SETUP_CSR) return;
+  if (s_bad_layout) return;
   // each thread reads back only the entries it wrote itself above
   for (int c = t; c < k; c += kSetupThreads) {
     const int s = p.counts[c];

@@ -262,6 +262,16 @@ def test_csr_validation(kz):
         want = kernelize_csr(r, c, colour, 3)["status"]
         got = status_of(kz, lambda: run_csr(kz, r, c, colour, 3, name))
         assert want != 0 and got == want, (name, got, want)
+    # colours outside [0,k): alone, on a row whose bounds are also broken,
+    # and beside an asymmetric pair; the colour error takes precedence
+    bad_rp = rp.copy(); bad_rp[5] = bad_rp[6] + 1
+    a = adj.copy(); other = int(np.nonzero(colour != colour[0])[0][0]); a[0, other] ^= 1
+    for name, (r, c, at) in {"colour": (rp, ci, len(colour) - 1), "colour+rowptr": (bad_rp, ci, 5),
+                             "colour+asym": inputs.dense_to_csr(a) + (40,)}.items():
+        col = colour.copy(); col[at] = 3 if at % 2 else -1
+        want = kernelize_csr(r, c, col, 3)["status"]
+        got = status_of(kz, lambda: run_csr(kz, r, c, col, 3, name))
+        assert want != 0 and got == want, (name, got, want)
     # k above the CSR limit is rejected on the host
     assert status_of(kz, lambda: run_csr(kz, rp, ci, colour, 2000, "k")) == -1
 
