@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
   Hdr *h = p.hdr;
   const int t = threadIdx.x, n = p.n, k = p.k;
   __shared__ int sh[kSetupLdsClasses];
+  __shared__ int sst[kSetupLdsClasses + 1];  // bit-row input: first vertex of each class
   __shared__ int sa[kSetupThreads / kWave], sb[kSetupThreads / kWave];
   __shared__ int s_bad_colour, s_bad_layout, carry_a, carry_b;
   const bool lds_hist = k <= kSetupLdsClasses;
@@ -103,6 +104,8 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
   }
   if (dense)
     for (long long i = t; i < (long long)p.nchunks * k; i += kSetupThreads) p.hist[i] = 0;
+  if (bitset && lds_hist)
+    for (int c = t; c <= k; c += kSetupThreads) sst[c] = 0;
   __syncthreads();
   for (int u = t; u < n; u += kSetupThreads) {
     const int c = colour[u];
@@ -111,8 +114,16 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
       continue;
     }
     if (bitset) {
-      // sorted colours: the class sizes come from binary searches below
-      if (u > 0 && colour[u - 1] > c) s_bad_layout = 1;
+      // sorted colours: u is the first vertex of every class in
+      // (colour[u-1], c], and the last vertex ends the classes above its own
+      const int prev = u > 0 ? colour[u - 1] : -1;
+      if (prev > c) {
+        s_bad_layout = 1;
+      } else if (lds_hist) {
+        for (int x = max(prev + 1, 0); x <= c; ++x) sst[x] = u;
+        if (u == n - 1)
+          for (int x = c + 1; x <= k; ++x) sst[x] = n;
+      }
       continue;
     }
     if (lds_hist)
@@ -121,10 +132,14 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
       atomicAdd(&p.counts[c], 1);
     if (dense) atomicAdd(&p.hist[(long long)(u / kRankChunk) * k + c], 1);
   }
-  if (bitset) {
+  if (bitset && lds_hist) {
+    // class sizes from the class starts (meaningful only when the colours
+    // are sorted; the layout check above flags them otherwise)
+    __syncthreads();
+    for (int c = t; c < k; c += kSetupThreads) sh[c] = sst[c + 1] - sst[c];
+  } else if (bitset) {
     // class c holds the vertices from the first colour >= c to the first
-    // colour >= c+1 (meaningful only when the colours are sorted; the
-    // layout check above flags them otherwise)
+    // colour >= c+1
     auto first_ge = [&](int c) {
       int lo = 0, hi = n;
       while (lo < hi) {
