@@ -355,57 +355,78 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
     const int cv = scls[vc];
     bool fail = false;
     int pr = P_NONE;
-    for (int c = wid; c < k; c += 4) {
-      const int w0 = lds_off ? sOff[1][c] : p.soff[c];
-      const int w1 = lds_off ? sOff[1][c + 1] : p.soff[c + 1];
-      ulonglong2 *Fcv = (ulonglong2 *)p.F + ((long long)c * n + v);
-      if (w1 == w0) {  // empty class: no neighbour possible
-        if (active) *Fcv = make_ulonglong2(0ull, 0ull);
-        fail |= c != cv;
-        continue;
+    // the wave's classes c = wid, wid+4, ... in groups of kVG: all loads of
+    // a group go out before any of them is used
+    constexpr int kVG = 4;
+    for (int cg = wid; cg < k; cg += 4 * kVG) {
+      unsigned long long x0[kVG], x1[kVG], xe[kVG];
+#pragma unroll
+      for (int g = 0; g < kVG; ++g) {
+        const int c = cg + 4 * g;
+        const int w0 = c < k ? (lds_off ? sOff[1][c] : p.soff[c]) : 0;
+        const int w1 = c < k ? (lds_off ? sOff[1][c + 1] : p.soff[c + 1]) : 0;
+        x0[g] = w1 > w0 ? row[w0] : 0ull;
+        x1[g] = w1 - w0 >= 2 ? row[w0 + 1] : 0ull;
+        xe[g] = FIRST && w1 - w0 >= 3 ? row[w1 - 1] : 0ull;  // last word (pass 1 checks its padding)
       }
-      const unsigned long long x = row[w0];
-      const unsigned long long x1 = w1 - w0 >= 2 ? row[w0 + 1] : 0ull;
-      if (active) *Fcv = make_ulonglong2(x, x1);
-      const int cc0 = lds_off ? sOff[0][c] : p.coff[c];
-      const int s = (lds_off ? sOff[0][c + 1] : p.coff[c + 1]) - cc0;
-      if (c == cv) {
-        if (FIRST && active) {
-          // own segment: must be empty in the input; classify what is there
-          const int jv = v - cc0;
-          for (int w = w0; w < w1; ++w) {
-            unsigned long long y = w == w0 ? x : row[w];
-            if (w == w1 - 1 && (s & 63)) {
-              if (y >> (s & 63)) pr = max(pr, P_EINVAL);
-              y &= (1ull << (s & 63)) - 1;
-            }
-            while (y) {
-              const int b = __builtin_ctzll(y);
-              y &= y - 1;
-              const int tslot = cc0 + (w - w0) * 64 + b;
-              if (tslot == v) {
-                pr = max(pr, P_ESELFLOOP);
-              } else {
-                const uint64_t z = src[(long long)tslot * R + w0 + (jv >> 6)];
-                pr = max(pr, ((z >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL : (int)P_EASYM);
+#pragma unroll
+      for (int g = 0; g < kVG; ++g) {
+        const int c = cg + 4 * g;
+        if (c >= k) break;
+        const int w0 = lds_off ? sOff[1][c] : p.soff[c];
+        const int w1 = lds_off ? sOff[1][c + 1] : p.soff[c + 1];
+        ulonglong2 *Fcv = (ulonglong2 *)p.F + ((long long)c * n + v);
+        if (w1 == w0) {  // empty class: no neighbour possible
+          if (active) *Fcv = make_ulonglong2(0ull, 0ull);
+          fail |= c != cv;
+          continue;
+        }
+        const unsigned long long x = x0[g];
+        if (active) *Fcv = make_ulonglong2(x, x1[g]);
+        const int cc0 = lds_off ? sOff[0][c] : p.coff[c];
+        const int s = (lds_off ? sOff[0][c + 1] : p.coff[c + 1]) - cc0;
+        const unsigned long long last = w1 - w0 >= 3 ? xe[g] : (w1 - w0 == 2 ? x1[g] : x);
+        if (c == cv) {
+          if (FIRST && active) {
+            // own segment: must be empty in the input, padding included
+            unsigned long long any = x | x1[g] | last;
+#pragma unroll 4
+            for (int w = w0 + 2; w < w1 - 1; ++w) any |= row[w];
+            if (any) {
+              // classify what is there
+              const int jv = v - cc0;
+              for (int w = w0; w < w1; ++w) {
+                unsigned long long y = row[w];
+                if (w == w1 - 1 && (s & 63)) {
+                  if (y >> (s & 63)) pr = max(pr, P_EINVAL);
+                  y &= (1ull << (s & 63)) - 1;
+                }
+                while (y) {
+                  const int b = __builtin_ctzll(y);
+                  y &= y - 1;
+                  const int tslot = cc0 + (w - w0) * 64 + b;
+                  if (tslot == v) {
+                    pr = max(pr, P_ESELFLOOP);
+                  } else {
+                    const uint64_t z = src[(long long)tslot * R + w0 + (jv >> 6)];
+                    pr = max(pr, ((z >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL : (int)P_EASYM);
+                  }
+                }
               }
             }
           }
+          continue;
         }
-        continue;
+        if (FIRST && active && (s & 63) && (last >> (s & 63))) pr = max(pr, P_EINVAL);
+        bool nz = (x | x1[g]) != 0;
+        if (active && !nz)
+          for (int w = w0 + 2; w < w1; ++w)
+            if (row[w]) {
+              nz = true;
+              break;
+            }
+        fail |= !nz;
       }
-      if (FIRST && active && (s & 63)) {
-        const unsigned long long last = w1 - 1 == w0 ? x : row[w1 - 1];
-        if (last >> (s & 63)) pr = max(pr, P_EINVAL);
-      }
-      bool nz = (x | x1) != 0;
-      if (active && !nz)
-        for (int w = w0 + 2; w < w1; ++w)
-          if (row[w]) {
-            nz = true;
-            break;
-          }
-      fail |= !nz;
     }
     if (pr) atomicMax(&h->prio, pr);
     if (fail && active) atomicOr(&sFail[lane], 1);
@@ -454,15 +475,18 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
                                                        uint64_t *__restrict__ dst, int pass,
                                                        const uint64_t *__restrict__ fb) {
   Hdr *h = p.hdr;
-  if (stage1_bad(h)) return;
-  const int R = h->R, k = p.k;
+  const int k = p.k;
+  const int cur = pass & 1, nxt = cur ^ 1;
   int X, Y;
   tri_decode(xcd_remap(blockIdx.x, gridDim.x), p.Rmax, X, Y);
-  if (Y >= R) return;
+  // one round of independent loads (X, Y < Rmax: the block table is in
+  // bounds even where this call's layout is shorter or invalid)
+  const int bad = h->bad_colour | h->bad_layout, R = h->R;
   const int cx = p.bcls[X], cy = p.bcls[Y];
-  if (cx == cy) return;
-  const int cur = pass & 1, nxt = cur ^ 1;
-  if (!FIRST && !(p.btouched[cur][X] | p.btouched[cur][Y])) return;
+  const int xs = p.bstart[X], xl = p.blen[X];
+  const int ys = p.bstart[Y], yl = p.blen[Y];
+  const bool btouch = FIRST || (p.btouched[cur][X] | p.btouched[cur][Y]);
+  if (bad || Y >= R || cx == cy || !btouch) return;
 
   constexpr int kWaves = kEdgeThreads / kWave;
   constexpr int kRowsPerWave = kBlk / kWaves;
@@ -471,89 +495,93 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
   __shared__ unsigned long long sV2[CH][kBlk];
   __shared__ unsigned long long sE[kBlk], sP[kBlk];
   __shared__ unsigned long long sT[kWaves][kBlk], sTE[kWaves][kBlk];
-  __shared__ int sW[CH][2];
-  __shared__ int sC[CH];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int xs = p.bstart[X], xl = p.blen[X];
-  const int ys = p.bstart[Y], yl = p.blen[Y];
   const unsigned long long ymask = yl == 64 ? ~0ull : ((1ull << yl) - 1);
   const unsigned long long xmask = xl == 64 ? ~0ull : ((1ull << xl) - 1);
-
-  if (tid < kBlk) {
-    // row index clamped into the block so the load is always in bounds
-    const unsigned long long e = src[(long long)(xs + (tid < xl ? tid : 0)) * R + Y];
-    sE[tid] = tid < xl ? e : 0ull;
-    sP[tid] = tid < xl ? (e & ymask) : 0ull;
-  }
-  __syncthreads();  // sE/sP are read by every wave, also when there is no third class
-  const uint64_t *rowv = src + (long long)(ys + (lane < yl ? lane : 0)) * R;
-  // pairs to re-test: those with a touched endpoint (all of them in pass 1);
-  // the others keep their outcome, so masks and rounds equal full sweeps
-  const unsigned long long TU = FIRST ? ~0ull : __ballot(lane < xl && p.touched[cur][xs + lane]);
-  const unsigned long long TV = FIRST ? ~0ull : __ballot(lane < yl && p.touched[cur][ys + lane]);
-  const ulonglong2 *F = (const ulonglong2 *)p.F;
-
   const int nthird = MF ? 0 : k - 2;
   const int n = p.n;
-  if (MF) {
-    // pairs with a touched endpoint take the MFMA path's outcome; the others
-    // keep theirs
-    if (tid < xl) {
-      const unsigned long long Pt = ((TU >> tid) & 1ull) ? ~0ull : TV;
-      sP[tid] &= ~(fb[(long long)(xs + tid) * R + Y] & Pt);
-    }
-    __syncthreads();
-  }
+  const ulonglong2 *F = (const ulonglong2 *)p.F;
   const int ur = tid & 63;                      // staging row of this thread
   const int urc = ur < xl ? ur : xl - 1;        // clamped into the block
   const int vrc = lane < yl ? lane : yl - 1;
-  for (int q = 0; q < nthird; q += CH) {
-    if (tid < CH) {
-      const int i = q + tid;
-      if (i < nthird) {
-        const int c = third_class(i, cx, cy);
-        sW[tid][0] = p.soff[c];
-        sW[tid][1] = p.soff[c + 1];
-        sC[tid] = c;
-      } else {
-        sW[tid][0] = -1;  // padding slot
-        sW[tid][1] = -1;
-        sC[tid] = 0;
-      }
-    }
-    __syncthreads();
-    // coalesced 16-byte loads from the first-word matrix, then the LDS writes;
-    // the lane keeps only the first words of its own row v in registers
-    unsigned long long vv[CH];
-    ulonglong2 uu[kStage];
+  const uint64_t *rowv = src + (long long)(ys + vrc) * R;
+
+  // Staging of one chunk of CH third classes from the first-word matrix:
+  // `issue` loads (the third classes follow from cx and cy alone, so these
+  // loads go out together with the tile's own), `stage` writes row u's two
+  // first words to LDS (read as broadcasts) and keeps row v's first word in
+  // the lane's registers.  Padding slots of the last chunk hold all-ones.
+  // Row v's second words go to LDS too, class j by wave j % kWaves.
+  constexpr int kV2 = (CH + kWaves - 1) / kWaves;
+  ulonglong2 uu[kStage];
+  unsigned long long vv[CH], vy[kV2];
+  auto issue = [&](int q) {
 #pragma unroll
     for (int e2 = 0; e2 < kStage; ++e2) {
       const int e = tid + e2 * kEdgeThreads;
-      const int j = e < CH * kBlk ? e >> 6 : 0;
-      uu[e2] = F[(long long)sC[j] * n + xs + urc];
-    }
-    if (wid == 0) {
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        const ulonglong2 f = F[(long long)sC[j] * n + ys + vrc];
-        sV2[j][lane] = sW[j][0] < 0 ? ~0ull : (lane < yl ? f.y : 0ull);
-      }
+      const int i = q + (e < CH * kBlk ? e >> 6 : 0);
+      const int c = i < nthird ? third_class(i, cx, cy) : 0;
+      uu[e2] = F[(long long)c * n + xs + urc];
     }
 #pragma unroll
-    for (int j = 0; j < CH; ++j) vv[j] = F[(long long)sC[j] * n + ys + vrc].x;
+    for (int j = 0; j < CH; ++j) {
+      const int c = q + j < nthird ? third_class(q + j, cx, cy) : 0;
+      vv[j] = F[(long long)c * n + ys + vrc].x;
+    }
+#pragma unroll
+    for (int jj = 0; jj < kV2; ++jj) {
+      const int j = wid + jj * kWaves;
+      const int c = j < CH && q + j < nthird ? third_class(q + j, cx, cy) : 0;
+      vy[jj] = F[(long long)c * n + ys + vrc].y;
+    }
+  };
+  auto stage = [&](int q) {
 #pragma unroll
     for (int e2 = 0; e2 < kStage; ++e2) {
       const int e = tid + e2 * kEdgeThreads;
       if (e < CH * kBlk) {
         const int j = e >> 6;
-        sU[j][ur] = sW[j][0] < 0 ? make_ulonglong2(~0ull, ~0ull) : uu[e2];
+        sU[j][ur] = q + j < nthird ? uu[e2] : make_ulonglong2(~0ull, ~0ull);
       }
     }
 #pragma unroll
-    for (int j = 0; j < CH; ++j) vv[j] = sW[j][0] < 0 ? ~0ull : (lane < yl ? vv[j] : 0ull);
-    __syncthreads();
+    for (int jj = 0; jj < kV2; ++jj) {
+      const int j = wid + jj * kWaves;
+      if (j < CH) sV2[j][lane] = q + j < nthird ? (lane < yl ? vy[jj] : 0ull) : ~0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) vv[j] = q + j < nthird ? (lane < yl ? vv[j] : 0ull) : ~0ull;
+  };
+
+  // row index clamped into the block so the load is always in bounds
+  const unsigned long long e0 = tid < kBlk ? src[(long long)(xs + urc) * R + Y] : 0ull;
+  if (nthird > 0) issue(0);
+  const unsigned long long ET = lane < yl ? rowv[X] : 0ull;  // used by the transpose
+  // pairs to re-test: those with a touched endpoint (all of them in pass 1);
+  // the others keep their outcome, so masks and rounds equal full sweeps
+  const unsigned long long TU = FIRST ? ~0ull : __ballot(lane < xl && p.touched[cur][xs + lane]);
+  const unsigned long long TV = FIRST ? ~0ull : __ballot(lane < yl && p.touched[cur][ys + lane]);
+  if (tid < kBlk) {
+    sE[tid] = tid < xl ? e0 : 0ull;
+    sP[tid] = tid < xl ? (e0 & ymask) : 0ull;
+  }
+  if (MF) {
+    // pairs with a touched endpoint take the MFMA path's outcome; the others
+    // keep theirs (each thread updates the word it wrote itself)
+    if (tid < xl) {
+      const unsigned long long Pt = ((TU >> tid) & 1ull) ? ~0ull : TV;
+      sP[tid] &= ~(fb[(long long)(xs + tid) * R + Y] & Pt);
+    }
+  }
+  for (int q = 0; q < nthird; q += CH) {
+    if (q > 0) {
+      issue(q);
+      __syncthreads();  // every wave is done with the previous chunk
+    }
+    stage(q);
+    __syncthreads();    // also publishes sE / sP before the first chunk
     for (int ui = 0; ui < kRowsPerWave; ++ui) {
       const int u = wid * kRowsPerWave + ui;
       if (u >= xl) break;
@@ -581,10 +609,12 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
       const uint64_t *rowu = src + (long long)(xs + u) * R;
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
+        if (q + j >= nthird) break;
         const ulonglong2 a = sU[j][u];
         unsigned long long miss = Pt & ~__ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
-        const int w1 = sW[j][1];
-        for (int w = sW[j][0] + 2; w < w1 && miss; ++w) {
+        const int c = third_class(q + j, cx, cy);
+        const int w1 = p.soff[c + 1];
+        for (int w = p.soff[c] + 2; w < w1 && miss; ++w) {
           const unsigned long long x = rowu[w];
           const unsigned long long y = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
           miss &= ~__ballot((x & y) != 0ull);
@@ -593,14 +623,13 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
       }
       if (lane == 0) sP[u] = P;
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // transpose: lane v gathers bit v of P(u) (and, in pass 1, of E(u)) for
   // this wave's rows u.  A wave whose rows all kept their edges contributes
   // its slice of ET instead (by symmetry, which pass 1 verifies).
   const int v = lane;
-  const unsigned long long ET = v < yl ? rowv[X] : 0ull;
   const unsigned long long wrows = (kRowsPerWave == 64 ? ~0ull : ((1ull << kRowsPerWave) - 1)) << (wid * kRowsPerWave);
   bool wchanged = false;
 #pragma unroll
@@ -915,17 +944,15 @@ void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pas
   const int nthird = p.k > 2 ? p.k - 2 : 0;
   const bool six = (nthird + 5) / 6 * 6 < (nthird + 7) / 8 * 8;
   const uint64_t *nofb = nullptr;
+#define KZ_EDGE(F, C) hipLaunchKernelGGL((k_edge<F, C, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb)
   if (first) {
-    if (six)
-      hipLaunchKernelGGL((k_edge<true, 6, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
-    else
-      hipLaunchKernelGGL((k_edge<true, 8, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
+    if (six) KZ_EDGE(true, 6);
+    else KZ_EDGE(true, 8);
   } else {
-    if (six)
-      hipLaunchKernelGGL((k_edge<false, 6, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
-    else
-      hipLaunchKernelGGL((k_edge<false, 8, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb);
+    if (six) KZ_EDGE(false, 6);
+    else KZ_EDGE(false, 8);
   }
+#undef KZ_EDGE
 }
 
 void launch_edge_pass_mfma(const Plan &p, const uint64_t *src, uint64_t *dst, uint64_t *fb, int pass, bool first,
