@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-one-by-one", action="store_true",
+                    help="c4: skip the one-graph-at-a-time comparison (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="steps of the per-kernel event-timed loop (default: --steps)")
@@ -140,12 +142,11 @@ def source_hash(workload="c2"):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload):
-    """HBM bytes per launch of the workload's roofline kernel, from the
-    committed counter summary profiles/<kernel>_<workload>.md ("-
-    hbm_bytes_per_launch: B" and "- source_sha: S"); None when absent or when
-    the kernel's sources changed since the counters were taken.
-    """
+def profile_value(workload, key):
+    """A figure ("- key: value") of the committed counter summary
+    profiles/<kernel>_<workload>.md of the workload's roofline kernel; None
+    when absent or when the kernel's sources changed since the counters were
+    taken ("- source_sha: S")."""
     kernel = PROFILED.get(workload, PROFILED["c2"])[0]
     path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
     if not os.path.exists(path):
@@ -154,14 +155,31 @@ def traffic_from_profile(workload):
     for line in open(path):
         line = line.strip()
         if line.startswith("- ") and ":" in line:
-            key, val = line[2:].split(":", 1)
-            vals[key.strip()] = val.strip()
-    if vals.get("source_sha") != source_hash(workload) or "hbm_bytes_per_launch" not in vals:
+            k, val = line[2:].split(":", 1)
+            vals[k.strip()] = val.strip()
+    if vals.get("source_sha") != source_hash(workload) or key not in vals:
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except ValueError:
         return None
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per launch of the workload's roofline kernel (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's readings)."""
+    return profile_value(workload, "hbm_bytes_per_launch")
+
+
+# What the full-segment models leave out (the ops and bytes that the
+# roofline's "achieved" counts are fixed per test, whatever a kernel does).
+ALU_MODEL_NOTE = ("achieved/frac count the full-segment test's ops (AND + OR per word of both rows in every third "
+                  "class); the witness search stops at the first word with a common neighbour, so it issues fewer "
+                  "ops than the model and frac can pass 1. valu_issue_frac is the VALU lane-ops the kernel actually "
+                  "issued (SQ_INSTS_VALU x 64 per launch, committed counter summary) over the same peak.")
+CSR_MODEL_NOTE = ("achieved/frac count both rows' int32 entries for every tested edge; the rows of a 100000-vertex "
+                  "graph are re-read from L2 and the Infinity Cache, so this stream can pass the HBM peak. traffic "
+                  "is the counter-measured HBM bytes per launch; the kernel is bound by gather latency, not HBM.")
 
 
 def cpu_baseline(w):
@@ -240,25 +258,27 @@ def bench_batch(args):
     kernel_ms = e0.elapsed_time(e1) / args.steps
     G = b.G
     value = G / (ms_per_step / 1e3)
-    # one graph at a time through the single-graph path, same device-resident inputs
-    views = []
-    for i in range(G):
-        d = b.desc[i]
-        n, R = int(d["n"]), int(d["row_words"])
-        a, o = int(d["row_offset"]), int(d["vertex_offset"])
-        rows_v = b.rows[a:a + n * R].view(n, R)
-        views.append((graph_bitset(rows_v), b.colour[o:o + n], int(d["k"]), b.vmask[o:o + n],
-                      b.emask[a:a + n * R].view(n, R)))
-    for gr, col, k, vm, em in views[:8]:
-        kz.run(gr, col, k, vm, em)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    single = [kz.run(gr, col, k, vm, em) for gr, col, k, vm, em in views]
-    torch.cuda.synchronize()
-    one_by_one_s = time.perf_counter() - t0
-    for i, r in enumerate(single):
-        assert r["rounds"] == res[i]["rounds"] and r["surviving_edges"] == res[i]["surviving_edges"], i
-    one_gps = G / one_by_one_s
+    one_gps = one_by_one_s = None
+    if not args.no_one_by_one:
+        # one graph at a time through the single-graph path, same device-resident inputs
+        views = []
+        for i in range(G):
+            d = b.desc[i]
+            n, R = int(d["n"]), int(d["row_words"])
+            a, o = int(d["row_offset"]), int(d["vertex_offset"])
+            rows_v = b.rows[a:a + n * R].view(n, R)
+            views.append((graph_bitset(rows_v), b.colour[o:o + n], int(d["k"]), b.vmask[o:o + n],
+                          b.emask[a:a + n * R].view(n, R)))
+        for gr, col, k, vm, em in views[:8]:
+            kz.run(gr, col, k, vm, em)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        single = [kz.run(gr, col, k, vm, em) for gr, col, k, vm, em in views]
+        torch.cuda.synchronize()
+        one_by_one_s = time.perf_counter() - t0
+        for i, r in enumerate(single):
+            assert r["rounds"] == res[i]["rounds"] and r["surviving_edges"] == res[i]["surviving_edges"], i
+        one_gps = G / one_by_one_s
     # algorithmic work: full-segment edge-test ops over the exact worklists
     ops = 0.0
     for i, (rows, colour, k) in enumerate(graphs):
@@ -295,14 +315,16 @@ def bench_batch(args):
                    "edges": int(res["input_edges"].sum()), "max_rounds": int(res["rounds"].max()),
                    "mean_rounds": float(res["rounds"].mean()), "planted": None, "seed": args.seed,
                    "batch_config": tuned, "parallelism": "single GPU"},
-        "one_by_one": {"value": one_gps, "unit": "graphs/s", "seconds": one_by_one_s,
-                       "what": "kz_kernelize per graph on the same device-resident inputs"},
-        "batched_over_one_by_one": value / one_gps,
+        "one_by_one": None if one_gps is None else {
+            "value": one_gps, "unit": "graphs/s", "seconds": one_by_one_s,
+            "what": "kz_kernelize per graph on the same device-resident inputs"},
+        "batched_over_one_by_one": None if one_gps is None else value / one_gps,
         "roofline": {"kernel": "k_batch", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                      "traffic": traffic_from_profile("c4"),
                      "ops": "32-bit integer VALU ops (AND, OR) of the full-segment edge test, all graphs",
-                     "avg_launch_ms": round(kernel_ms, 4), "alg_ops_per_launch": ops},
+                     "avg_launch_ms": round(kernel_ms, 4), "alg_ops_per_launch": ops,
+                     "valu_issue_frac": profile_value("c4", "valu_issue_frac"), "model_note": ALU_MODEL_NOTE},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -552,7 +574,9 @@ def main():
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic, "alg_bytes_per_launch": bytes_per_launch,
                     "bytes": "4 (deg u + deg v) per tested edge",
-                    "avg_launch_ms": round(edge_avg_ms, 5), "launches_per_step": edge_launches / psteps}
+                    "avg_launch_ms": round(edge_avg_ms, 5), "launches_per_step": edge_launches / psteps,
+                    "traffic_GBps": None if traffic is None else round(traffic / (edge_avg_ms / 1e3) / 1e9, 1),
+                    "model_note": CSR_MODEL_NOTE}
     elif mfma:
         # int8 MFMA counts: every pair of two classes against every third
         # class, 2 ops per multiply-accumulate, over the first (full) pass;
@@ -593,6 +617,8 @@ def main():
             "launches_per_step": edge_launches / psteps,
             "operand_stream_GBps": round(stream_gbps, 1),
             "operand_stream_frac_of_hbm": round(stream_gbps / HBM_PEAK_GBPS, 3),
+            "valu_issue_frac": profile_value(args.workload, "valu_issue_frac"),
+            "model_note": ALU_MODEL_NOTE,
         }
 
     cpu = None

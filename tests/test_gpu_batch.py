@@ -57,6 +57,15 @@ def check_batch(kz, graphs, ctx, bk=None):
         assert r["status"] == ref["status"], (ctx, i, r["status"], ref["status"])
         if ref["status"]:
             continue
+        if r["rounds"] != ref["rounds"]:
+            vm, em = b.masks(i)
+            detail = {"rounds": (int(r["rounds"]), ref["rounds"]),
+                      "surv_v": (int(r["surviving_vertices"]), ref["surv_vertices"]),
+                      "surv_e": (int(r["surviving_edges"]), ref["surv_edges"]),
+                      "tests": (int(r["edge_tests"]), ref["edge_tests"]),
+                      "vmask_equal": bool(np.array_equal(vm, ref["vmask"])),
+                      "emask_equal": bool(np.array_equal(em, ref["emask"]))}
+            raise AssertionError("%s graph %d: %s" % (ctx, i, detail))
         assert r["rounds"] == ref["rounds"] and r["equals_input"] == ref["equals_input"], (ctx, i)
         assert r["surviving_vertices"] == ref["surv_vertices"], (ctx, i)
         assert r["surviving_edges"] == ref["surv_edges"], (ctx, i)
