@@ -270,8 +270,9 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
     kzi::launch_setup(p, colour, 0, kzi::SETUP_CSR, s);
   }
   {
-    ProfScope t(ctx, KZ_KERNEL_PACK, s);
-    kzi::launch_csr_validate(p, rp, ci, nnz, colour, vmask, emask, s);
+    // validation and pass 1's vertex test share one sweep over the rows
+    ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
+    kzi::launch_csr_first(p, rp, ci, nnz, colour, vmask, emask, s);
   }
   if (hipGetLastError() != hipSuccess) return finish(res, r);
   long long removed_v = 0, removed_e = 0, tests = 0, m = 0;
@@ -279,9 +280,9 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
   for (;;) {
     ++pass;
     const bool first = pass == 1;
-    {
+    if (!first) {
       ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
-      kzi::launch_csr_vertex(p, rp, ci, colour, vmask, emask, pass, first, s);
+      kzi::launch_csr_vertex(p, rp, ci, colour, vmask, emask, pass, s);
     }
     {
       ProfScope t(ctx, KZ_KERNEL_EDGE, s);
@@ -289,7 +290,7 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
     }
     {
       ProfScope t(ctx, KZ_KERNEL_APPLY, s);
-      kzi::launch_csr_apply(p, ci, nnz, emask, pass, s);
+      kzi::launch_csr_apply(p, nnz, emask, s);
     }
     if (hipGetLastError() != hipSuccess) return finish(res, r);
     if (hipMemcpyAsync(ctx->pinned, p.hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -301,7 +302,7 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
       // unequal counts of entries above and below the diagonal: some
       // entry below it has no reverse
       unsigned long long balance = 0;
-      for (int slot = 0; slot < kzi::kCtrSlots; ++slot) balance += h.ctr[1][slot][3];
+      for (int slot = 0; slot < kzi::kCtrSlots; ++slot) balance += h.ctr(1, slot, 3);
       kzi::Hdr hs = h;
       if (balance != 0 && hs.prio < kzi::P_EASYM) hs.prio = kzi::P_EASYM;
       const int st = map_hdr_status(hs);
@@ -312,7 +313,7 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
     }
     unsigned long long c[3] = {0, 0, 0};
     for (int slot = 0; slot < kzi::kCtrSlots; ++slot)
-      for (int j = 0; j < 3; ++j) c[j] += h.ctr[pass & 1][slot][j];
+      for (int j = 0; j < 3; ++j) c[j] += h.ctr(pass & 1, slot, j);
     if (first) m = (long long)c[2];
     tests += (long long)c[2];
     removed_v += (long long)c[0];
@@ -671,7 +672,7 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
     }
     unsigned long long c[3] = {0, 0, 0};
     for (int slot = 0; slot < kzi::kCtrSlots; ++slot)
-      for (int j = 0; j < 3; ++j) c[j] += h.ctr[pass & 1][slot][j];
+      for (int j = 0; j < 3; ++j) c[j] += h.ctr(pass & 1, slot, j);
     if (first) m = (long long)c[2];
     tests += (long long)c[2];
     removed_v += (long long)c[0];

@@ -30,6 +30,29 @@ __device__ __forceinline__ int wave_sum_i(int x) {
   return x;
 }
 
+// Adds two per-wave counts into counter slots (par, slot, j0) and (par,
+// slot, j1) with one atomic each per workgroup of 4 waves: the counter lines
+// take one update per workgroup instead of one per wave.  Every thread of the
+// workgroup calls it.
+__device__ __forceinline__ void wg_add2(Hdr *h, int par, int j0, long long a, int j1, long long b) {
+  __shared__ long long sRed[4][2];
+  const int wv = threadIdx.x >> 6;
+  a = (long long)wave_sum_i((int)a);
+  b = (long long)wave_sum_i((int)b);
+  if ((threadIdx.x & 63) == 0) {
+    sRed[wv][0] = a;
+    sRed[wv][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long ta = sRed[0][0] + sRed[1][0] + sRed[2][0] + sRed[3][0];
+    const long long tb = sRed[0][1] + sRed[1][1] + sRed[2][1] + sRed[3][1];
+    const int slot = blockIdx.x % kCtrSlots;
+    if (ta) atomicAdd(&h->ctr(par, slot, j0), (unsigned long long)ta);
+    if (tb) atomicAdd(&h->ctr(par, slot, j1), (unsigned long long)tb);
+  }
+}
+
 // Row bounds of u, or false when they do not lie inside [0, nnz].
 __device__ __forceinline__ bool row_ok(const int64_t *rp, int u, long long nnz, long long &b, long long &e) {
   b = rp[u];
@@ -37,82 +60,101 @@ __device__ __forceinline__ bool row_ok(const int64_t *rp, int u, long long nnz, 
   return b >= 0 && b <= e && e <= nnz;
 }
 
-// Colour range (stage 1), structure and stage-2 checks, one wave per row;
-// also records the row of every entry and starts the state (everything
-// alive, everything touched).
-__global__ void __launch_bounds__(256) k_csr_validate(Plan p, const int64_t *rp, const int32_t *ci,
-                                                      long long nnz, const int *colour, uint8_t *vmask,
-                                                      uint8_t *emask) {
+// Pass 1's sweep over the rows, one wave per row u: the colour range (stage
+// 1), the structure and stage-2 checks, the start of the state (every entry
+// alive, every vertex touched, the row of every entry recorded) and pass 1's
+// vertex test with u's presence mask, all from one read of the row.
+template <int KW>
+__global__ void __launch_bounds__(256) k_csr_first(Plan p, const int64_t *rp, const int32_t *ci,
+                                                   long long nnz, const int *colour, uint8_t *vmask,
+                                                   uint8_t *emask) {
   Hdr *h = p.hdr;
-  if (csr_bad(h)) return;
-  const int u = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int n = p.n;
-  if (u >= n) return;
-  // stage 1: every colour in [0,k)
-  const int cu = colour[u];
-  if (lane == 0 && (cu < 0 || cu >= p.k)) h->bad_colour = 1;
-  int pr = P_NONE;
-  if (u == 0 && lane == 0 && rp[0] != 0) pr = P_EINVAL;
-  if (u == n - 1 && lane == 0 && rp[n] != nnz) pr = P_EINVAL;
-  long long b, e;
-  if (!row_ok(rp, u, nnz, b, e)) {
-    if (lane == 0) atomicMax(&h->prio, P_EINVAL);
-    return;
-  }
-  if (lane == 0) {
-    vmask[u] = 1;
-    p.touched[1][u] = 1;
-    p.touched[0][u] = 0;
-  }
+  __shared__ unsigned long long sPM[4][KW];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int u = blockIdx.x * 4 + wv;
+  const int n = p.n, k = p.k;
   int balance = 0;  // entries above the diagonal minus entries below it
-  for (long long i = b + lane; i < e; i += kWave) {
-    const int v = ci[i];
-    p.src[i] = u;
-    emask[i] = 1;
-    p.efail[i] = 0;
-    if (v < 0 || v >= n || (i > b && ci[i - 1] >= v)) {
-      pr = max(pr, P_EINVAL);
-      continue;
-    }
-    if (v == u) {
-      pr = max(pr, P_ESELFLOOP);
-      continue;
-    }
-    // Symmetry: every entry (u,v) with v > u must have its reverse (v,u),
-    // found by binary search in row v; with as many entries below the
-    // diagonal as above it (summed on the host), reversal then maps the
-    // upper entries onto the lower ones, so the lower ones need no search.
-    // The same-class check likewise covers both directions from above.
-    if (v < u) {
-      --balance;
-      continue;
-    }
-    ++balance;
-    long long vb, ve;
-    bool found = false;
-    if (row_ok(rp, v, nnz, vb, ve)) {
-      long long lo = vb, hi = ve;
-      while (lo < hi) {
-        const long long mid = lo + (hi - lo) / 2;
-        const int x = ci[mid];
-        if (x < u) lo = mid + 1;
-        else hi = mid;
+  bool uf = false;  // u fails pass 1's vertex test
+  long long b, e;
+  // stage 1: every colour in [0,k) (also on rows whose bounds are broken)
+  const int cu = u < n ? colour[u] : 0;
+  if (u < n && lane == 0 && (cu < 0 || cu >= k)) h->bad_colour = 1;
+  if (u < n && !row_ok(rp, u, nnz, b, e)) {
+    if (lane == 0) atomicMax(&h->prio, P_EINVAL);
+  } else if (u < n) {
+    int pr = P_NONE;
+    if (u == 0 && lane == 0 && rp[0] != 0) pr = P_EINVAL;
+    if (u == n - 1 && lane == 0 && rp[n] != nnz) pr = P_EINVAL;
+    if (lane < KW) sPM[wv][lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (long long i = b + lane; i < e; i += kWave) {
+      const int v = ci[i];
+      p.src[i] = u;
+      emask[i] = 1;
+      p.efail[i] = 0;
+      if (v < 0 || v >= n || (i > b && ci[i - 1] >= v)) {
+        pr = max(pr, P_EINVAL);
+        continue;
       }
-      found = lo < ve && ci[lo] == u;
+      if (v == u) {
+        pr = max(pr, P_ESELFLOOP);
+        continue;
+      }
+      const int cv = colour[v];
+      if (cv == cu) pr = max(pr, P_EILLEGAL);
+      if (cv >= 0 && cv < k) atomicOr(&sPM[wv][cv >> 6], 1ull << (cv & 63));
+      // Symmetry: every entry (u,v) with v > u must have its reverse (v,u),
+      // found by binary search in row v; with as many entries below the
+      // diagonal as above it (summed on the host), reversal then maps the
+      // upper entries onto the lower ones, so the lower ones need no search.
+      if (v < u) {
+        --balance;
+        continue;
+      }
+      ++balance;
+      long long vb, ve;
+      bool found = false;
+      if (row_ok(rp, v, nnz, vb, ve)) {
+        long long lo = vb, hi = ve;
+        while (lo < hi) {
+          const long long mid = lo + (hi - lo) / 2;
+          const int x = ci[mid];
+          if (x < u) lo = mid + 1;
+          else hi = mid;
+        }
+        found = lo < ve && ci[lo] == u;
+      }
+      if (!found) pr = max(pr, P_EASYM);
     }
-    if (!found) pr = max(pr, P_EASYM);
-    if (colour[v] == cu) pr = max(pr, P_EILLEGAL);
+    if (pr) atomicMax(&h->prio, pr);
+    __builtin_amdgcn_wave_barrier();
+    // pass 1's vertex test: u fails iff some class other than its own is
+    // missing from PM(u)
+    bool fail = false;
+    if (lane < KW) {
+      const unsigned long long pm = sPM[wv][lane];
+      p.pm[(long long)u * KW + lane] = pm;
+      const int lo = lane * 64;
+      unsigned long long want = 0;
+      if (k > lo) want = (k - lo >= 64) ? ~0ull : ((1ull << (k - lo)) - 1);
+      if ((cu >> 6) == lane) want &= ~(1ull << (cu & 63));
+      fail = (want & ~pm) != 0;
+    }
+    uf = __ballot(fail) != 0;
+    if (lane == 0) {
+      vmask[u] = uf ? 0 : 1;
+      p.touched[1][u] = 1;
+      p.touched[0][u] = 0;
+    }
   }
-  if (pr) atomicMax(&h->prio, pr);
-  balance = wave_sum_i(balance);
-  if (lane == 0 && balance)
-    atomicAdd(&h->ctr[1][blockIdx.x % kCtrSlots][3], (unsigned long long)(long long)balance);
+  // removed vertices and the balance, counted with pass 1's counters
+  wg_add2(h, 1, 0, lane == 0 && uf ? 1 : 0, 3, balance);
 }
 
-// Vertex test and presence masks.  One wave per vertex, lanes over its
-// entries.  Pass 1 processes every vertex; later passes the alive vertices
-// touched by the previous round.  Also resets this pass's bookkeeping.
-template <bool FIRST, int KW>
+// Vertex test and presence masks of passes after the first.  One wave per
+// vertex, lanes over its entries; only the alive vertices touched by the
+// previous round.  Also resets this pass's bookkeeping.
+template <int KW>
 __global__ void __launch_bounds__(256) k_csr_vertex(Plan p, const int64_t *rp, const int32_t *ci,
                                                     const int *colour, uint8_t *vmask,
                                                     const uint8_t *emask, int pass) {
@@ -123,15 +165,14 @@ __global__ void __launch_bounds__(256) k_csr_vertex(Plan p, const int64_t *rp, c
   {
     const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    if (!FIRST)
-      for (long long i = gt; i < n; i += stride) p.touched[nxt][i] = 0;
-    if (gt < kCtrSlots * 4) (&h->ctr[nxt][0][0])[gt] = 0;
+    for (long long i = gt; i < n; i += stride) p.touched[nxt][i] = 0;
+    if (gt < kCtrSlots * 4) h->ctr(nxt, gt / 4, gt % 4) = 0;
   }
   __shared__ unsigned long long sPM[4][KW];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int v = blockIdx.x * 4 + wv;
   if (v >= n) return;
-  if (!FIRST && (!vmask[v] || !p.touched[cur][v])) return;
+  if (!vmask[v] || !p.touched[cur][v]) return;
   if (lane < KW) sPM[wv][lane] = 0;
   __builtin_amdgcn_wave_barrier();
   const long long b = rp[v], e = rp[v + 1];
@@ -155,13 +196,16 @@ __global__ void __launch_bounds__(256) k_csr_vertex(Plan p, const int64_t *rp, c
   }
   const bool vf = __ballot(fail) != 0;
   if (lane == 0) {
-    if (FIRST) vmask[v] = vf ? 0 : 1;
-    else if (vf) vmask[v] = 0;
-    if (vf) atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][0], 1ull);
+    if (vf) {
+      vmask[v] = 0;
+      atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 0), 1ull);
+    }
   }
 }
 
-// Edge test, one thread per directed entry.
+// Edge test, one thread per directed entry.  A failing entry is flagged for
+// the apply pass, counted once per undirected edge (u < v) and marks its row
+// u touched for the next pass (the reverse entry fails too and marks v).
 template <bool FIRST, int KW>
 __global__ void __launch_bounds__(256) k_csr_edge(Plan p, const int64_t *rp, const int32_t *ci,
                                                   long long nnz, const int *colour, const uint8_t *emask,
@@ -169,9 +213,10 @@ __global__ void __launch_bounds__(256) k_csr_edge(Plan p, const int64_t *rp, con
   Hdr *h = p.hdr;
   if (csr_bad(h) || h->prio) return;
   const int k = p.k;
-  const int cur = pass & 1;
+  const int cur = pass & 1, nxt = cur ^ 1;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool tested = false;
+  bool tested = false, removed = false;
+  int marks = -1;  // row to mark touched (the entry failed)
   if (i < nnz && emask[i]) {
     const int u = p.src[i], v = ci[i];
     if (FIRST || p.touched[cur][u] || p.touched[cur][v]) {
@@ -215,33 +260,34 @@ __global__ void __launch_bounds__(256) k_csr_edge(Plan p, const int64_t *rp, con
         }
         fail = !done;
       }
-      if (fail) p.efail[i] = 1;
+      if (fail) {
+        p.efail[i] = 1;
+        marks = u;
+        removed = u < v;
+      }
     }
   }
-  const int cnt = wave_sum_i(tested ? 1 : 0);
-  if ((threadIdx.x & 63) == 0 && cnt)
-    atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][2], (unsigned long long)cnt);
+  // entries are in row order: of the lanes marking one row, only the first
+  // of each run stores the flag
+  const int prev = __shfl_up(marks, 1, kWave);
+  if (marks >= 0 && ((threadIdx.x & 63) == 0 || prev != marks)) p.touched[nxt][marks] = 1;
+  wg_add2(h, cur, 2, tested ? 1 : 0, 1, removed ? 1 : 0);
 }
 
-// Removes the entries that failed this pass and marks their endpoints.
-__global__ void __launch_bounds__(256) k_csr_apply(Plan p, const int32_t *ci, long long nnz, uint8_t *emask,
-                                                   int pass) {
-  Hdr *h = p.hdr;
+// Removes the entries that failed this pass (after every test of the pass
+// has read the old masks).  Four entries per thread.
+__global__ void __launch_bounds__(256) k_csr_apply(Plan p, long long nnz, uint8_t *emask) {
+  const Hdr *h = p.hdr;
   if (csr_bad(h) || h->prio) return;
-  const int cur = pass & 1, nxt = cur ^ 1;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  bool removed = false;
-  if (i < nnz && p.efail[i]) {
-    const int u = p.src[i], v = ci[i];
-    p.efail[i] = 0;
-    emask[i] = 0;
-    p.touched[nxt][u] = 1;
-    p.touched[nxt][v] = 1;
-    removed = u < v;
+  const long long i0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const long long i = i0 + j;
+    if (i < nnz && p.efail[i]) {
+      p.efail[i] = 0;
+      emask[i] = 0;
+    }
   }
-  const int cnt = wave_sum_i(removed ? 1 : 0);
-  if ((threadIdx.x & 63) == 0 && cnt)
-    atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][1], (unsigned long long)cnt);
 }
 
 inline unsigned grid_of(long long work, int per_block) {
@@ -253,26 +299,23 @@ inline unsigned grid_of(long long work, int per_block) {
 
 int csr_words(int k) { return k <= 64 ? 1 : (k <= 256 ? 4 : 16); }
 
-void launch_csr_validate(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
-                         uint8_t *vmask, uint8_t *emask, hipStream_t s) {
-  hipLaunchKernelGGL(k_csr_validate, dim3(grid_of(p.n, 4)), dim3(256), 0, s, p, rp, ci, nnz, colour, vmask,
-                     emask);
+void launch_csr_first(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
+                      uint8_t *vmask, uint8_t *emask, hipStream_t s) {
+  const dim3 grid(grid_of(p.n, 4)), block(256);
+  const int kw = csr_words(p.k);
+  if (kw == 1) hipLaunchKernelGGL((k_csr_first<1>), grid, block, 0, s, p, rp, ci, nnz, colour, vmask, emask);
+  else if (kw == 4) hipLaunchKernelGGL((k_csr_first<4>), grid, block, 0, s, p, rp, ci, nnz, colour, vmask, emask);
+  else hipLaunchKernelGGL((k_csr_first<16>), grid, block, 0, s, p, rp, ci, nnz, colour, vmask, emask);
 }
 
 void launch_csr_vertex(const Plan &p, const int64_t *rp, const int32_t *ci, const int *colour, uint8_t *vmask,
-                       const uint8_t *emask, int pass, bool first, hipStream_t s) {
+                       const uint8_t *emask, int pass, hipStream_t s) {
   const dim3 grid(grid_of(p.n, 4)), block(256);
   const int kw = csr_words(p.k);
-#define KZ_CSR_V(F, W) hipLaunchKernelGGL((k_csr_vertex<F, W>), grid, block, 0, s, p, rp, ci, colour, vmask, emask, pass)
-  if (first) {
-    if (kw == 1) KZ_CSR_V(true, 1);
-    else if (kw == 4) KZ_CSR_V(true, 4);
-    else KZ_CSR_V(true, 16);
-  } else {
-    if (kw == 1) KZ_CSR_V(false, 1);
-    else if (kw == 4) KZ_CSR_V(false, 4);
-    else KZ_CSR_V(false, 16);
-  }
+#define KZ_CSR_V(W) hipLaunchKernelGGL((k_csr_vertex<W>), grid, block, 0, s, p, rp, ci, colour, vmask, emask, pass)
+  if (kw == 1) KZ_CSR_V(1);
+  else if (kw == 4) KZ_CSR_V(4);
+  else KZ_CSR_V(16);
 #undef KZ_CSR_V
 }
 
@@ -294,9 +337,9 @@ void launch_csr_edge(const Plan &p, const int64_t *rp, const int32_t *ci, long l
 #undef KZ_CSR_E
 }
 
-void launch_csr_apply(const Plan &p, const int32_t *ci, long long nnz, uint8_t *emask, int pass, hipStream_t s) {
+void launch_csr_apply(const Plan &p, long long nnz, uint8_t *emask, hipStream_t s) {
   if (nnz <= 0) return;
-  hipLaunchKernelGGL(k_csr_apply, dim3(grid_of(nnz, 256)), dim3(256), 0, s, p, ci, nnz, emask, pass);
+  hipLaunchKernelGGL(k_csr_apply, dim3(grid_of(nnz, 1024)), dim3(256), 0, s, p, nnz, emask);
 }
 
 }  // namespace kzi

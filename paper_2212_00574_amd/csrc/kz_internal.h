@@ -22,19 +22,27 @@ constexpr int kSetupThreads = 1024;  // the single setup workgroup
 constexpr int kVertexLdsClasses = 2048;  // vertex pass keeps class offsets in LDS up to this k
 constexpr int kSetupLdsClasses = 4096;  // class histogram kept in LDS up to this k
 
-constexpr int kCtrSlots = 64;      // spread of the per-pass counters
+constexpr int kCtrSlots = 32;      // spread of the per-pass counters
+constexpr int kCtrStride = 16;     // words per counter slot: 4 per pass parity, one cache line
 
 // stage-2 status priorities (largest wins)
 enum : int { P_NONE = 0, P_EILLEGAL = 1, P_EASYM = 2, P_ESELFLOOP = 3, P_EINVAL = 4 };
 
 // Device-resident header at the start of the workspace.
 struct Hdr {
-  // per pass parity and slot: removed vertices, removed edges, edge tests,
-  // and a fourth counter that only the CSR validation uses (ctr[1][*][3]:
+  // Per slot and pass parity: removed vertices, removed edges, edge tests,
+  // and a fourth counter that only the CSR validation uses (ctr(1, *, 3):
   // entries above minus entries below the diagonal, read with pass 1's
   // counters).  Workgroups add into slot (id % kCtrSlots) so that thousands
-  // of same-address atomics do not serialise; the host sums the slots.
-  unsigned long long ctr[2][kCtrSlots][4];
+  // of same-address atomics do not serialise; each slot is one 128-byte
+  // cache line holding both parities (atomics on one line serialise too,
+  // and the host copies the header back every pass, so it stays 4 KiB); the
+  // host sums the slots.
+  unsigned long long ctrw[kCtrSlots][kCtrStride];
+  __host__ __device__ unsigned long long &ctr(int par, int slot, int j) { return ctrw[slot][par * 4 + j]; }
+  __host__ __device__ const unsigned long long &ctr(int par, int slot, int j) const {
+    return ctrw[slot][par * 4 + j];
+  }
   int tile_count;        // changed tiles appended by the edge pass
   int prio;              // stage-2 status priority
   int bad_colour;        // stage 1: some colour outside [0,k)
@@ -107,13 +115,15 @@ void launch_unpack_dense(const Plan &p, const int *colour, const uint64_t *cur, 
 
 // Sparse path (kz_csr.hip).  State in place: vmask / emask (per entry).
 int csr_words(int k);  // 64-bit words of a class set: 1, 4 or 16 (k <= 1024)
-void launch_csr_validate(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
-                         uint8_t *vmask, uint8_t *emask, hipStream_t s);
+// Pass 1's validation, state start and vertex test in one sweep; later
+// passes' vertex tests.
+void launch_csr_first(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
+                      uint8_t *vmask, uint8_t *emask, hipStream_t s);
 void launch_csr_vertex(const Plan &p, const int64_t *rp, const int32_t *ci, const int *colour, uint8_t *vmask,
-                       const uint8_t *emask, int pass, bool first, hipStream_t s);
+                       const uint8_t *emask, int pass, hipStream_t s);
 void launch_csr_edge(const Plan &p, const int64_t *rp, const int32_t *ci, long long nnz, const int *colour,
                      const uint8_t *emask, int pass, bool first, hipStream_t s);
-void launch_csr_apply(const Plan &p, const int32_t *ci, long long nnz, uint8_t *emask, int pass, hipStream_t s);
+void launch_csr_apply(const Plan &p, long long nnz, uint8_t *emask, hipStream_t s);
 
 // Batched path (kz_batch.hip).
 constexpr int kBatchK = 64;          // classes

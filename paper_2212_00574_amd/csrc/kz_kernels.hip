@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
     carry_a = 0;
     carry_b = 0;
   }
-  for (int i = t; i < 2 * kCtrSlots * 4; i += kSetupThreads) (&h->ctr[0][0][0])[i] = 0;
+  for (int i = t; i < 2 * kCtrSlots * 4; i += kSetupThreads) h->ctr(i / (4 * kCtrSlots), (i / 4) % kCtrSlots, i % 4) = 0;
   // CSR kernels use no class table; their validation checks the colours
   if (mode == SETUP_CSR) return;
   for (int c = t; c < k; c += kSetupThreads) {
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
     for (long long i = gt; i < n; i += stride) p.touched[nxt][i] = 0;
     for (long long i = gt; i < R; i += stride) p.btouched[nxt][i] = 0;
     if (gt == 0) h->tile_count = 0;
-    if (gt < kCtrSlots * 4) (&h->ctr[nxt][0][0])[gt] = 0;
+    if (gt < kCtrSlots * 4) h->ctr(nxt, gt / 4, gt % 4) = 0;
   }
   __shared__ int sFail[kWave];
   __shared__ int sOff[2][kVertexLdsClasses + 1];  // coff, soff
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
       p.valive[v] = 0;
   }
   const int nf = wave_sum(fail ? 1 : 0);
-  if (lane == 0 && nf) atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][0], (unsigned long long)nf);
+  if (lane == 0 && nf) atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 0), (unsigned long long)nf);
 }
 
 // The i-th class other than cx and cy (cx < cy): the third classes of a tile.
@@ -471,7 +471,7 @@ __device__ __forceinline__ int third_class(int i, int cx, int cy) {
 // MF: the witness search is replaced by the fail bits `fb` of the MFMA
 // count path (k_mfma_count), so both paths share this tile epilogue.
 template <bool FIRST, int CH, bool MF>
-__global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *__restrict__ src,
+__global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 1) k_edge(Plan p, const uint64_t *__restrict__ src,
                                                        uint64_t *__restrict__ dst, int pass,
                                                        const uint64_t *__restrict__ fb) {
   Hdr *h = p.hdr;
@@ -684,7 +684,7 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
         const int pos = atomicAdd(&h->tile_count, 1);
         p.tiles[pos] = make_int2(X, Y);
       }
-      atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][1], (unsigned long long)rem);
+      atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 1), (unsigned long long)rem);
     }
   }
   // exact worklist size: edges of this tile with a touched endpoint
@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *_
     const unsigned long long TV = __ballot(tV != 0);
     cnt = wave_sum(lane < xl ? __popcll(Eu & (tU ? ~0ull : TV)) : 0);
   }
-  if (lane == 0 && cnt) atomicAdd(&h->ctr[cur][blockIdx.x % kCtrSlots][2], (unsigned long long)cnt);
+  if (lane == 0 && cnt) atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 2), (unsigned long long)cnt);
 }
 
 // ---------------------------------------------------------------- MFMA count path
