@@ -267,14 +267,13 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
     __builtin_amdgcn_wave_barrier();
   }
   const unsigned long long Pu = sPw[lane];
-  // transposes: lane v gathers bit v of P(u) and, in pass 1, of E(u) to check
-  // that the rows are symmetric
-  unsigned long long newET = 0, trE = 0;
-  for (int u = 0; u < xl; ++u) {
-    newET |= ((bcast64(Pu, u) >> lane) & 1ull) << u;
-    if (first) trE |= ((bcast64(Eu, u) >> lane) & 1ull) << u;
+  // transposes: lane v gets bit v of every P(u) (rows u >= xl hold zero) and,
+  // in pass 1, of every E(u), to check that the rows are symmetric
+  const unsigned long long newET = wave_transpose64(Pu, lane);
+  if (first) {
+    const unsigned long long trE = wave_transpose64(Eu, lane);
+    if (lane < yl && ((trE ^ ET) & xmask)) atomicMax(&S.prio, P_EASYM);
   }
-  if (first && lane < yl && ((trE ^ ET) & xmask)) atomicMax(&S.prio, P_EASYM);
   const bool chU = lane < xl && Eu != Pu;
   const bool chV = lane < yl && (ET & xmask) != newET;
   const unsigned long long bu = __ballot(chU), bv = __ballot(chV);
@@ -785,6 +784,7 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
   __syncthreads();
   int job = -1;
   unsigned long long idle0 = 0;  // thread 0: when this workgroup ran out of work
+  int backoff = 1;                // idle polls sleep 1, 2, 4 or 8 times between looks
   for (;;) {
     if (job >= 0) {
       if (!S.got) claim<NW>(a, S, job);
@@ -811,12 +811,14 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
       if (g >= 0) {
         if (start_job<NW>(a, S, g)) job = g;
         idle0 = 0;
+        backoff = 1;
         continue;
       }
     }
     job = find_job(a, S, 1u);
     if (job >= 0) {
       idle0 = 0;
+      backoff = 1;
       continue;
     }
     if (tid == 0) {
@@ -827,7 +829,11 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
     }
     __syncthreads();
     if (S.quit) break;
-    __builtin_amdgcn_s_sleep(8);
+    // back off while idle: every look at the board is a few KiB of loads
+    // that bypass the caches, and hundreds of idle workgroups looking at
+    // once slow down the ones still working
+    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(32);
+    backoff = backoff < 8 ? 2 * backoff : 8;
   }
 }
 

@@ -28,6 +28,24 @@ constexpr int kCtrStride = 16;     // words per counter slot: 4 per pass parity,
 // stage-2 status priorities (largest wins)
 enum : int { P_NONE = 0, P_EILLEGAL = 1, P_EASYM = 2, P_ESELFLOOP = 3, P_EINVAL = 4 };
 
+// Transposes a 64x64 bit matrix held one row per lane (lane l holds row l,
+// bit b = column b): returns row l of the transpose, i.e. bit b of the
+// result is bit l of lane b's input.  Six butterfly stages: at stage j,
+// lanes l and l^j swap the j-wide column groups on the wrong side of the
+// diagonal.  Every lane of the wave must take part.
+__device__ __forceinline__ unsigned long long wave_transpose64(unsigned long long x, int lane) {
+  constexpr unsigned long long kM[6] = {0xFFFFFFFF00000000ull, 0xFFFF0000FFFF0000ull, 0xFF00FF00FF00FF00ull,
+                                        0xF0F0F0F0F0F0F0F0ull, 0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int j = 32 >> st;
+    const unsigned long long m = kM[st];
+    const unsigned long long y = (unsigned long long)__shfl_xor((long long)x, j, kWave);
+    x = (lane & j) ? ((x & m) | ((y & m) >> j)) : ((x & ~m) | ((y & ~m) << j));
+  }
+  return x;
+}
+
 // Device-resident header at the start of the workspace.
 struct Hdr {
   // Per slot and pass parity: removed vertices, removed edges, edge tests,

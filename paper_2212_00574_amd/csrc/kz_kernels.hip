@@ -494,7 +494,6 @@ __global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 1) k_edge(Plan p, 
   __shared__ ulonglong2 sU[CH][kBlk];
   __shared__ unsigned long long sV2[CH][kBlk];
   __shared__ unsigned long long sE[kBlk], sP[kBlk];
-  __shared__ unsigned long long sT[kWaves][kBlk], sTE[kWaves][kBlk];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -626,47 +625,16 @@ __global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 1) k_edge(Plan p, 
   }
   __syncthreads();
 
-  // transpose: lane v gathers bit v of P(u) (and, in pass 1, of E(u)) for
-  // this wave's rows u.  A wave whose rows all kept their edges contributes
-  // its slice of ET instead (by symmetry, which pass 1 verifies).
-  const int v = lane;
-  const unsigned long long wrows = (kRowsPerWave == 64 ? ~0ull : ((1ull << kRowsPerWave) - 1)) << (wid * kRowsPerWave);
-  bool wchanged = false;
-#pragma unroll
-  for (int ui = 0; ui < kRowsPerWave; ++ui) {
-    const int u = wid * kRowsPerWave + ui;
-    wchanged |= u < xl && sP[u] != (sE[u] & ymask);
-  }
-  unsigned long long part = 0, partE = 0;
-  if (wchanged || FIRST) {
-#pragma unroll
-    for (int ui = 0; ui < kRowsPerWave; ++ui) {
-      const int u = wid * kRowsPerWave + ui;
-      if (u < xl) {
-        const unsigned long long P = sP[u], E = sE[u];
-        const unsigned bp = v < 32 ? (unsigned)P >> v : (unsigned)(P >> 32) >> (v - 32);
-        part |= (unsigned long long)(bp & 1u) << u;
-        if (FIRST) {
-          const unsigned be = v < 32 ? (unsigned)E >> v : (unsigned)(E >> 32) >> (v - 32);
-          partE |= (unsigned long long)(be & 1u) << u;
-        }
-      }
-    }
-  }
-  if (!wchanged) part = ET & wrows;
-  sT[wid][lane] = part;
-  if (FIRST) sTE[wid][lane] = partE;
-  __syncthreads();
   if (wid != 0) return;
 
-  unsigned long long newET = 0, trE = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    newET |= sT[w][v];
-    if (FIRST) trE |= sTE[w][v];
+  // wave 0: lane v gets bit v of every P(u) -- the new word X of row v --
+  // and, in pass 1, of every E(u), to check that the rows are symmetric
+  const int v = lane;
+  const unsigned long long newET = wave_transpose64(sP[lane], lane) & xmask;
+  if (FIRST) {
+    const unsigned long long trE = wave_transpose64(sE[lane], lane);
+    if (v < yl && ((trE ^ ET) & xmask)) atomicMax(&h->prio, P_EASYM);
   }
-  newET &= xmask;
-  if (FIRST && v < yl && ((trE ^ ET) & xmask)) atomicMax(&h->prio, P_EASYM);
   const unsigned long long Eu = sE[lane] & ymask, Pu = sP[lane];
   const bool chU = lane < xl && Eu != Pu;
   const bool chV = v < yl && (ET & xmask) != newET;
