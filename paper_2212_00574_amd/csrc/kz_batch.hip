@@ -188,7 +188,7 @@ __device__ void vertex_chunk(const GView &V, BatchLds &S, int v0, bool first, in
 // tested again after pass 1; the others keep their outcome.
 template <int CH>
 __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int lane,
-                     unsigned long long (*sU)[kBlk], unsigned long long (*sU2)[kBlk], unsigned long long *sPw) {
+                     unsigned long long (*sU)[kBlk], unsigned long long (*sU2)[kBlk]) {
   const int R = V.R;
   const uint64_t *src = V.cur;
   const int cx = S.bcls[X], cy = S.bcls[Y];
@@ -201,7 +201,7 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
   const unsigned long long ET = lane < yl ? rowv[X] : 0ull;
   const unsigned long long TU = first ? ~0ull : __ballot(lane < xl && tbit(S.tc, xs + lane));
   const unsigned long long TV = first ? ~0ull : __ballot(lane < yl && tbit(S.tc, ys + lane));
-  sPw[lane] = Eu;
+  unsigned long long myP = Eu;  // P of the row this lane stands for
   const int nthird = V.k - 2;
   for (int q = 0; q < nthird; q += CH) {
     // stage the first two words of each third-class segment: row u's in LDS
@@ -232,7 +232,7 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
     }
     __builtin_amdgcn_wave_barrier();
     for (int u = 0; u < xl; ++u) {
-      unsigned long long P = bcast64(sPw[lane], u);
+      unsigned long long P = bcast64(myP, u);
       const unsigned long long Pt = P & (((TU >> u) & 1ull) ? ~0ull : TV);
       if (!Pt) continue;
       unsigned long long all = ~0ull;
@@ -262,11 +262,11 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
         }
         P &= ~miss;
       }
-      if (lane == u) sPw[lane] = P;
+      if (lane == u) myP = P;
     }
     __builtin_amdgcn_wave_barrier();
   }
-  const unsigned long long Pu = sPw[lane];
+  const unsigned long long Pu = myP;
   // transposes: lane v gets bit v of every P(u) (rows u >= xl hold zero) and,
   // in pass 1, of every E(u), to check that the rows are symmetric
   const unsigned long long newET = wave_transpose64(Pu, lane);
@@ -298,7 +298,7 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
 // The waves of the workgroup take the items of the claimed run one by one.
 template <int NW, int CH>
 __device__ void run_items(const GView &V, BatchLds &S, unsigned long long (*sU)[CH][kBlk],
-                          unsigned long long (*sU2)[CH][kBlk], unsigned long long (*sPw)[kBlk]) {
+                          unsigned long long (*sU2)[CH][kBlk]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool first = S.pass == 1;
   const int cnt = S.cnt, base = S.base;
@@ -309,7 +309,7 @@ __device__ void run_items(const GView &V, BatchLds &S, unsigned long long (*sU)[
     if (i >= cnt) break;
     const int it = V.items[base + i];
     if (it & kVertexItem) vertex_chunk(V, S, (it & 0xffff) * kWave, first, lane);
-    else tile<CH>(V, S, it & kXMask, (it >> kYShift) & kXMask, first, lane, sU[wid], sU2[wid], sPw[wid]);
+    else tile<CH>(V, S, it & kXMask, (it >> kYShift) & kXMask, first, lane, sU[wid], sU2[wid]);
   }
   __syncthreads();
 }
@@ -773,7 +773,6 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
   __shared__ BatchLds S;
   __shared__ unsigned long long sU[NW][CH][kBlk];
   __shared__ unsigned long long sU2[NW][CH][kBlk];
-  __shared__ unsigned long long sPw[NW][kBlk];
   const int tid = threadIdx.x;
   if (tid == 0) {
     S.job = -1;
@@ -790,7 +789,7 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
       if (!S.got) claim<NW>(a, S, job);
       if (S.got) {
         const GView V = gview(a, job);
-        run_items<NW, CH>(V, S, sU, sU2, sPw);
+        run_items<NW, CH>(V, S, sU, sU2);
         if (retire(V, S) && !carry<NW>(a, V, S)) job = -1;
         continue;
       }

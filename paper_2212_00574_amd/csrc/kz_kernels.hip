@@ -107,30 +107,44 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
   if (bitset && lds_hist)
     for (int c = t; c <= k; c += kSetupThreads) sst[c] = 0;
   __syncthreads();
-  for (int u = t; u < n; u += kSetupThreads) {
-    const int c = colour[u];
-    if (c < 0 || c >= k) {
-      s_bad_colour = 1;
-      continue;
+  // four vertices per thread at a time, their colour loads issued together
+  constexpr int kBatch = 4;
+  for (int u0 = t; u0 < n; u0 += kBatch * kSetupThreads) {
+    int cs[kBatch], ps[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int u = u0 + q * kSetupThreads;
+      cs[q] = u < n ? colour[u] : 0;
+      ps[q] = bitset && u < n && u > 0 ? colour[u - 1] : -1;
     }
-    if (bitset) {
-      // sorted colours: u is the first vertex of every class in
-      // (colour[u-1], c], and the last vertex ends the classes above its own
-      const int prev = u > 0 ? colour[u - 1] : -1;
-      if (prev > c) {
-        s_bad_layout = 1;
-      } else if (lds_hist) {
-        for (int x = max(prev + 1, 0); x <= c; ++x) sst[x] = u;
-        if (u == n - 1)
-          for (int x = c + 1; x <= k; ++x) sst[x] = n;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int u = u0 + q * kSetupThreads;
+      if (u >= n) break;
+      const int c = cs[q];
+      if (c < 0 || c >= k) {
+        s_bad_colour = 1;
+        continue;
       }
-      continue;
+      if (bitset) {
+        // sorted colours: u is the first vertex of every class in
+        // (colour[u-1], c], and the last vertex ends the classes above its own
+        const int prev = ps[q];
+        if (prev > c) {
+          s_bad_layout = 1;
+        } else if (lds_hist) {
+          for (int x = max(prev + 1, 0); x <= c; ++x) sst[x] = u;
+          if (u == n - 1)
+            for (int x = c + 1; x <= k; ++x) sst[x] = n;
+        }
+        continue;
+      }
+      if (lds_hist)
+        atomicAdd(&sh[c], 1);
+      else
+        atomicAdd(&p.counts[c], 1);
+      if (dense) atomicAdd(&p.hist[(long long)(u / kRankChunk) * k + c], 1);
     }
-    if (lds_hist)
-      atomicAdd(&sh[c], 1);
-    else
-      atomicAdd(&p.counts[c], 1);
-    if (dense) atomicAdd(&p.hist[(long long)(u / kRankChunk) * k + c], 1);
   }
   if (bitset && lds_hist) {
     // class sizes from the class starts (meaningful only when the colours
@@ -334,12 +348,12 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
       uint4 *d4 = (uint4 *)(dst + base);
       const long long c2 = cnt / 2;
       long long i = tid;
-      for (; i + 3 * 256 < c2; i += 4 * 256) {
-        const uint4 a = s4[i], b = s4[i + 256], c = s4[i + 512], d = s4[i + 768];
-        d4[i] = a;
-        d4[i + 256] = b;
-        d4[i + 512] = c;
-        d4[i + 768] = d;
+      for (; i + 7 * 256 < c2; i += 8 * 256) {
+        uint4 r[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[q] = s4[i + q * 256];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d4[i + q * 256] = r[q];
       }
       for (; i < c2; i += 256) d4[i] = s4[i];
       if ((cnt & 1) && tid == 0) dst[base + cnt - 1] = src[base + cnt - 1];
