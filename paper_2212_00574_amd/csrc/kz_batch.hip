@@ -208,6 +208,7 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
     // (read as broadcasts), row v's in registers
     unsigned long long vv[CH], vv2[CH];
     int w2[CH];
+    bool any2 = false, any3 = false;  // some segment of the chunk has a second / third word
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
       const int i = q + j;
@@ -217,6 +218,8 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
         if (c >= cy) ++c;
         const int w0 = S.soff[c], w1 = S.soff[c + 1];
         const bool has = w1 > w0, two = w1 > w0 + 1;
+        any2 |= two;
+        any3 |= w0 + 2 < w1;
         sU[j][lane] = (has && lane < xl) ? rowu_l[w0] : 0ull;
         sU2[j][lane] = (two && lane < xl) ? rowu_l[w0 + 1] : 0ull;
         vv[j] = (has && lane < yl) ? rowv[w0] : 0ull;
@@ -239,11 +242,20 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
 #pragma unroll
       for (int j = 0; j < CH; ++j) all &= __ballot((sU[j][u] & vv[j]) != 0ull);
       if (!(Pt & ~all)) continue;
-      // level 2: the first two words
-      all = ~0ull;
+      // level 2: the first two words (nothing new when no segment has two)
+      if (any2) {
+        all = ~0ull;
 #pragma unroll
-      for (int j = 0; j < CH; ++j) all &= __ballot(((sU[j][u] & vv[j]) | (sU2[j][u] & vv2[j])) != 0ull);
-      if (!(Pt & ~all)) continue;
+        for (int j = 0; j < CH; ++j) all &= __ballot(((sU[j][u] & vv[j]) | (sU2[j][u] & vv2[j])) != 0ull);
+        if (!(Pt & ~all)) continue;
+      }
+      if (!any3) {
+        // the first two words are the whole segments: a lane missing a
+        // witness in some class loses its edge
+        P &= ~(Pt & ~all);
+        if (lane == u) myP = P;
+        continue;
+      }
       // level 3: scan the rest of the segment in memory
       const uint64_t *rowu = src + (long long)(xs + u) * R;
 #pragma unroll
