@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -135,10 +136,20 @@ PROFILED = {
 }
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed (the
+    sources hold no comment markers inside string literals)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash(workload="c2"):
+    """Hash of the code (comments and layout ignored) the workload's roofline
+    kernel is built from."""
     h = hashlib.sha256()
     for f in PROFILED.get(workload, PROFILED["c2"])[1]:
-        h.update(open(os.path.join(ROOT, "paper_2212_00574_amd", "csrc", f), "rb").read())
+        h.update(_code_only(open(os.path.join(ROOT, "paper_2212_00574_amd", "csrc", f)).read()).encode())
     return h.hexdigest()[:16]
 
 

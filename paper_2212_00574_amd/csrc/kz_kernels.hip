@@ -479,11 +479,15 @@ __device__ __forceinline__ int third_class(int i, int cx, int cy) {
 // covered: the same with the first two words.  Level 3 (rare): class by
 // class, the lanes still missing a witness scan the rest of the segment in
 // memory.  Padding slots of the last chunk hold all-ones words, so they never
-// drop a lane.  When a bit of the tile changed, both copies of its new bits
-// go to `dst` (pass 1: the output state, which already holds a copy of the
-// input; later passes: scratch, and the tile is listed for the apply pass).
-// MF: the witness search is replaced by the fail bits `fb` of the MFMA
-// count path (k_mfma_count), so both paths share this tile epilogue.
+// drop a lane.  Wave 0 then turns the rows P(u) into the new word X of every
+// row v with a lane butterfly transpose (and, in pass 1, checks the input's
+// symmetry the same way).  When a bit of the tile changed, both copies of
+// its new bits go to `dst` (pass 1: the output state, which already holds a
+// copy of the input; later passes: scratch, and the tile is listed for the
+// apply pass).  MF: the witness search is replaced by the fail bits `fb` of
+// the MFMA count path (k_mfma_count), so both paths share this tile
+// epilogue.  Six-class chunks keep the kernel within 80 registers, so six
+// waves fit on a SIMD.
 template <bool FIRST, int CH, bool MF>
 __global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 1) k_edge(Plan p, const uint64_t *__restrict__ src,
                                                        uint64_t *__restrict__ dst, int pass,
