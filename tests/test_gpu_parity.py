@@ -121,6 +121,9 @@ CASES = [
     ([50, 70], 0.05, False),         # k = 2: isolated vertices only
     ([90], 0.0, False),              # k = 1
     ([30, 0, 40, 20], 0.6, False),   # an empty class empties the graph
+    ([0, 45, 70], 0.5, False),       # empty first class
+    ([45, 70, 0], 0.5, False),       # empty last class
+    ([50, 0, 0, 66], 0.5, False),    # two empty classes in a row
     ([100] * 5, 0.12, False),        # sparse: long cascades
     ([80] * 8, 0.22, False),
     ([7, 300, 9, 250], 0.5, False),
