@@ -88,7 +88,7 @@ kzi::WsSizes plan_sizes_csr(const kz_graph *g, int32_t k) {
   z.off_touched1 = take(n);
   z.off_src = take(sizeof(int32_t) * nnz);
   z.off_efail = take(nnz);
-  z.off_pm = take(sizeof(uint64_t) * n * (size_t)kzi::csr_words(k));
+  z.off_pm = take(sizeof(uint64_t) * n * ((size_t)kzi::csr_words(k) + 1));  // presence mask + colour
   z.total = o;
   return z;
 }

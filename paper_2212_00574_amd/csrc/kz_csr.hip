@@ -131,9 +131,10 @@ __global__ void __launch_bounds__(256) k_csr_first(Plan p, const int64_t *rp, co
     // pass 1's vertex test: u fails iff some class other than its own is
     // missing from PM(u)
     bool fail = false;
+    if (lane == KW) p.pm[(long long)u * (KW + 1) + KW] = (unsigned long long)(unsigned)cu;  // record: colour
     if (lane < KW) {
       const unsigned long long pm = sPM[wv][lane];
-      p.pm[(long long)u * KW + lane] = pm;
+      p.pm[(long long)u * (KW + 1) + lane] = pm;
       const int lo = lane * 64;
       unsigned long long want = 0;
       if (k > lo) want = (k - lo >= 64) ? ~0ull : ((1ull << (k - lo)) - 1);
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(256) k_csr_vertex(Plan p, const int64_t *rp, c
   bool fail = false;
   if (lane < KW) {
     const unsigned long long pm = sPM[wv][lane];
-    p.pm[(long long)v * KW + lane] = pm;
+    p.pm[(long long)v * (KW + 1) + lane] = pm;
     const int lo = lane * 64;
     unsigned long long want = 0;
     if (k > lo) want = (k - lo >= 64) ? ~0ull : ((1ull << (k - lo)) - 1);
@@ -221,7 +222,23 @@ __global__ void __launch_bounds__(256) k_csr_edge(Plan p, const int64_t *rp, con
     const int u = p.src[i], v = ci[i];
     if (FIRST || p.touched[cur][u] || p.touched[cur][v]) {
       tested = u < v;
-      const int cu = colour[u], cv = colour[v];
+      // each endpoint's record: its presence mask, then its colour
+      const uint64_t *ru = p.pm + (long long)u * (KW + 1), *rv = p.pm + (long long)v * (KW + 1);
+      unsigned long long mu[KW + 1], mv[KW + 1];
+      if constexpr (KW == 1) {
+        const ulonglong2 a = *(const ulonglong2 *)ru, c = *(const ulonglong2 *)rv;
+        mu[0] = a.x;
+        mu[1] = a.y;
+        mv[0] = c.x;
+        mv[1] = c.y;
+      } else {
+#pragma unroll
+        for (int j = 0; j <= KW; ++j) {
+          mu[j] = ru[j];
+          mv[j] = rv[j];
+        }
+      }
+      const int cu = (int)mu[KW], cv = (int)mv[KW];
       unsigned long long need[KW];
       bool fail = false;
 #pragma unroll
@@ -230,7 +247,7 @@ __global__ void __launch_bounds__(256) k_csr_edge(Plan p, const int64_t *rp, con
         need[j] = k > lo ? ((k - lo >= 64) ? ~0ull : ((1ull << (k - lo)) - 1)) : 0ull;
         if ((cu >> 6) == j) need[j] &= ~(1ull << (cu & 63));
         if ((cv >> 6) == j) need[j] &= ~(1ull << (cv & 63));
-        fail |= (need[j] & ~(p.pm[(long long)u * KW + j] & p.pm[(long long)v * KW + j])) != 0;
+        fail |= (need[j] & ~(mu[j] & mv[j])) != 0;
       }
       if (!fail) {
         // merge the sorted rows; collect classes of common alive neighbours

@@ -93,7 +93,8 @@ struct Plan {
   uint64_t *fb;      // [n*Rmax] MFMA count path: fail bits of the pairs of a pass
   int32_t *src;      // [nnz] csr: row of every entry
   uint8_t *efail;    // [nnz] csr: entry failed the edge test this pass
-  uint64_t *pm;      // [n*KW] csr: classes holding an alive neighbour of each vertex
+  uint64_t *pm;      // [n*(KW+1)] csr: per vertex the KW words of classes holding an alive
+                     // neighbour, then its colour (one record, one gather per endpoint)
   int n, k, Rmax, nchunks;
   long long Tmax;    // Rmax*(Rmax-1)/2
 };
