@@ -314,6 +314,22 @@ def test_csr_sparse_generator_graphs(kz):
         check_same(res, ref, vm, em, "sparse%d" % seed)
 
 
+def test_csr_wide_class_sets(kz):
+    """k above 64: the presence masks take 4 or 16 words per vertex."""
+    g = inputs.make_graph([2] * 70, 0.9, seed=4, gid=0, plant=True)   # k = 70, cascades
+    adj, colour = g.dense()
+    rp, ci = inputs.dense_to_csr(adj)
+    ref = kernelize_csr(rp, ci, colour, 70)
+    res, vm, em = run_csr(kz, rp, ci, colour, 70, "k70")
+    check_same(res, ref, vm, em, "k70")
+    assert ref["rounds"] >= 1
+    for seed, (n, k, m) in enumerate([(3000, 100, 40000), (4000, 300, 80000)]):
+        sg = inputs.make_sparse(n, k, m, seed=seed + 7)
+        ref = kernelize_csr(sg.row_ptr, sg.col_idx, sg.colour, k)
+        res, vm, em = run_csr(kz, sg.row_ptr, sg.col_idx, sg.colour, k, "wide%d" % k)
+        check_same(res, ref, vm, em, "wide%d" % k)
+
+
 def test_workspace_too_small(kz):
     adj = torch.zeros((10, 10), dtype=torch.uint8, device=DEV)
     colour = torch.zeros(10, dtype=torch.int32, device=DEV)
