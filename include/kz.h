@@ -304,10 +304,12 @@ void kz_server_destroy(kz_server *srv);
  * per launch; off by default. */
 typedef enum {
   KZ_KERNEL_SETUP = 0,   /* header, colour count, layout, partition, state init */
-  KZ_KERNEL_PACK = 1,    /* input -> class-partitioned bit rows               */
-  KZ_KERNEL_VERTEX = 2,  /* vertex colour-index test                          */
-  KZ_KERNEL_EDGE = 3,    /* edge colour-index test (tiles)                    */
-  KZ_KERNEL_APPLY = 4,   /* copy changed tiles into the state                 */
+  KZ_KERNEL_PACK = 1,    /* dense input -> class-partitioned bit rows         */
+  KZ_KERNEL_VERTEX = 2,  /* vertex colour-index test (CSR pass 1: also the
+                            validation sweep over the rows)                   */
+  KZ_KERNEL_EDGE = 3,    /* edge colour-index test (tiles / CSR entries)      */
+  KZ_KERNEL_APPLY = 4,   /* changed tiles into the state / failed CSR entries
+                            cleared                                           */
   KZ_KERNEL_UNPACK = 5,  /* bit rows -> output masks                          */
   KZ_KERNEL_COUNT = 6
 } kz_kernel;
