@@ -330,6 +330,49 @@ def test_csr_wide_class_sets(kz):
         check_same(res, ref, vm, em, "wide%d" % k)
 
 
+def test_repeated_calls_same_buffers(kz):
+    """Calls with the same arguments again and again (workspace, outputs and
+    context reused, eager work on the stream and a synchronisation in
+    between) each give the oracle's result: cascades, dense input, the MFMA
+    edge path."""
+    from paper_2212_00574_amd import binding as b
+    cases = [("bitset", [100] * 5, 0.12, False, b.KZ_EDGE_BITSET),
+             ("bitset", [300] * 10, 0.6, True, b.KZ_EDGE_BITSET),
+             ("dense", [60] * 6, 0.2, False, b.KZ_EDGE_BITSET),
+             ("bitset", [130, 70, 90, 64], 0.3, False, b.KZ_EDGE_MFMA_I8)]
+    try:
+        for ci, (fmt, sizes, p, plant, path) in enumerate(cases):
+            kz.set_edge_path(path)
+            g = inputs.make_graph(sizes, p, seed=11, gid=ci, plant=plant)
+            k = len(sizes)
+            if fmt == "bitset":
+                rows, col, lay = g.bitset()
+                ref = kernelize_bitset(rows, col, k)
+                t_rows = torch.from_numpy(rows.view(np.int64)).to(DEV)
+                graph, colour = b.graph_bitset(t_rows), torch.from_numpy(col).to(DEV)
+                vmask = torch.empty(lay.n, dtype=torch.uint8, device=DEV)
+                emask = torch.empty_like(t_rows)
+            else:
+                adj, col = g.dense()
+                ref = kernelize_dense(adj, col, k)
+                t_adj = torch.from_numpy(adj).to(DEV)
+                graph, colour = b.graph_dense(t_adj), torch.from_numpy(col).to(DEV)
+                vmask = torch.empty(len(col), dtype=torch.uint8, device=DEV)
+                emask = torch.empty_like(t_adj)
+            for rep in range(4):
+                vmask.fill_(7)
+                emask.fill_(3)
+                torch.cuda.synchronize()
+                res = kz.run(graph, colour, k, vmask, emask)
+                torch.cuda.synchronize()
+                em = emask.cpu().numpy()
+                if fmt == "bitset":
+                    em = em.view(np.uint64)
+                check_same(res, ref, vmask.cpu().numpy(), em, "%s case %d call %d" % (fmt, ci, rep))
+    finally:
+        kz.set_edge_path(b.KZ_EDGE_BITSET)
+
+
 def test_workspace_too_small(kz):
     adj = torch.zeros((10, 10), dtype=torch.uint8, device=DEV)
     colour = torch.zeros(10, dtype=torch.int32, device=DEV)
