@@ -72,6 +72,18 @@ def test_mfma_config3a_equals_bitset_path(kzm):
     ref.close()
 
 
+def test_mfma_row_limit(kzm):
+    """Rows of more than 2048 words are beyond the MFMA path: the call is
+    refused with KZ_ETOOLARGE before anything is launched."""
+    from paper_2212_00574_amd.binding import KZ_ETOOLARGE
+    k = n = 2049                            # one vertex per class: 2049 words per row
+    rows = torch.zeros((n, k), dtype=torch.int64, device=DEV)
+    col = torch.arange(n, dtype=torch.int32, device=DEV)
+    with pytest.raises(KzError) as err:
+        kzm.kernelize_bitset(rows, col, k)
+    assert err.value.status == KZ_ETOOLARGE
+
+
 def test_edge_path_argument(kzm):
     with pytest.raises(KzError):
         kzm.set_edge_path(7)
