@@ -252,8 +252,10 @@ def bench_batch(args):
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
+    tc0 = time.perf_counter()
     with torch.cuda.graph(graph):
         bk.run(b)
+    capture_ms = (time.perf_counter() - tc0) * 1e3
     for _ in range(args.warmup):
         graph.replay()
     torch.cuda.synchronize()
@@ -330,6 +332,7 @@ def bench_batch(args):
             "value": one_gps, "unit": "graphs/s", "seconds": one_by_one_s,
             "what": "kz_kernelize per graph on the same device-resident inputs"},
         "batched_over_one_by_one": None if one_gps is None else value / one_gps,
+        "graph_capture_ms": round(capture_ms, 3),
         "roofline": {"kernel": "k_batch", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                      "traffic": traffic_from_profile("c4"),
@@ -520,6 +523,22 @@ def main():
             raise SystemExit("the MFMA edge path applies to dense and bit-row input")
         from paper_2212_00574_amd.binding import KZ_EDGE_MFMA_I8
         kz.set_edge_path(KZ_EDGE_MFMA_I8)
+    # the input's copy to the device, timed on its own (the timed steps start
+    # with the input resident; the library takes device buffers only)
+    host_in = [w["colour"]] + ([w["adj"]] if w["fmt"] == "dense" else
+                               [w["rp"], w["ci"]] if w["fmt"] == "csr" else [w["rows"]])
+    h2d_bytes = int(sum(a.nbytes for a in host_in))
+    e_h0, e_h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pinned = [torch.from_numpy(np.ascontiguousarray(a).view(np.uint8).reshape(-1)).pin_memory() for a in host_in]
+    dev_copy = [torch.empty(t.shape, dtype=torch.uint8, device=dev) for t in pinned]
+    torch.cuda.synchronize()
+    e_h0.record()
+    for d, t in zip(dev_copy, pinned):
+        d.copy_(t, non_blocking=True)
+    e_h1.record()
+    torch.cuda.synchronize()
+    h2d_ms = e_h0.elapsed_time(e_h1)
+    del pinned, dev_copy
     colour = torch.from_numpy(w["colour"]).to(dev)
     k = w["k"]
     if w["fmt"] == "dense":
@@ -559,6 +578,14 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = res["edge_tests"] / (ms_per_step / 1e3)
+    # 20 steps timed one by one with HIP events on the stream: median and min
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for e0, e1 in ev:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    per_step = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
     print("timed %d steps: %.4f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
 
     # per-kernel times with HIP events on the launch stream (same workload, same launches)
@@ -634,7 +661,18 @@ def main():
 
     cpu = None
     check = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c3a":
+        # the whole graph would keep the oracle busy for minutes: time it on a
+        # smaller instance of the same recipe instead (k=20, p=0.3)
+        from paper_2212_00574_amd import inputs
+        gs = inputs.make_graph([200] * 20, 0.3, seed=args.seed, gid=1, shuffle=False)
+        rows_s, col_s, _ = gs.bitset()
+        sample = dict(fmt="bitset", rows=rows_s, colour=col_s, k=20)
+        ores, _, secs, load_s = cpu_baseline(sample)
+        cpu = {"value": ores["edge_tests"] / secs, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
+               "sample": "a smaller instance of the recipe (k=20 x 200, p=0.3), one oracle fixpoint "
+                         "(%d edge tests, %.1f s; ingest %.1f s excluded)" % (ores["edge_tests"], secs, load_s)}
+    elif not args.no_cpu_baseline:
         ores, (ovm, oem), secs, load_s = cpu_baseline(w)
         cpu = {"value": ores["edge_tests"] / secs, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
                "sample": "the whole %s graph, one oracle fixpoint (%d edge tests, %.1f s; ingest %.1f s excluded)"
@@ -667,6 +705,11 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {name: round(t[0] / psteps, 5) for name, t in times.items()},
+        "step_ms_median": round(per_step[len(per_step) // 2], 5),
+        "step_ms_min": round(per_step[0], 5),
+        "input_edges_per_s": res["input_edges"] / (ms_per_step / 1e3),
+        "h2d": {"bytes": h2d_bytes, "ms": round(h2d_ms, 4),
+                "what": "the input's copy from pinned host memory, outside the timed steps"},
         "oracle_equal": check,
     }
     assert m_check == res["input_edges"], (m_check, res["input_edges"])
