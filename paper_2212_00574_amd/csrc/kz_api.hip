@@ -646,7 +646,7 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
     const uint64_t *src = first ? in_rows : cur;
     {
       ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
-      kzi::launch_vertex_pass(p, scls, src, cur, pass, first, s);
+      kzi::launch_vertex_pass(p, scls, src, cur, pass, first, dense ? 0 : g->row_words, s);
     }
     {
       ProfScope t(ctx, KZ_KERNEL_EDGE, s);

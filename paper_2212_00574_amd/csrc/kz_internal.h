@@ -20,6 +20,7 @@ constexpr int kRankChunk = 256;    // vertices per stable-partition chunk
 constexpr int kPackLdsWords = 8192;  // dense pack: row assembled in LDS up to this many words
 constexpr int kSetupThreads = 1024;  // the single setup workgroup
 constexpr int kVertexLdsClasses = 2048;  // vertex pass keeps class offsets in LDS up to this k
+constexpr int kVfRows = 16;  // rows per workgroup of the pass-1 vertex test (4 per wave)
 constexpr int kSetupLdsClasses = 4096;  // class histogram kept in LDS up to this k
 
 constexpr int kCtrSlots = 32;      // spread of the per-pass counters
@@ -114,14 +115,15 @@ struct WsSizes {
 // into `dst` and its edge pass rewrites the tiles that change, so `dst` ends
 // up holding the state after round 1.  Later passes read the state `cur`,
 // write changed tiles into `scratch`, and the apply pass copies them back
-// into `cur`.
+// into `cur`.  `row_words` of the vertex pass: the caller's row width for
+// bit-row input, 0 for dense input (the width the setup pass computed).
 enum SetupMode : int { SETUP_BITSET = 0, SETUP_DENSE = 1, SETUP_CSR = 2 };
 void launch_setup(const Plan &p, const int *colour, int row_words, SetupMode mode, hipStream_t s);
 void launch_rank(const Plan &p, const int *colour, hipStream_t s);
 void launch_pack_dense(const Plan &p, const uint8_t *adj, const int *colour, uint64_t *dst,
                        hipStream_t s);
 void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uint64_t *dst, int pass,
-                        bool first, hipStream_t s);
+                        bool first, int row_words, hipStream_t s);
 void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first,
                       hipStream_t s);
 // The int8 MFMA count path of the edge test: fail bits of every pair (into

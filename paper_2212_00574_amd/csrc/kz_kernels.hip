@@ -178,6 +178,7 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
   // each wave, then a scan of the wave totals
   constexpr int kSetupWaves = kSetupThreads / kWave;
   const int lane = t & 63, wv = t >> 6;
+  int my_s = 0, my_c0 = 0, my_w0 = 0;  // class t's size and offsets, kept for the block table
   for (int base = 0; base < k; base += kSetupThreads) {
     const int c = base + t;
     int s = 0;
@@ -211,9 +212,15 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
     }
     __syncthreads();
     if (c < k) {
+      const int c0 = sa[wv] + ia - a, w0 = sb[wv] + ib - b;
       p.counts[c] = a;
-      p.coff[c] = sa[wv] + ia - a;
-      p.soff[c] = sb[wv] + ib - b;
+      p.coff[c] = c0;
+      p.soff[c] = w0;
+      if (base == 0) {
+        my_s = a;
+        my_c0 = c0;
+        my_w0 = w0;
+      }
     }
     __syncthreads();
   }
@@ -232,8 +239,9 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
   if (s_bad_layout) return;
   // each thread reads back only the entries it wrote itself above
   for (int c = t; c < k; c += kSetupThreads) {
-    const int s = p.counts[c];
-    const int w0 = p.soff[c], c0 = p.coff[c];
+    const bool mine = c == t;
+    const int s = mine ? my_s : p.counts[c];
+    const int w0 = mine ? my_w0 : p.soff[c], c0 = mine ? my_c0 : p.coff[c];
     for (int b = 0; 64 * b < s; ++b) {
       p.bcls[w0 + b] = c;
       p.bstart[w0 + b] = c0 + 64 * b;
@@ -303,17 +311,15 @@ __global__ void __launch_bounds__(256) k_pack_dense(Plan p, const uint8_t *adj, 
 
 // ---------------------------------------------------------------- passes
 
-// Vertex test.  A workgroup takes 64 slots (lane v = slot 64*block + v) and
-// its 4 waves split the classes (wave w walks c = w, w+4, ...).  For each
-// processed row it also refreshes the first-word matrix F[c][v] (the first
-// word of row v's class-c segment), which the edge pass stages from.  Pass 1
-// processes and validates every row and first streams the block's 64 input
-// rows into `dst` (the edge pass then only rewrites tiles that change);
-// later passes process only alive vertices touched by the previous round.
-// Also resets the bookkeeping the edge pass of this pass fills.
-template <bool FIRST>
+// Vertex test of the passes after the first.  A workgroup takes 64 slots
+// (lane v = slot 64*block + v) and its 4 waves split the classes (wave w
+// walks c = w, w+4, ...); only alive vertices touched by the previous round
+// are tested.  For each tested row it also refreshes the first-word matrix
+// F[c][v] (the first two words of row v's class-c segment), which the edge
+// pass stages from.  Also resets the bookkeeping the edge pass of this pass
+// fills.
 __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const uint64_t *__restrict__ src,
-                                                uint64_t *__restrict__ dst, int pass) {
+                                                int pass) {
   Hdr *h = p.hdr;
   if (stage1_bad(h)) return;
   const int R = h->R, n = p.n, k = p.k;
@@ -328,111 +334,44 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
     if (gt < kCtrSlots * 4) h->ctr(nxt, gt / 4, gt % 4) = 0;
   }
   __shared__ int sFail[kWave];
-  __shared__ int sOff[2][kVertexLdsClasses + 1];  // coff, soff
+  __shared__ int sOff[kVertexLdsClasses + 1];  // soff
   const bool lds_off = k <= kVertexLdsClasses;
   const int v0 = blockIdx.x * kWave;
   if (tid < kWave) sFail[tid] = 0;
   if (lds_off)
-    for (int c = tid; c <= k; c += 256) {
-      sOff[0][c] = p.coff[c];
-      sOff[1][c] = p.soff[c];
-    }
-  if (FIRST) {
-    // the block's rows are contiguous: stream them into the output state
-    const long long base = (long long)v0 * R;
-    const long long cnt = (long long)min(kWave, n - v0) * R;
-    if ((((uintptr_t)(src + base)) | ((uintptr_t)(dst + base))) & 15) {
-      for (long long i = tid; i < cnt; i += 256) dst[base + i] = src[base + i];
-    } else {
-      const uint4 *s4 = (const uint4 *)(src + base);
-      uint4 *d4 = (uint4 *)(dst + base);
-      const long long c2 = cnt / 2;
-      long long i = tid;
-      for (; i + 7 * 256 < c2; i += 8 * 256) {
-        uint4 r[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) r[q] = s4[i + q * 256];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) d4[i + q * 256] = r[q];
-      }
-      for (; i < c2; i += 256) d4[i] = s4[i];
-      if ((cnt & 1) && tid == 0) dst[base + cnt - 1] = src[base + cnt - 1];
-    }
-  }
+    for (int c = tid; c <= k; c += 256) sOff[c] = p.soff[c];
   __syncthreads();
   const int v = v0 + lane;
-  const bool inr = v < n;
-  const bool active = inr && (FIRST || (p.valive[v] && p.touched[cur][v]));
+  const bool active = v < n && p.valive[v] && p.touched[cur][v];
   if (__ballot(active)) {
-    const int vc = inr ? v : v0;  // clamped row for inactive lanes
+    const int vc = active ? v : v0;  // clamped row for inactive lanes
     const uint64_t *row = src + (long long)vc * R;
     const int cv = scls[vc];
     bool fail = false;
-    int pr = P_NONE;
     // the wave's classes c = wid, wid+4, ... in groups of kVG: all loads of
     // a group go out before any of them is used
     constexpr int kVG = 4;
     for (int cg = wid; cg < k; cg += 4 * kVG) {
-      unsigned long long x0[kVG], x1[kVG], xe[kVG];
+      unsigned long long x0[kVG], x1[kVG];
 #pragma unroll
       for (int g = 0; g < kVG; ++g) {
         const int c = cg + 4 * g;
-        const int w0 = c < k ? (lds_off ? sOff[1][c] : p.soff[c]) : 0;
-        const int w1 = c < k ? (lds_off ? sOff[1][c + 1] : p.soff[c + 1]) : 0;
+        const int w0 = c < k ? (lds_off ? sOff[c] : p.soff[c]) : 0;
+        const int w1 = c < k ? (lds_off ? sOff[c + 1] : p.soff[c + 1]) : 0;
         x0[g] = w1 > w0 ? row[w0] : 0ull;
         x1[g] = w1 - w0 >= 2 ? row[w0 + 1] : 0ull;
-        xe[g] = FIRST && w1 - w0 >= 3 ? row[w1 - 1] : 0ull;  // last word (pass 1 checks its padding)
       }
 #pragma unroll
       for (int g = 0; g < kVG; ++g) {
         const int c = cg + 4 * g;
         if (c >= k) break;
-        const int w0 = lds_off ? sOff[1][c] : p.soff[c];
-        const int w1 = lds_off ? sOff[1][c + 1] : p.soff[c + 1];
+        const int w0 = lds_off ? sOff[c] : p.soff[c];
+        const int w1 = lds_off ? sOff[c + 1] : p.soff[c + 1];
         ulonglong2 *Fcv = (ulonglong2 *)p.F + ((long long)c * n + v);
-        if (w1 == w0) {  // empty class: no neighbour possible
-          if (active) *Fcv = make_ulonglong2(0ull, 0ull);
-          fail |= c != cv;
-          continue;
-        }
-        const unsigned long long x = x0[g];
-        if (active) *Fcv = make_ulonglong2(x, x1[g]);
-        const int cc0 = lds_off ? sOff[0][c] : p.coff[c];
-        const int s = (lds_off ? sOff[0][c + 1] : p.coff[c + 1]) - cc0;
-        const unsigned long long last = w1 - w0 >= 3 ? xe[g] : (w1 - w0 == 2 ? x1[g] : x);
-        if (c == cv) {
-          if (FIRST && active) {
-            // own segment: must be empty in the input, padding included
-            unsigned long long any = x | x1[g] | last;
-#pragma unroll 4
-            for (int w = w0 + 2; w < w1 - 1; ++w) any |= row[w];
-            if (any) {
-              // classify what is there
-              const int jv = v - cc0;
-              for (int w = w0; w < w1; ++w) {
-                unsigned long long y = row[w];
-                if (w == w1 - 1 && (s & 63)) {
-                  if (y >> (s & 63)) pr = max(pr, P_EINVAL);
-                  y &= (1ull << (s & 63)) - 1;
-                }
-                while (y) {
-                  const int b = __builtin_ctzll(y);
-                  y &= y - 1;
-                  const int tslot = cc0 + (w - w0) * 64 + b;
-                  if (tslot == v) {
-                    pr = max(pr, P_ESELFLOOP);
-                  } else {
-                    const uint64_t z = src[(long long)tslot * R + w0 + (jv >> 6)];
-                    pr = max(pr, ((z >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL : (int)P_EASYM);
-                  }
-                }
-              }
-            }
-          }
-          continue;
-        }
-        if (FIRST && active && (s & 63) && (last >> (s & 63))) pr = max(pr, P_EINVAL);
-        bool nz = (x | x1[g]) != 0;
+        if (active) *Fcv = make_ulonglong2(x0[g], x1[g]);
+        if (c == cv) continue;
+        // an empty class has no words: no neighbour possible
+        bool nz = (x0[g] | x1[g]) != 0;
         if (active && !nz)
           for (int w = w0 + 2; w < w1; ++w)
             if (row[w]) {
@@ -442,19 +381,205 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
         fail |= !nz;
       }
     }
-    if (pr) atomicMax(&h->prio, pr);
     if (fail && active) atomicOr(&sFail[lane], 1);
   }
   __syncthreads();
   if (wid != 0 || !__ballot(active)) return;
   const bool fail = active && sFail[lane];
-  if (active) {
-    if (FIRST)
-      p.valive[v] = fail ? 0 : 1;
-    else if (fail)
-      p.valive[v] = 0;
-  }
+  if (fail) p.valive[v] = 0;
   const int nf = wave_sum(fail ? 1 : 0);
+  if (lane == 0 && nf) atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 0), (unsigned long long)nf);
+}
+
+// Pass-1 vertex test fused with the copy of the input into the output state.
+// A workgroup takes kVfRows slots; wave w takes rows v0+w, v0+w+4, ... and lane l
+// holds word 64*j+l of a row, so every load is one contiguous 512-byte
+// piece, stored to `dst` as it is tested.  Per piece the lane knows its
+// word's class, the word's place in that class's segment and its valid bits;
+// the lanes that start a class in the piece ("heads") see, through a wave
+// ballot of the nonzero words, whether their class has a bit in this row.  A
+// class that runs on into the next piece carries its verdict there.  A row
+// fails when a class other than its own has no bit, or when some class is
+// empty.  Words of the row's own class must be zero (a nonzero one is
+// classified: self-loop, edge inside a class, or asymmetry), and so must
+// padding bits past a class's size.  The first two words of every segment
+// fill the first-word matrix F.  All loads of a piece are independent of
+// each other, so one memory round serves the copy, the test and F.  Rh > 0:
+// the caller's row width (bit-row input; a layout whose classes do not add up
+// to it is flagged by the setup pass and nothing is written); 0: the setup
+// pass's.
+__global__ void __launch_bounds__(256) k_vertex_first(Plan p, const int *scls, const uint64_t *__restrict__ src,
+                                                      uint64_t *__restrict__ dst, int Rh) {
+  Hdr *h = p.hdr;
+  const int n = p.n, k = p.k;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int kRows = kVfRows / 4;  // rows per wave
+  __shared__ int sOff[2][kVertexLdsClasses + 1];  // coff, soff
+  const bool lds_off = k <= kVertexLdsClasses;
+  const int v0 = blockIdx.x * kVfRows;
+  const int nrows = min(kVfRows, n - v0);
+  const int R = Rh > 0 ? Rh : h->R;
+  const int nch = (R + kWave - 1) / kWave;
+  // Every load of the first piece goes out before any is used: indices are
+  // clamped into range (the values of clamped lanes and rows are unused), so
+  // no load sits behind a branch.
+  const int Rl = max(R - 1, 0);  // last word (a failed setup pass leaves R = 0)
+  auto load_rows = [&](int ch, unsigned long long (&x)[kRows]) {
+    const int w = min(ch * kWave + lane, Rl);
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const int r = min(wid + 4 * i, nrows - 1);
+      x[i] = src[(long long)(v0 + r) * R + w];
+    }
+  };
+  // per-piece word facts: class of the word and of its neighbours two back
+  // and one ahead, and the word's valid bits
+  struct Meta {
+    int c, cm1, cm2, cp1, bl;
+  };
+  auto load_meta = [&](int ch) {
+    const int w = ch * kWave + lane;
+    Meta m;
+    m.c = p.bcls[min(w, Rl)];
+    m.cm1 = p.bcls[min(max(w - 1, 0), Rl)];
+    m.cm2 = p.bcls[min(max(w - 2, 0), Rl)];
+    m.cp1 = p.bcls[min(w + 1, Rl)];
+    m.bl = p.blen[min(w, Rl)];
+    return m;
+  };
+  const int c0 = min(tid, k);
+  const int off0 = p.coff[c0], soff0 = p.soff[c0];
+  const int sc = scls[min(v0 + (lane & (kVfRows - 1)), n - 1)];  // class of slot v0+lane
+  unsigned long long x[kRows];
+  load_rows(0, x);
+  Meta m = load_meta(0);
+  if (lds_off) {
+    // every thread stores (threads past k repeat entry k), so the wait for
+    // these loads is not behind a branch
+    sOff[0][c0] = off0;
+    sOff[1][c0] = soff0;
+    for (int c = tid + 256; c <= k; c += 256) {
+      sOff[0][c] = p.coff[c];
+      sOff[1][c] = p.soff[c];
+    }
+  }
+  if (stage1_bad(h)) return;
+  // one wait for every load above (vmcnt(0)), so that no use further down
+  // waits again -- such a wait would also wait for the stores issued since
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  const int cur = 1, nxt = 0;
+  {
+    const long long gt = (long long)blockIdx.x * blockDim.x + tid;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = gt; i < n; i += stride) p.touched[nxt][i] = 0;
+    for (long long i = gt; i < R; i += stride) p.btouched[nxt][i] = 0;
+    if (gt == 0) h->tile_count = 0;
+    if (gt < kCtrSlots * 4) h->ctr(nxt, gt / 4, gt % 4) = 0;
+  }
+  __shared__ int sEmpty;
+  if (tid == 0) sEmpty = 0;
+  __syncthreads();
+  // an empty class leaves every vertex without a neighbour there (a vertex's
+  // own class is never empty); F of an empty class is zero
+  auto empty_class = [&](int c) {
+    sEmpty = 1;
+    for (int r = 0; r < nrows; ++r) {
+      p.F[2 * ((long long)c * n + v0 + r)] = 0ull;
+      p.F[2 * ((long long)c * n + v0 + r) + 1] = 0ull;
+    }
+  };
+  if (lds_off) {
+    for (int c = tid; c < k; c += 256)
+      if (sOff[1][c] == sOff[1][c + 1]) empty_class(c);
+  } else {
+    for (int c = tid; c < k; c += 256)
+      if (p.soff[c] == p.soff[c + 1]) empty_class(c);
+  }
+  __syncthreads();
+  const bool any_empty = sEmpty != 0;
+  unsigned long long failRows = 0, carryRows = 0;
+  int pr = P_NONE;
+  // one piece: copy, test, F (the first piece is peeled off the loop so that
+  // its values, already waited for, are not waited for again)
+  auto piece = [&](int ch) {
+    const int w = ch * kWave + lane;
+    const bool valid = w < R;
+    // the word's class, its place in the class's segment (0, 1, or 2 for
+    // later), its valid bits, and whether the segment ends with it
+    const int cw = valid ? m.c : -1;
+    const int off = !valid ? 2 : (w < 1 || m.cm1 != m.c) ? 0 : (w < 2 || m.cm2 != m.c) ? 1 : 2;
+    const int bl = valid ? m.bl : 64;
+    const bool ends = !valid || w + 1 >= R || m.cp1 != m.c;
+    const bool head = valid && (lane == 0 || off == 0);
+    const unsigned long long heads = __ballot(head);
+    // lanes of my class in this piece: from me up to the next head
+    const unsigned long long above = lane == 63 ? 0ull : heads >> (lane + 1);
+    const int nh = above ? lane + 1 + __builtin_ctzll(above) : 64;
+    const unsigned long long mine = (nh == 64 ? ~0ull : (1ull << nh) - 1) & ~((1ull << lane) - 1);
+    const bool cont0 = ch > 0 && __shfl(off, 0, kWave) != 0;  // lane 0's class began before
+    const int lastLane = min(kWave, R - ch * kWave) - 1;
+    const unsigned long long lastHead = 1ull << (63 - __builtin_clzll(heads));
+    const bool contL = __shfl(ends ? 0 : 1, lastLane, kWave) != 0;  // the last class runs on
+    unsigned bad_rows = 0;  // rows with a bit in this lane's word of their own class
+#pragma unroll
+    for (int i = 0; i < kRows; ++i) {
+      const int r = wid + 4 * i;
+      if (r >= nrows) continue;
+      const int v = v0 + r;
+      const unsigned long long xi = x[i];
+      const int cvr = __builtin_amdgcn_readlane(sc, r);
+      if (valid) {
+        dst[(long long)v * R + w] = xi;
+        if (off < 2) p.F[2 * ((long long)cw * n + v) + off] = xi;
+        if (off == 0 && ends) p.F[2 * ((long long)cw * n + v) + 1] = 0ull;
+        if (bl < 64 && (xi >> bl)) pr = max(pr, (int)P_EINVAL);
+      }
+      const unsigned long long nz = __ballot(valid && xi != 0);
+      unsigned long long H = __ballot(head && (nz & mine) != 0);
+      if (cont0 && ((carryRows >> i) & 1)) H |= 1ull;
+      const unsigned long long own = __ballot(head && cw == cvr);
+      const unsigned long long defer = contL ? lastHead : 0ull;
+      if (heads & ~H & ~own & ~defer) failRows |= 1ull << i;
+      carryRows = (carryRows & ~(1ull << i)) | ((contL && (H & lastHead)) ? 1ull << i : 0ull);
+      if (valid && cw == cvr && xi) bad_rows |= 1u << i;
+    }
+    // bits inside a row's own class (invalid input): classify them
+    while (bad_rows) {
+      const int i = __builtin_ctz(bad_rows);
+      bad_rows &= bad_rows - 1;
+      const int v = v0 + wid + 4 * i;
+      const unsigned long long xi = src[(long long)v * R + w];
+      unsigned long long y = bl < 64 ? xi & ((1ull << bl) - 1) : xi;
+      const int jv = v - (lds_off ? sOff[0][cw] : p.coff[cw]);
+      const int wv = (lds_off ? sOff[1][cw] : p.soff[cw]) + (jv >> 6);
+      const int b0 = p.bstart[w];
+      while (y) {
+        const int b = __builtin_ctzll(y);
+        y &= y - 1;
+        const int tslot = b0 + b;
+        if (tslot == v) {
+          pr = max(pr, (int)P_ESELFLOOP);
+        } else {
+          const uint64_t z = src[(long long)tslot * R + wv];
+          pr = max(pr, ((z >> (jv & 63)) & 1ull) ? (int)P_EILLEGAL : (int)P_EASYM);
+        }
+      }
+    }
+  };
+  piece(0);
+  for (int ch = 1; ch < nch; ++ch) {
+    load_rows(ch, x);
+    m = load_meta(ch);
+    piece(ch);
+  }
+  if (pr) atomicMax(&h->prio, pr);
+  // lane i < kRows publishes row wid + 4i
+  const int r = wid + 4 * lane;
+  const bool fail = any_empty || ((failRows >> (lane & (kRows - 1))) & 1);
+  const bool mine_row = lane < kRows && r < nrows;
+  if (mine_row) p.valive[v0 + r] = fail ? 0 : 1;
+  const int nf = wave_sum(mine_row && fail ? 1 : 0);
   if (lane == 0 && nf) atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 0), (unsigned long long)nf);
 }
 
@@ -915,12 +1040,13 @@ void launch_pack_dense(const Plan &p, const uint8_t *adj, const int *colour, uin
 }
 
 void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uint64_t *dst, int pass,
-                        bool first, hipStream_t s) {
+                        bool first, int row_words, hipStream_t s) {
   const dim3 grid(grid_for(p.n, kWave, 1LL << 30));  // 64 slots per workgroup
   if (first)
-    hipLaunchKernelGGL(k_vertex<true>, grid, dim3(256), 0, s, p, scls, src, dst, pass);
+    hipLaunchKernelGGL(k_vertex_first, dim3(grid_for(p.n, kVfRows, 1LL << 30)), dim3(256), 0, s, p, scls, src, dst,
+                       row_words);
   else
-    hipLaunchKernelGGL(k_vertex<false>, grid, dim3(256), 0, s, p, scls, src, dst, pass);
+    hipLaunchKernelGGL(k_vertex, grid, dim3(256), 0, s, p, scls, src, pass);
 }
 
 void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first, hipStream_t s) {
