@@ -373,6 +373,91 @@ def test_repeated_calls_same_buffers(kz):
         kz.set_edge_path(b.KZ_EDGE_BITSET)
 
 
+# ------------------------------------------------- rows wider than 64 words
+# The pass-1 vertex test reads a row in 64-word pieces, one word per lane; a
+# class whose segment runs on past a piece carries its verdict into the next.
+def wide_graph(seed=7):
+    """k = 3, sizes 100, 8200, 50: class 1's segment (129 words, words 2..130)
+    crosses all three pieces of a row.  Hand-placed vertices of classes 0 and
+    2 have their only class-1 neighbour in the first, second or third piece
+    (or none), each closed into a triangle so that it can survive."""
+    sizes = [100, 8200, 50]
+    lay = inputs.class_layout(sizes)
+    n = lay.n
+    o = [int(x) for x in lay.offsets]
+    rng = np.random.default_rng(seed)
+    a = np.zeros((n, n), dtype=bool)
+    for ca, cb, m in ((0, 1, 6000), (0, 2, 120), (1, 2, 3000)):
+        a[rng.integers(o[ca], o[ca + 1], m), rng.integers(o[cb], o[cb + 1], m)] = True
+    crafted = [0, 1, 2, 3, o[2], o[2] + 1]
+    a[crafted, :] = False
+    a[:, crafted] = False
+    a |= a.T
+    # (class 0, class 1, class 2) triangles; class-1 slot 8150 is in word 129
+    # (third piece), 5000 in word 80 and 4032 in word 65 (second piece), 10 in
+    # word 2 (first piece), 8199 is the last valid bit of word 130
+    tri = [(0, o[1] + 8150, o[2] + 5), (1, o[1] + 5000, o[2] + 6), (3, o[1] + 10, o[2] + 8),
+           (50, o[1] + 8199, o[2] + 0), (51, o[1] + 4032, o[2] + 1)]
+    for x, y, z in tri:
+        a[x, y] = a[y, x] = a[x, z] = a[z, x] = a[y, z] = a[z, y] = True
+    a[2, o[2] + 7] = a[o[2] + 7, 2] = True   # slot 2: no class-1 neighbour at all
+    return sizes, lay, a
+
+
+def test_rows_across_pieces(kz):
+    sizes, lay, a = wide_graph()
+    col = inputs.sorted_colour(sizes)
+    rows = inputs.pack_rows(a, lay)
+    ref = kernelize_bitset(rows, col, 3)
+    res, vm, em = run_bitset(kz, rows, col, 3, "wide")
+    check_same(res, ref, vm, em, "wide bitset")
+    o2 = int(lay.offsets[2])
+    assert list(vm[[0, 1, 2, 3, o2, o2 + 1]]) == [1, 1, 0, 1, 1, 1]
+    adj = a.astype(np.uint8)
+    refd = kernelize_dense(adj, col, 3)
+    res, vm, em = run_dense(kz, adj, col, 3, "wide")
+    check_same(res, refd, vm, em, "wide dense")
+    rp, ci = inputs.dense_to_csr(adj)
+    refc = kernelize_csr(rp, ci, col, 3)
+    res, vm, em = run_csr(kz, rp, ci, col, 3, "wide")
+    check_same(res, refc, vm, em, "wide csr")
+
+
+def test_class_starting_on_a_piece_boundary(kz):
+    # words 64 + 3 + 63: class 1 starts at word 64, class 2 runs into the third piece
+    g = inputs.make_graph([4096, 130, 4000], 0.004, seed=5, gid=1, plant=True, shuffle=False)
+    rows, col, lay = g.bitset()
+    assert lay.R == 130 and int(lay.segoff[1]) == 64
+    ref = kernelize_bitset(rows, col, 3)
+    res, vm, em = run_bitset(kz, rows, col, 3, "boundary")
+    check_same(res, ref, vm, em, "boundary bitset")
+
+
+def test_validation_in_later_pieces(kz):
+    sizes, lay, a = wide_graph()
+    col = inputs.sorted_colour(sizes)
+    rows = inputs.pack_rows(a, lay)
+    o1 = int(lay.offsets[1])
+    one = np.uint64(1)
+    cases = {}
+    bad = rows.copy(); bad[0, 130] |= one << np.uint64(20)           # padding of class 1 (8 valid bits)
+    cases["padding"] = bad
+    u = o1 + 8150                                                     # word 129, bit 22 of its own class
+    bad = rows.copy(); bad[u, 129] |= one << np.uint64(22)            # self-loop in the third piece
+    cases["loop"] = bad
+    bad = rows.copy(); bad[u, 129] |= one << np.uint64(23)            # intra-class, one direction
+    cases["asym_intra"] = bad
+    v, w = o1 + 5000, o1 + 5001                                       # word 80 (second piece)
+    bad = rows.copy()
+    bad[v, 80] |= one << np.uint64(5001 % 64)
+    bad[w, 80] |= one << np.uint64(5000 % 64)                         # intra-class, both directions
+    cases["intra"] = bad
+    for name, r in cases.items():
+        want = kernelize_bitset(r, col, 3)["status"]
+        got = status_of(kz, lambda: run_bitset(kz, r, col, 3, name))
+        assert want != 0 and got == want, (name, got, want)
+
+
 def test_workspace_too_small(kz):
     adj = torch.zeros((10, 10), dtype=torch.uint8, device=DEV)
     colour = torch.zeros(10, dtype=torch.int32, device=DEV)
