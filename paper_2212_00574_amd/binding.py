@@ -279,6 +279,20 @@ def kz_server_destroy(srv: int) -> None:
 
 
 # ----------------------------------------------------------- tensor helpers
+_RAW_STREAM = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream_handle(stream: torch.cuda.Stream | None, device: torch.device) -> int:
+    """The HIP stream handle to launch on: `stream`'s, else the device's
+    current stream (read without building a Stream object: this is on the
+    per-call path)."""
+    if stream is not None:
+        return stream.cuda_stream
+    if _RAW_STREAM is not None:
+        return _RAW_STREAM(device.index if device.index is not None else torch.cuda.current_device())
+    return torch.cuda.current_stream(device).cuda_stream
+
+
 def _dev_ptr(t: torch.Tensor | None) -> int | None:
     if t is None or t.numel() == 0:
         return None
@@ -352,9 +366,8 @@ class Kernelizer:
         if colour.dtype != torch.int32:
             raise ValueError("colour must be int32")
         ws = self.workspace(graph, k)
-        s = stream if stream is not None else torch.cuda.current_stream(self.device)
         res = kz_kernelize(self.ctx, graph, _dev_ptr(colour), k, ws.data_ptr(), ws.numel(),
-                           _dev_ptr(vmask), _dev_ptr(emask), s.cuda_stream)
+                           _dev_ptr(vmask), _dev_ptr(emask), _stream_handle(stream, self.device))
         if check and res.status != KZ_OK:
             raise KzError(res.status, "kz_kernelize")
         return res.as_dict()
@@ -450,9 +463,8 @@ class BatchKernelizer:
     def run(self, batch: Batch, stream: torch.cuda.Stream | None = None) -> None:
         """Enqueues the batch on the stream (asynchronous)."""
         ws = self.workspace(batch)
-        s = stream if stream is not None else torch.cuda.current_stream(batch.device)
         st = kz_kernelize_batch(self.kz.ctx, *batch.args(), ws.data_ptr(), ws.numel(), *batch.outputs(),
-                                s.cuda_stream)
+                                _stream_handle(stream, batch.device))
         if st != KZ_OK:
             raise KzError(st, "kz_kernelize_batch")
 
