@@ -458,6 +458,30 @@ def test_validation_in_later_pieces(kz):
         assert want != 0 and got == want, (name, got, want)
 
 
+def test_current_and_explicit_streams(kz):
+    """The binding launches on the caller's current stream, or on the one it
+    is given: the input is written on a side stream just before the call,
+    with no synchronisation in between."""
+    g = inputs.make_graph([70, 130, 64, 1, 65], 0.45, seed=3, gid=2, plant=True, shuffle=False)
+    rows, col, lay = g.bitset()
+    ref = kernelize_bitset(rows, col, 5)
+    host = torch.from_numpy(rows.view(np.int64)).pin_memory()
+    colour = torch.from_numpy(col).to(DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for explicit in (False, True):
+        say("stream", "explicit" if explicit else "current")
+        with torch.cuda.stream(side):
+            x = torch.empty(tuple(host.shape), dtype=torch.int64, device=DEV)
+            x.copy_(host, non_blocking=True)
+            if not explicit:
+                vm, em, res = kz.kernelize_bitset(x, colour, 5)
+        if explicit:
+            vm, em, res = kz.kernelize_bitset(x, colour, 5, stream=side)
+        torch.cuda.synchronize()
+        check_same(res, ref, vm.cpu().numpy(), em.cpu().numpy().view(np.uint64), "stream %s" % explicit)
+
+
 def test_workspace_too_small(kz):
     adj = torch.zeros((10, 10), dtype=torch.uint8, device=DEV)
     colour = torch.zeros(10, dtype=torch.int32, device=DEV)
