@@ -60,6 +60,58 @@ __device__ __forceinline__ bool row_ok(const int64_t *rp, int u, long long nnz, 
   return b >= 0 && b <= e && e <= nnz;
 }
 
+// Whether u is among entries [vb, ve) of col_idx (strictly increasing).
+// With `vec` (col_idx 16-byte aligned) the search walks aligned pieces of
+// four entries, one 16-byte load each: a piece whose valid entries bracket u
+// decides, otherwise half of the remaining pieces are dropped.  Entries of
+// neighbouring rows that share a boundary piece are ignored; a piece that
+// would reach past nnz is read entry by entry.
+__device__ __forceinline__ bool row_has(const int32_t *ci, long long nnz, long long vb, long long ve, int u,
+                                        bool vec) {
+  if (vb >= ve) return false;
+  if (!vec) {
+    long long lo = vb, hi = ve;
+    while (lo < hi) {
+      const long long mid = lo + (hi - lo) / 2;
+      if (ci[mid] < u) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo < ve && ci[lo] == u;
+  }
+  long long lo = vb >> 2, hi = (ve - 1) >> 2;  // pieces, inclusive
+  while (lo <= hi) {
+    const long long mid = lo + (hi - lo) / 2;
+    const long long e0 = mid << 2;
+    int x0, x1, x2, x3;
+    if (e0 + 3 < nnz) {
+      const int4 q = *(const int4 *)(ci + e0);
+      x0 = q.x;
+      x1 = q.y;
+      x2 = q.z;
+      x3 = q.w;
+    } else {
+      x0 = ci[e0];
+      x1 = e0 + 1 < nnz ? ci[e0 + 1] : 0;
+      x2 = e0 + 2 < nnz ? ci[e0 + 2] : 0;
+      x3 = 0;
+    }
+    // the piece's entries inside [vb, ve): positions jf..jl
+    const int jf = (int)(vb > e0 ? vb - e0 : 0);
+    const int jl = (int)(ve - 1 - e0 < 3 ? ve - 1 - e0 : 3);
+    const int f = jf == 0 ? x0 : jf == 1 ? x1 : jf == 2 ? x2 : x3;
+    const int l = jl == 0 ? x0 : jl == 1 ? x1 : jl == 2 ? x2 : x3;
+    if (u < f) {
+      hi = mid - 1;
+    } else if (u > l) {
+      lo = mid + 1;
+    } else {
+      return (jf <= 0 && x0 == u) || (jf <= 1 && jl >= 1 && x1 == u) || (jf <= 2 && jl >= 2 && x2 == u) ||
+             (jl >= 3 && x3 == u);
+    }
+  }
+  return false;
+}
+
 // Pass 1's sweep over the rows, one wave per row u: the colour range (stage
 // 1), the structure and stage-2 checks, the start of the state (every entry
 // alive, every vertex touched, the row of every entry recorded) and pass 1's
@@ -75,6 +127,7 @@ __global__ void __launch_bounds__(256) k_csr_first(Plan p, const int64_t *rp, co
   const int n = p.n, k = p.k;
   int balance = 0;  // entries above the diagonal minus entries below it
   bool uf = false;  // u fails pass 1's vertex test
+  const bool vec = ((uintptr_t)ci & 15) == 0;
   long long b, e;
   // stage 1: every colour in [0,k) (also on rows whose bounds are broken)
   const int cu = u < n ? colour[u] : 0;
@@ -113,17 +166,7 @@ __global__ void __launch_bounds__(256) k_csr_first(Plan p, const int64_t *rp, co
       }
       ++balance;
       long long vb, ve;
-      bool found = false;
-      if (row_ok(rp, v, nnz, vb, ve)) {
-        long long lo = vb, hi = ve;
-        while (lo < hi) {
-          const long long mid = lo + (hi - lo) / 2;
-          const int x = ci[mid];
-          if (x < u) lo = mid + 1;
-          else hi = mid;
-        }
-        found = lo < ve && ci[lo] == u;
-      }
+      const bool found = row_ok(rp, v, nnz, vb, ve) && row_has(ci, nnz, vb, ve, u, vec);
       if (!found) pr = max(pr, P_EASYM);
     }
     if (pr) atomicMax(&h->prio, pr);
