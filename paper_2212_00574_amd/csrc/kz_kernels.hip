@@ -614,7 +614,7 @@ __device__ __forceinline__ int third_class(int i, int cx, int cy) {
 // epilogue.  Six-class chunks keep the kernel within 80 registers, so six
 // waves fit on a SIMD.
 template <bool FIRST, int CH, bool MF>
-__global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 1) k_edge(Plan p, const uint64_t *__restrict__ src,
+__global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 5) k_edge(Plan p, const uint64_t *__restrict__ src,
                                                        uint64_t *__restrict__ dst, int pass,
                                                        const uint64_t *__restrict__ fb) {
   Hdr *h = p.hdr;
@@ -724,10 +724,15 @@ __global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 1) k_edge(Plan p, 
     }
     stage(q);
     __syncthreads();    // also publishes sE / sP before the first chunk
+    // P of the wave's rows, lane i holding row wid*kRowsPerWave + i: one LDS
+    // read per chunk instead of one per row (a row's P changes only in its
+    // own iteration below)
+    const unsigned long long Pw = sP[wid * kRowsPerWave + (lane & (kRowsPerWave - 1))];
     for (int ui = 0; ui < kRowsPerWave; ++ui) {
       const int u = wid * kRowsPerWave + ui;
       if (u >= xl) break;
-      unsigned long long P = uniform64(sP[u]);
+      unsigned long long P = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(Pw >> 32), ui) << 32) |
+                             (unsigned)__builtin_amdgcn_readlane((int)Pw, ui);
       const unsigned long long Pt = P & (((TU >> u) & 1ull) ? ~0ull : TV);
       if (!Pt) continue;
       unsigned long long all = ~0ull;
