@@ -612,7 +612,8 @@ __device__ __forceinline__ int third_class(int i, int cx, int cy) {
 // apply pass).  MF: the witness search is replaced by the fail bits `fb` of
 // the MFMA count path (k_mfma_count), so both paths share this tile
 // epilogue.  Six-class chunks keep the kernel within 80 registers, so six
-// waves fit on a SIMD.
+// waves fit on a SIMD; eight-class chunks are held to five (96 registers),
+// which lets every tile of a 50-block row width be resident at once.
 template <bool FIRST, int CH, bool MF>
 __global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 5) k_edge(Plan p, const uint64_t *__restrict__ src,
                                                        uint64_t *__restrict__ dst, int pass,
