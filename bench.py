@@ -500,8 +500,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(graphs would shard by class columns; see the design notes).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(a graph would shard by class columns, one block of classes per GPU).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "c4":
         bench_batch(args)
