@@ -507,6 +507,43 @@ def test_config3b_full_size(kz):
     check_same(res, ref, vm, em, "config3b")
 
 
+def test_config3a_full_size_sampled(kz):
+    """The largest bit-row workload (k=20 x 1000, p=0.3, 5.7e7 edges), in
+    the configuration the benchmark times.  The whole-graph oracle would take
+    minutes, so sampled outputs are checked one by one with the set-based
+    colour indices of section 4.2: the GPU reports that nothing is removed,
+    so every sampled vertex must have a neighbour in each of the other 19
+    classes and every sampled edge a common neighbour in each of its 18 third
+    classes.  At any size: the output rows equal the input, every vertex
+    survives, and each input edge is tested once."""
+    from oracle.setref import colour_index_edge, colour_index_vertex
+    g = inputs.config3a(0)
+    rows, col, lay = g.bitset()
+    k = 20
+    res, vm, em = run_bitset(kz, rows, col, k, "config3a")
+    assert res["status"] == 0 and res["rounds"] == 0 and res["equals_input"] == 1
+    assert np.array_equal(em, rows) and bool(vm.all())
+    m = int(np.unpackbits(rows.view(np.uint8)).sum()) // 2
+    assert res["input_edges"] == m and res["edge_tests"] == m and res["surviving_edges"] == m
+    rng = np.random.default_rng(3)
+    n = lay.n
+    nb = {}
+
+    def neighbours(v):
+        if v not in nb:
+            nb[v] = set(np.nonzero(inputs.unpack_rows(rows[v:v + 1], lay)[0])[0].tolist())
+        return nb[v]
+
+    for v in rng.integers(0, n, 300).tolist():
+        neighbours(v)
+        assert colour_index_vertex(nb, col, v) >= k - 1, v
+    for u in rng.integers(0, n, 300).tolist():
+        nu = sorted(neighbours(u))
+        v = nu[int(rng.integers(0, len(nu)))]
+        neighbours(v)
+        assert colour_index_edge(nb, col, u, v) >= k - 2, (u, v)
+
+
 def test_config2_full_size(kz):
     """The benchmark's workload (k=10 x 300, p=0.6, planted 10-clique) against the full oracle."""
     g = inputs.config2(0)
