@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(256) k_vertex_first(Plan p, const int *scls, c
   };
   const int c0 = min(tid, k);
   const int off0 = p.coff[c0], soff0 = p.soff[c0];
-  const int sc = scls[min(v0 + (lane & (kVfRows - 1)), n - 1)];  // class of slot v0+lane
+  const int sc = scls[min(v0 + (lane & (kVfRows - 1)), n - 1)];  // class of slot v0 + lane % kVfRows
   unsigned long long x[kRows];
   load_rows(0, x);
   Meta m = load_meta(0);
