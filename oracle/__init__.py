@@ -22,6 +22,15 @@ something other than itself):
   indices the thesis prints for Figure 8.
 * ``OracleGraph.kcliques`` -- pinned by closed-form clique counts of complete
   k-partite graphs (prod of class sizes) and by itertools enumeration.
+* ``OracleGraph.failing`` -- vertex output pinned by Figure 8's round-1
+  survivors (hand derivation); edge output pinned by the Figure 8 edges whose
+  printed or derived index is below k-2 (all report 1), by complete
+  multipartite graphs (no edge fails) and by the same graphs with one class
+  emptied (every edge fails).
+* ``OracleGraph.set_masks`` -- pinned by round trips through ``masks`` in
+  all three formats, by resuming from the kernel (no round, invariant I2) and
+  from the input (same result), and by rejecting one-way edges, edges at dead
+  vertices, edges absent from the input and non-0/1 bytes.
 """
 from __future__ import annotations
 

@@ -388,3 +388,95 @@ def test_validation_bitset_and_csr():
         assert kernelize_csr(rp, bad, colour, 3)["status"] == -1
     bad_rp = rp.copy(); bad_rp[-1] += 1
     assert kernelize_csr(bad_rp, ci, colour, 3)["status"] == -1
+
+
+# ----------------------------------------- per-element failure report (failing)
+def test_failing_reports_the_figure8_edges_that_fail():
+    """Thesis section 4.2: the edge index of {a,d} is 0 and of {h,i} is 1, both
+    below k-2 = 2 at k = 4; on the completion {f,h} has the single common
+    neighbour i (index 1) and fails too, and so does every other edge (the
+    hand derivation removes all nine in round 1)."""
+    fx, idx, colour, adj = load_fig8()
+    g = OracleGraph(FMT_DENSE, len(idx), fx["k"], colour, adj=adj)
+    names = [("a", "d"), ("f", "h"), ("h", "i")]
+    us = np.array([idx[a] for a, _ in names])
+    ws = np.array([idx[b] for _, b in names])
+    _, ef = g.failing(us=us, ws=ws)
+    assert ef.tolist() == [1, 1, 1]
+    eu, ev = np.nonzero(np.triu(adj, 1))
+    _, ef = g.failing(us=eu, ws=ev)
+    assert ef.all() and ef.size == 9
+    # a pair that is not an edge never "fails"
+    _, ef = g.failing(us=np.array([idx["a"]]), ws=np.array([idx["e"]]))
+    assert ef.tolist() == [0]
+
+
+@pytest.mark.parametrize("k,s", [(3, 2), (4, 3), (5, 2)])
+def test_failing_reports_no_edge_of_a_complete_multipartite_graph(k, s):
+    colour = np.repeat(np.arange(k), s).astype(np.int32)
+    adj = (colour[:, None] != colour[None, :]).astype(np.uint8)
+    g = OracleGraph(FMT_DENSE, adj.shape[0], k, colour, adj=adj)
+    eu, ev = np.nonzero(np.triu(adj, 1))
+    vf, ef = g.failing(vs=np.arange(adj.shape[0]), us=eu, ws=ev)
+    assert ef.size == len(eu) and not ef.any() and not vf.any()
+    # drop one class entirely: every edge then lacks a common neighbour there
+    # (k >= 3), and every vertex outside it lacks a neighbour there
+    keep = colour != k - 1
+    sub = adj * keep[:, None] * keep[None, :]
+    g2 = OracleGraph(FMT_DENSE, adj.shape[0], k, colour, adj=sub.astype(np.uint8))
+    eu, ev = np.nonzero(np.triu(sub, 1))
+    vf, ef = g2.failing(vs=np.nonzero(keep)[0], us=eu, ws=ev)
+    assert ef.all() and vf.all()
+
+
+# ----------------------------------------- installing a state (set_masks)
+@pytest.mark.parametrize("seed", range(3))
+def test_set_masks_round_trips_in_every_format_and_resumes(seed):
+    """A state installed with set_masks reads back unchanged, and resuming
+    from the kernel removes nothing (the kernel is a fixpoint, invariant I2)."""
+    gr = inputs.make_graph([6, 9, 4, 7], 0.5, seed=seed, gid=5, plant=True)
+    k = 4
+    adj, colour = gr.dense()
+    rows, scol, lay = gr.bitset()
+    rp, ci = inputs.dense_to_csr(adj)
+    makers = {
+        "dense": lambda: OracleGraph(FMT_DENSE, adj.shape[0], k, colour, adj=adj),
+        "bitset": lambda: OracleGraph(FMT_BITSET, rows.shape[0], k, scol, rows=rows, row_words=rows.shape[1]),
+        "csr": lambda: OracleGraph(FMT_CSR, adj.shape[0], k, colour, row_ptr=rp, col_idx=ci),
+    }
+    for name, make in makers.items():
+        ref = make()
+        r = ref.fixpoint()
+        vm, em = ref.masks()
+        g = make()
+        assert g.set_masks(vm, em), name
+        vm2, em2 = g.masks()
+        assert np.array_equal(vm, vm2) and np.array_equal(em, em2), name
+        r2 = g.fixpoint()
+        assert r2["rounds"] == 0 and r2["surv_edges"] == r["surv_edges"], name
+        assert r2["surv_vertices"] == r["surv_vertices"], name
+        # installing the input itself resumes to the same kernel and rounds
+        g3 = make()
+        vin, ein = g3.masks()
+        assert g3.set_masks(vin, ein)
+        assert g3.fixpoint() == r, name
+
+
+def test_set_masks_rejects_states_that_are_not_subgraphs():
+    gr = inputs.make_graph([5, 5, 5], 0.6, seed=2, gid=1)
+    adj, colour = gr.dense()
+    n = adj.shape[0]
+    g = OracleGraph(FMT_DENSE, n, 3, colour, adj=adj)
+    vm = np.ones(n, np.uint8)
+    u, v = edges_of(adj)[0]
+    one_way = adj.copy(); one_way[u, v] = 0          # alive in one direction only
+    assert not g.set_masks(vm, one_way)
+    dead = vm.copy(); dead[u] = 0                    # alive edge at a dead vertex
+    assert not g.set_masks(dead, adj)
+    extra = adj.copy()
+    a, b = np.nonzero((adj == 0) & (colour[:, None] != colour[None, :]) & ~np.eye(n, dtype=bool))
+    extra[a[0], b[0]] = extra[b[0], a[0]] = 1        # an edge the input does not have
+    assert not g.set_masks(vm, extra)
+    bad = vm.copy(); bad[0] = 2
+    assert not g.set_masks(bad, adj)
+    assert g.set_masks(vm, adj)

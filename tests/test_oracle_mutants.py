@@ -25,6 +25,12 @@ MUTANTS = {
         "if (u < v && g->ea[e] && edge_fails(g, u, v)) { fe[e] = 1; any = 1; }",
         "if (u < v && g->ea[e] && edge_fails(g, u, v)) { fe[e] = 1; any = 1; kill_entry(g, e); }"),
     "rounds_count_the_confirming_pass": ("stats[0] = rounds;", "stats[0] = rounds + 1;"),
+    "failing_edge_output_stuck_at_zero": (
+        "efail[i] = edge_alive(g, us[i], ws[i]) && edge_fails(g, us[i], ws[i]);", "efail[i] = 0;"),
+    "set_masks_accepts_one_way_edges": (
+        "    if (g->ea[e] != g->ea[g->mate[e]]) return -1;\n", ""),
+    "set_masks_ignores_dead_endpoints": (
+        "    if (g->ea[e] && (!g->va[g->src[e]] || !g->va[g->nb[e]])) return -1;\n", ""),
     "vertex_index_counts_removed_edges": (
         "  for (int64_t e = g->rp[v]; e < g->rp[v + 1] && count < cap; ++e) {\n    if (!g->ea[e]) continue;",
         "  for (int64_t e = g->rp[v]; e < g->rp[v + 1] && count < cap; ++e) {\n    if (0) continue;"),
