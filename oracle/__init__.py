@@ -22,6 +22,12 @@ something other than itself):
   indices the thesis prints for Figure 8.
 * ``OracleGraph.kcliques`` -- pinned by closed-form clique counts of complete
   k-partite graphs (prod of class sizes) and by itertools enumeration.
+* ``fixpoint_rows`` (O3, the synchronous rounds of O1 on plain bit rows, for
+  graphs too large for O1's adjacency lists) -- pinned by equality with O1
+  (masks, rounds, survivors, exact-worklist counts, validation statuses) on
+  seeded graphs of every shape the tests use, and by the same closed forms:
+  Figure 8's hand-derived fixpoint, the k=3 kernel = union of triangles,
+  complete multipartite graphs and the index-inequality family.
 * ``OracleGraph.failing`` -- vertex output pinned by Figure 8's round-1
   survivors (hand derivation); edge output pinned by the Figure 8 edges whose
   printed or derived index is below k-2 (all report 1), by complete
@@ -74,6 +80,8 @@ def _load():
     lib.kzo_set_masks.restype = C.c_int
     lib.kzo_set_masks.argtypes = [vp, vp, vp]
     lib.kzo_failing.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
+    lib.kzo_fixpoint_rows.restype = C.c_int
+    lib.kzo_fixpoint_rows.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -211,3 +219,24 @@ def kernelize_bitset(rows, colour, k, row_words=None) -> dict:
 def kernelize_csr(row_ptr, col_idx, colour, k) -> dict:
     n = len(row_ptr) - 1
     return _guard(lambda: OracleGraph(FMT_CSR, n, k, colour, row_ptr=row_ptr, col_idx=col_idx))
+
+
+def fixpoint_rows(rows, colour, k) -> dict:
+    """O3 on class-major bit rows (the BITSET format): same result and
+    counts as O1.  Returns the dict of ``kernelize_bitset`` (emask as uint64
+    rows)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    colour = np.ascontiguousarray(colour, dtype=np.int32)
+    n = int(colour.size)
+    R = int(rows.shape[1]) if rows.ndim == 2 else 0
+    if n and rows.shape[0] != n:
+        raise ValueError("rows and colour disagree on n")
+    vmask = np.zeros(n, np.uint8)
+    emask = np.zeros((n, R), np.uint64)
+    stats = np.zeros(5, np.int64)
+    st = _load().kzo_fixpoint_rows(n, int(k), _ptr(colour), _ptr(rows) if rows.size else None, R,
+                                   _ptr(vmask), _ptr(emask) if emask.size else None, _ptr(stats))
+    if st:
+        return dict(status=int(st))
+    return dict(status=0, rounds=int(stats[0]), equals_input=int(stats[1]), surv_vertices=int(stats[2]),
+                surv_edges=int(stats[3]), edge_tests=int(stats[4]), vmask=vmask, emask=emask)

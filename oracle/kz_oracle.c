@@ -639,3 +639,184 @@ void kzo_failing(void *h, const int32_t *vs, int64_t nv, uint8_t *vfail,
   for (int64_t i = 0; i < ne; ++i)
     efail[i] = edge_alive(g, us[i], ws[i]) && edge_fails(g, us[i], ws[i]);
 }
+
+/* ------------------------------------------------------------------- O3 */
+
+/* O3: the synchronous rounds of O1 (same tests, same schedule, same counts),
+ * computed on plain bit rows instead of adjacency lists, so that graphs with
+ * 10^8 edges finish in seconds.  Input: the BITSET format (vertices class by
+ * class, colour sorted; class c's segment holds ceil(s_c/64) words).  Its
+ * own layout arithmetic and loops; nothing shared with O1/O2 except the
+ * status codes.  Outputs: vmask[n], emask in the input's row layout (n *
+ * row_words words), stats as kzo_fixpoint.  Returns a status code (input
+ * validation in the documented order, checked on the rows themselves).
+ *
+ * One round, on the state A (alive edges as bits; a dead vertex has an
+ * empty row):
+ *   vertex v fails  <=> v alive and some class c != colour(v) has no bit in
+ *                       A[v]'s segment c                   (index < k-1);
+ *   edge {u,v} fails <=> some class c outside {colour(u), colour(v)} has
+ *                       A[u][c] AND A[v][c] all zero         (index < k-2);
+ * every failure is decided on A before any removal; then failed edges and
+ * every edge of a failed vertex are cleared (both directions). */
+#define O3_BIT(row, w) (((row)[(w) >> 6] >> ((w) & 63)) & 1ull)
+
+int kzo_fixpoint_rows(int32_t n, int32_t k, const int32_t *col, const uint64_t *rows, int32_t row_words,
+                      uint8_t *vmask, uint64_t *emask, int64_t *stats) {
+  if (n < 0 || k < 1 || row_words < 0 || (n > 0 && (!col || !rows || !vmask || !emask))) return ST_EINVAL;
+  for (int32_t v = 0; v < n; ++v)
+    if (col[v] < 0 || col[v] >= k) return ST_ECOLOUR;
+  for (int32_t v = 1; v < n; ++v)
+    if (col[v] < col[v - 1]) return ST_EINVAL;
+  int64_t *first = (int64_t *)calloc((size_t)k + 1, sizeof(int64_t));  /* first vertex of class c */
+  int64_t *seg = (int64_t *)calloc((size_t)k + 1, sizeof(int64_t));    /* first word of segment c */
+  if (!first || !seg) { free(first); free(seg); return ST_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) first[col[v] + 1] += 1;
+  for (int32_t c = 0; c < k; ++c) {
+    seg[c + 1] = seg[c] + (first[c + 1] + 63) / 64;
+    first[c + 1] += first[c];
+  }
+  if (seg[k] != row_words) { free(first); free(seg); return ST_EINVAL; }
+  const int64_t R = row_words;
+  /* vertex id of bit j of word w: first[c] + 64*(w - seg[c]) + j for the
+   * class c owning word w */
+  int32_t *wcls = (int32_t *)malloc(sizeof(int32_t) * (size_t)(R ? R : 1));
+  if (!wcls) { free(first); free(seg); return ST_ENOMEM; }
+  for (int32_t c = 0; c < k; ++c)
+    for (int64_t w = seg[c]; w < seg[c + 1]; ++w) wcls[w] = c;
+  /* validation: malformed (padding bit) > self-loop > asymmetry > intra-class */
+  int bad_pad = 0, bad_loop = 0, bad_asym = 0, bad_intra = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    const uint64_t *ru = rows + (int64_t)u * R;
+    for (int64_t w = 0; w < R; ++w) {
+      uint64_t x = ru[w];
+      while (x) {
+        int j = __builtin_ctzll(x);
+        x &= x - 1;
+        int32_t c = wcls[w];
+        int64_t v = first[c] + 64 * (w - seg[c]) + j;
+        if (v >= first[c + 1]) { bad_pad = 1; continue; }
+        if (v == u) { bad_loop = 1; continue; }
+        int32_t cu = col[u];
+        int64_t wu = seg[cu] + (u - first[cu]) / 64;
+        if (!((rows[v * R + wu] >> ((u - first[cu]) % 64)) & 1ull)) bad_asym = 1;
+        if (c == cu) bad_intra = 1;
+      }
+    }
+  }
+  int st = bad_pad ? ST_EINVAL : bad_loop ? ST_ESELFLOOP : bad_asym ? ST_EASYM : bad_intra ? ST_EILLEGAL : ST_OK;
+  if (st) { free(first); free(seg); free(wcls); return st; }
+
+  uint64_t *A = emask;                                    /* the state, in place */
+  if (n) memcpy(A, rows, sizeof(uint64_t) * (size_t)n * (size_t)R);
+  uint64_t *Fe = (uint64_t *)calloc((size_t)n * (size_t)R + 1, sizeof(uint64_t));  /* failed edges, u < v bits */
+  uint8_t *fv = (uint8_t *)calloc((size_t)n + 1, 1);
+  uint8_t *touched = (uint8_t *)calloc((size_t)n + 1, 1);
+  if (!Fe || !fv || !touched) { free(first); free(seg); free(wcls); free(Fe); free(fv); free(touched); return ST_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) vmask[v] = 1;
+  int64_t m = 0;
+  for (int32_t u = 0; u < n; ++u)
+    for (int64_t w = 0; w < R; ++w) m += __builtin_popcountll(A[(int64_t)u * R + w]);
+  m /= 2;
+  int64_t rounds = 0, tests = m;
+  for (;;) {
+    int any = 0;
+    /* vertex tests on the snapshot */
+    for (int32_t v = 0; v < n; ++v) {
+      fv[v] = 0;
+      if (!vmask[v]) continue;
+      const uint64_t *rv = A + (int64_t)v * R;
+      for (int32_t c = 0; c < k && !fv[v]; ++c) {
+        if (c == col[v]) continue;
+        int has = 0;
+        for (int64_t w = seg[c]; w < seg[c + 1] && !has; ++w) has = rv[w] != 0;
+        if (!has) fv[v] = 1;
+      }
+      any |= fv[v];
+    }
+    /* edge tests on the snapshot: every alive edge u < v */
+    for (int32_t u = 0; u < n; ++u) {
+      const uint64_t *ru = A + (int64_t)u * R;
+      uint64_t *fu = Fe + (int64_t)u * R;
+      for (int64_t w = 0; w < R; ++w) {
+        fu[w] = 0;
+        uint64_t x = ru[w];
+        while (x) {
+          int j = __builtin_ctzll(x);
+          x &= x - 1;
+          int32_t cv = wcls[w];
+          int64_t v = first[cv] + 64 * (w - seg[cv]) + j;
+          if (v <= u || k < 3) continue;
+          const uint64_t *rv = A + v * R;
+          int fails = 0;
+          for (int32_t c = 0; c < k && !fails; ++c) {
+            if (c == col[u] || c == cv) continue;
+            int common = 0;
+            for (int64_t t = seg[c]; t < seg[c + 1] && !common; ++t) common = (ru[t] & rv[t]) != 0;
+            if (!common) fails = 1;
+          }
+          if (fails) { fu[w] |= 1ull << j; any = 1; }
+        }
+      }
+    }
+    if (!any) break;
+    /* apply the round: failed edges, then every edge at a failed vertex */
+    memset(touched, 0, (size_t)n + 1);
+    for (int32_t u = 0; u < n; ++u) {
+      uint64_t *ru = A + (int64_t)u * R;
+      for (int64_t w = 0; w < R; ++w) {
+        uint64_t x = Fe[(int64_t)u * R + w];
+        while (x) {
+          int j = __builtin_ctzll(x);
+          x &= x - 1;
+          int32_t cv = wcls[w];
+          int64_t v = first[cv] + 64 * (w - seg[cv]) + j;
+          int32_t cu = col[u];
+          ru[w] &= ~(1ull << j);
+          A[v * R + seg[cu] + (u - first[cu]) / 64] &= ~(1ull << ((u - first[cu]) % 64));
+          touched[u] = touched[v] = 1;
+        }
+      }
+    }
+    for (int32_t u = 0; u < n; ++u) {
+      if (!fv[u]) continue;
+      uint64_t *ru = A + (int64_t)u * R;
+      int32_t cu = col[u];
+      for (int64_t w = 0; w < R; ++w) {
+        uint64_t x = ru[w];
+        while (x) {
+          int j = __builtin_ctzll(x);
+          x &= x - 1;
+          int32_t cv = wcls[w];
+          int64_t v = first[cv] + 64 * (w - seg[cv]) + j;
+          A[v * R + seg[cu] + (u - first[cu]) / 64] &= ~(1ull << ((u - first[cu]) % 64));
+          touched[u] = touched[v] = 1;
+        }
+        ru[w] = 0;
+      }
+      vmask[u] = 0;
+    }
+    ++rounds;
+    /* next pass's exact worklist: alive edges with a touched endpoint */
+    for (int32_t u = 0; u < n; ++u) {
+      const uint64_t *ru = A + (int64_t)u * R;
+      for (int64_t w = 0; w < R; ++w) {
+        uint64_t x = ru[w];
+        while (x) {
+          int j = __builtin_ctzll(x);
+          x &= x - 1;
+          int32_t cv = wcls[w];
+          int64_t v = first[cv] + 64 * (w - seg[cv]) + j;
+          if (v > u && (touched[u] || touched[v])) ++tests;
+        }
+      }
+    }
+  }
+  int64_t sv = 0, se = 0;
+  for (int32_t v = 0; v < n; ++v) sv += vmask[v];
+  for (int64_t i = 0; i < (int64_t)n * R; ++i) se += __builtin_popcountll(A[i]);
+  const int64_t out[5] = {rounds, rounds == 0, sv, se / 2, tests};
+  memcpy(stats, out, sizeof out);
+  free(first); free(seg); free(wcls); free(Fe); free(fv); free(touched);
+  return ST_OK;
+}

@@ -480,3 +480,103 @@ def test_set_masks_rejects_states_that_are_not_subgraphs():
     bad = vm.copy(); bad[0] = 2
     assert not g.set_masks(bad, adj)
     assert g.set_masks(vm, adj)
+
+
+# ------------------------------------------- O3: the rounds on plain bit rows
+from oracle import fixpoint_rows  # noqa: E402
+
+
+def to_rows(adj, colour, k):
+    """Dense (any vertex order) -> class-major bit rows with sorted colours."""
+    order = np.argsort(colour, kind="stable")
+    sizes = np.bincount(colour, minlength=k)
+    lay = inputs.class_layout(sizes)
+    slot = adj[np.ix_(order, order)].astype(bool)
+    return inputs.pack_rows(slot, lay), np.sort(colour).astype(np.int32), order, lay
+
+
+def same_as_o1(rows, col, k):
+    a = fixpoint_rows(rows, col, k)
+    b = kernelize_bitset(rows, col, k)
+    assert a["status"] == b["status"]
+    if a["status"]:
+        return a
+    for key in ("rounds", "equals_input", "surv_vertices", "surv_edges", "edge_tests"):
+        assert a[key] == b[key], key
+    assert np.array_equal(a["vmask"], b["vmask"]) and np.array_equal(a["emask"], b["emask"])
+    return a
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_o3_equals_o1_on_seeded_graphs(seed):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 8))
+    sizes = rng.integers(0 if seed % 3 == 0 else 1, 140, size=k)     # ragged, some empty classes
+    p = float(rng.uniform(0.15, 0.85))
+    g = inputs.make_graph(sizes, p, seed=seed, gid=9, plant=bool(sizes.min() > 0 and seed % 2), shuffle=False)
+    rows, col, lay = g.bitset()
+    same_as_o1(rows, col, k)
+
+
+def test_o3_figure8_fixpoint_hand_derived():
+    fx, idx, colour, adj = load_fig8()
+    rows, col, order, lay = to_rows(adj, colour, fx["k"])
+    r = same_as_o1(rows, col, fx["k"])
+    assert r["rounds"] == fx["expected_fixpoint"]["rounds"] == 2
+    assert r["surv_vertices"] == 0 and r["surv_edges"] == 0
+
+
+@pytest.mark.parametrize("seed,p", [(0, 0.3), (1, 0.5), (2, 0.7)])
+def test_o3_k3_kernel_is_union_of_triangles(seed, p):
+    adj, colour = random_small(9, 3, p, seed)
+    rows, col, order, lay = to_rows(adj, colour, 3)
+    r = fixpoint_rows(rows, col, 3)
+    slot = adj[np.ix_(order, order)]
+    n = slot.shape[0]
+    tri = np.zeros_like(slot)
+    for a, b, c in itertools.combinations(range(n), 3):
+        if slot[a, b] and slot[b, c] and slot[a, c]:
+            for x, y in ((a, b), (b, c), (a, c)):
+                tri[x, y] = tri[y, x] = 1
+    got = inputs.unpack_rows(r["emask"], lay).astype(np.uint8)
+    assert np.array_equal(got, tri)
+    assert np.array_equal(r["vmask"], tri.any(axis=1).astype(np.uint8))
+
+
+@pytest.mark.parametrize("k,s", [(2, 3), (4, 3), (6, 1)])
+def test_o3_complete_multipartite_and_index_inequality(k, s):
+    colour = np.repeat(np.arange(k), s).astype(np.int32)
+    adj = (colour[:, None] != colour[None, :]).astype(np.uint8)
+    rows, col, _, _ = to_rows(adj, colour, k)
+    r = same_as_o1(rows, col, k)
+    assert r["rounds"] == 0 and r["surv_edges"] == len(edges_of(adj))
+    if k >= 4:
+        adj, colour = index_inequality(k)
+        rows, col, _, _ = to_rows(adj, colour, k)
+        r = same_as_o1(rows, col, k)
+        assert r["rounds"] == 0 and r["surv_edges"] == len(edges_of(adj))
+
+
+def test_o3_validation_matches_o1():
+    gr = inputs.make_graph([3, 4, 2], 0.7, seed=1, gid=0, shuffle=False)
+    rows, col, lay = gr.bitset()
+    cases = [(rows, col), (rows, col[::-1].copy()), (rows, np.array([0, 0, 0, 1, 1, 1, 1, 2, 5], np.int32))]
+    for mut in ((0, 0, 1 << 5), (0, 0, 1), (0, 0, 2), (3, 0, 1 << 1)):
+        bad = rows.copy()
+        bad[mut[0], mut[1]] |= np.uint64(mut[2])
+        cases.append((bad, col))
+    bad = rows.copy(); bad[0, 0] |= np.uint64(2); bad[1, 0] |= np.uint64(1)
+    cases.append((bad, col))
+    for r, c in cases:
+        a, b = fixpoint_rows(r, c, 3), kernelize_bitset(r, c, 3)
+        assert a["status"] == b["status"], (a["status"], b["status"])
+    assert {fixpoint_rows(r, c, 3)["status"] for r, c in cases} >= {0, -1, -2, -3, -4, -5}
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 6])
+def test_o3_empty_class_empties_the_graph_in_one_round(k):
+    colour = np.repeat(np.arange(k - 1), 3).astype(np.int32)   # class k-1 is empty
+    adj = (colour[:, None] != colour[None, :]).astype(np.uint8)
+    rows, col, _, _ = to_rows(adj, colour, k)
+    r = same_as_o1(rows, col, k)
+    assert r["rounds"] == 1 and r["surv_vertices"] == 0 and r["surv_edges"] == 0
