@@ -178,10 +178,15 @@ int kz_set_edge_path(kz_ctx *ctx, int32_t path);
  *   colour (int32) and vmask (uint8): graph g's n entries start at
  *          vertex_offset;
  *   emask  (uint64): same layout as rows (must not overlap it).
- * The graphs' row ranges must not overlap.  Limits of the batched path:
- * k <= 64, row_words <= 512, n <= 32768; a graph beyond them gets status
- * KZ_ETOOLARGE in its result (run it through kz_kernelize); negative offsets
- * give KZ_EINVAL.  The call is
+ * The graphs' row ranges must not overlap.  Every graph's ranges start on a
+ * 128-byte line: row_offset a multiple of 16 words and vertex_offset a
+ * multiple of 128 vertices, and the four arena pointers 128-byte aligned
+ * (else the call returns KZ_EINVAL before any device work).  Workgroups on
+ * different XCDs work on different graphs at once, and each XCD's L2 is a
+ * write-back cache: a line holding two graphs' bytes could be read stale.
+ * Limits of the batched path: k <= 64, row_words <= 512, n <= 32768; a graph
+ * beyond them gets status KZ_ETOOLARGE in its result (run it through
+ * kz_kernelize); negative offsets give KZ_EINVAL.  The call is
  * asynchronous: it enqueues the work on the stream and returns; results[g]
  * (device memory) is valid in stream order.  It performs no host
  * synchronisation, so a caller may capture it in a hipGraph and replay it. */
@@ -206,8 +211,8 @@ typedef struct kz_batch_config {
 
 /* Workspace bytes kz_kernelize_batch needs for these graphs (host array),
  * the same for every configuration: the queue, a job record per graph
- * (about 11 KB), and per row word one next-state word and two list ints
- * up to the highest row_offset + n*row_words. */
+ * (about 11 KB), and per row word one next-state word and four list ints
+ * (changed tiles, items) up to the highest row_offset + n*row_words. */
 int kz_batch_workspace_bytes(const kz_ctx *ctx, const kz_batch_graph *graphs, int32_t G, size_t *bytes);
 
 /* Kernelizes G graphs.  graphs_host and graphs_dev hold the same
@@ -239,8 +244,9 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
  * row-word limits) take a second lane instead: two worker threads, each
  * with a stream of its own, run them through the single-graph path, one
  * request each at a time, overlapping the batch launches.  A request is a
- * KZ_BITSET_U64 graph in caller-owned device buffers; results are the same
- * as kz_kernelize on the graph alone.  The server takes a fixed part of a
+ * KZ_BITSET_U64 graph in caller-owned device buffers (vmask and emask
+ * 128-byte aligned, else KZ_EINVAL); results are the same as kz_kernelize on
+ * the graph alone.  The server takes a fixed part of a
  * caller-provided device arena for its launch records and carves each
  * admitted request's scratch from the rest (first fit); it admits a request
  * only when a slot and its scratch are free, else KZ_EAGAIN.  It allocates

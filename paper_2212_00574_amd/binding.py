@@ -396,10 +396,18 @@ class Kernelizer:
         return vmask, emask, res
 
 
+LINE_WORDS, LINE_VERTICES = 16, 128   # a graph's arena ranges start on a 128-byte line
+
+
+def _line_up(x: int, q: int) -> int:
+    return (x + q - 1) // q * q
+
+
 class Batch:
     """Arenas, descriptors and results of one batch of bit-row graphs on a device.
 
-    ``graphs`` is a list of (rows uint64 [n, R], colour int32 [n], k).
+    ``graphs`` is a list of (rows uint64 [n, R], colour int32 [n], k).  Each
+    graph's ranges start on a 128-byte line (kz_kernelize_batch requires it).
     """
 
     def __init__(self, graphs, device):
@@ -410,8 +418,8 @@ class Batch:
         for i, (rows, colour, k) in enumerate(graphs):
             n, R = (rows.shape[0], rows.shape[1]) if rows.ndim == 2 else (len(colour), 0)
             desc[i] = (n, k, R, 0, ro, vo)
-            ro += n * R
-            vo += n
+            ro = _line_up(ro + n * R, LINE_WORDS)
+            vo = _line_up(vo + n, LINE_VERTICES)
         self.G = G
         self.desc = desc
         rows_all = np.zeros(max(ro, 1), np.uint64)

@@ -159,16 +159,20 @@ int finish(kz_result *res, const kz_result &r) {
 constexpr int kBatchMaxWorkgroups = 1024;
 
 struct BatchWs {
-  size_t off_queue, off_finished, off_board, off_order, off_jobs, off_next, off_lists, total;
+  size_t off_queue, off_finished, off_board, off_order, off_jobs, off_next, off_lists, off_items, total;
 };
+
+// Every graph's ranges start on a 128-byte line (no line holds two graphs'
+// data, see the batch kernel's notes on cache lines).
+constexpr long long kLineWords = 16, kLineVertices = 128;
 
 bool batch_fits(const kz_batch_graph &g) {
   return g.n >= 0 && g.k >= 1 && g.row_words >= 0 && g.row_offset >= 0 && g.vertex_offset >= 0 &&
          g.k <= kzi::kBatchK && g.row_words <= kzi::kBatchR && g.n <= kzi::kBatchN;
 }
 
-// Arenas indexed like rows: the next-state words (one word per row word) and
-// the tile lists (two ints per row word).
+// Arenas indexed like rows: the next-state words (one word per row word), the
+// changed-tile lists and the item lists (two ints per row word each).
 BatchWs batch_ws(const kz_batch_graph *graphs, int32_t G) {
   BatchWs w{};
   long long extent = 0;
@@ -191,6 +195,7 @@ BatchWs batch_ws(const kz_batch_graph *graphs, int32_t G) {
   w.off_jobs = take(sizeof(kzi::BatchJob) * (size_t)G);
   w.off_next = take(sizeof(uint64_t) * (size_t)extent);
   w.off_lists = take(2 * sizeof(int) * (size_t)extent);
+  w.off_items = take(2 * sizeof(int) * (size_t)extent);
   w.total = o;
   return w;
 }
@@ -218,6 +223,10 @@ int batch_launch(kz_ctx *ctx, const kzi::BatchConfig &cfg, const kz_batch_graph 
     return KZ_EINVAL;
   if (G == 0) return KZ_OK;
   if ((uintptr_t)ws % kAlign) return KZ_EINVAL;
+  if ((uintptr_t)rows % 128 || (uintptr_t)colour % 128 || (uintptr_t)vmask % 128 || (uintptr_t)emask % 128)
+    return KZ_EINVAL;
+  for (int32_t i = 0; i < G; ++i)
+    if (graphs_host[i].row_offset % kLineWords || graphs_host[i].vertex_offset % kLineVertices) return KZ_EINVAL;
   const BatchWs w = batch_ws(graphs_host, G);
   if (ws_bytes < w.total) return KZ_EWORKSPACE;
   if (hipSetDevice(ctx->device) != hipSuccess) return KZ_EHIP;
@@ -238,6 +247,7 @@ int batch_launch(kz_ctx *ctx, const kzi::BatchConfig &cfg, const kz_batch_graph 
   a.results = results;
   a.next = (uint64_t *)(base + w.off_next);
   a.lists = (int *)(base + w.off_lists);
+  a.items = (int *)(base + w.off_items);
   kzi::BatchConfig c = cfg;
   c.workgroups = batch_workgroups(ctx, cfg);
   kzi::launch_batch(a, c, s);

@@ -2,7 +2,7 @@
 //
 // Each graph is a job: a sequence of synchronous passes (Definition 4.2.1's
 // vertex and edge colour-index tests, applied to a snapshot), and each pass
-// is a list of items: 64-vertex chunks for the vertex test and 64x64 block
+// is a list of items: 128-vertex chunks for the vertex test and 64x64 block
 // tiles (X < Y) for the edge test.  A workgroup takes the next graph from an
 // atomic queue, sets it up and lists its first pass; its waves split the
 // items.  The workgroup that finishes the last item of a pass carries the
@@ -29,7 +29,20 @@
 // vertex_offset[g].  The state is kept in the emask arena (same layout); the
 // changed words of a pass go to the next-state arena (same layout); the
 // changed-tile list and the item list sit at int offset 2*row_offset[g] of
-// the list arena.  Graphs too large for this path (k > kBatchK, row words >
+// two list arenas of their own.
+//
+// Cache lines.  The L2 of each XCD is a write-back cache, and an invalidate
+// (the acquire half of a fence) keeps lines that hold dirty bytes.  A line
+// that a workgroup reads while another workgroup on the same XCD writes
+// other bytes of it can therefore survive a fence with stale bytes.  So no
+// 128-byte line is shared between two graphs (the host requires every
+// graph's ranges to start on a line, and the list arenas are laid out per
+// row word), and within a pass every line that is read is written by at
+// most the item that reads it: a vertex item owns 128 vertices (one line of
+// the vertex mask), and the item list starts on a line of its own, away
+// from the changed-tile list that tiles append to during the pass.  Lines
+// that several items write in one pass (next-state words, the changed-tile
+// list) are read only by the carrier, after every writer has released them.  Graphs too large for this path (k > kBatchK, row words >
 // kBatchR, or n > kBatchN) get status KZ_ETOOLARGE in their result and are
 // left to the single-graph path.
 #include "kz_internal.h"
@@ -39,6 +52,7 @@ namespace kzi {
 namespace {
 
 constexpr int kVertexItem = 1 << 30;                 // item = kVertexItem | chunk, else X | Y << kYShift
+constexpr int kVChunk = 128;                         // vertices of a vertex item: one line of the vertex mask
 constexpr int kYShift = 9, kXMask = (1 << kYShift) - 1;
 constexpr unsigned long long kIdleTicks = 2000000;   // 20 ms of the 100 MHz wall clock
 // Claim word: pass (24 bits) | items (20 bits) | next unclaimed item (20 bits).
@@ -97,7 +111,7 @@ struct GView {
   uint64_t *cur, *nxt;
   const int *colour;
   uint8_t *valive;
-  int *changed, *items;
+  int *changed, *items;  // each starts on a 128-byte line
   BatchJob *J;
 };
 
@@ -117,6 +131,7 @@ __device__ __forceinline__ GView gview(const BatchArgs &a, int g) {
     v.colour = P.colour;
     v.valive = P.vmask;
     v.changed = P.lists;
+    v.items = P.items;
   } else {
     v.rows = a.rows + G.row_offset;
     v.cur = a.emask + G.row_offset;
@@ -124,8 +139,9 @@ __device__ __forceinline__ GView gview(const BatchArgs &a, int g) {
     v.colour = a.colour + G.vertex_offset;
     v.valive = a.vmask + G.vertex_offset;
     v.changed = a.lists + 2 * G.row_offset;
+    v.items = a.items + 2 * G.row_offset;
   }
-  v.items = v.changed + T;
+  (void)T;
   v.J = a.jobs + g;
   return v;
 }
@@ -320,7 +336,12 @@ __device__ void run_items(const GView &V, BatchLds &S, unsigned long long (*sU)[
     i = __builtin_amdgcn_readfirstlane(i);
     if (i >= cnt) break;
     const int it = V.items[base + i];
-    if (it & kVertexItem) vertex_chunk(V, S, (it & 0xffff) * kWave, first, lane);
+    if (it & kVertexItem) {
+      // both halves of the item's line of the vertex mask, by this wave
+      const int v0 = (it & 0xffff) * kVChunk;
+      vertex_chunk(V, S, v0, first, lane);
+      vertex_chunk(V, S, v0 + kWave, first, lane);
+    }
     else tile<CH>(V, S, it & kXMask, (it >> kYShift) & kXMask, first, lane, sU[wid], sU2[wid]);
   }
   __syncthreads();
@@ -366,12 +387,17 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
   const int nw = (n + 31) >> 5, nbw = (R + 31) >> 5;
   if (tid == 0) S.nitems = 0;
   __syncthreads();
-  // vertex chunks holding a touched vertex
-  const int nvc = (n + 63) >> 6;
+  // vertex chunks (128 vertices, four touched words) holding a touched vertex
+  const int nvc = (n + kVChunk - 1) / kVChunk;
   for (int c0 = wid * kWave; c0 < nvc; c0 += NW * kWave) {
     const int c = c0 + lane;
     bool want = false;
-    if (c < nvc) want = (S.tc[2 * c] | (2 * c + 1 < nw ? S.tc[2 * c + 1] : 0u)) != 0u;
+    if (c < nvc) {
+      unsigned t = 0;
+#pragma unroll
+      for (int j = 0; j < kVChunk / 32; ++j) t |= 4 * c + j < nw ? S.tc[4 * c + j] : 0u;
+      want = t != 0u;
+    }
     const unsigned long long b = __ballot(want);
     int at = 0;
     if (lane == 0 && b) at = atomicAdd(&S.nitems, __popcll(b));

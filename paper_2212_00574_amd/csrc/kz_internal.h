@@ -184,8 +184,9 @@ struct BatchPtrs {
   uint8_t *vmask;
   uint64_t *emask;
   uint64_t *next;  // n*row_words words
-  int *lists;      // 2*n*row_words ints
-};
+  int *lists;      // changed tiles: 2*n*row_words ints
+  int *items;      // pass items: 2*n*row_words ints
+};                 // every buffer starts on a 128-byte line
 
 struct BatchArgs {
   const kz_batch_graph *graphs;
@@ -203,7 +204,8 @@ struct BatchArgs {
   uint8_t *vmask;
   kz_result *results;
   uint64_t *next;  // next-state words, same layout as rows
-  int *lists;      // changed tiles and items: graph g's at int offset 2*row_offset
+  int *lists;      // changed tiles: graph g's at int offset 2*row_offset
+  int *items;      // pass items: graph g's at int offset 2*row_offset
 };
 
 struct BatchConfig {

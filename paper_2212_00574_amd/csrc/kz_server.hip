@@ -239,6 +239,7 @@ int launch(kz_server *s, Record &rec) {
     p.emask = q.r.emask;
     p.next = (uint64_t *)(s->arena + q.at);
     p.lists = (int *)(s->arena + q.at + up(words * sizeof(uint64_t)));
+    p.items = (int *)(s->arena + q.at + up(words * sizeof(uint64_t)) + up(2 * words * sizeof(int)));
   }
   kzi::BatchArgs a{};
   a.graphs = (const kz_batch_graph *)(rec.dev + s->L.graphs);
@@ -280,10 +281,10 @@ size_t kz_server_fixed_bytes(int32_t max_slots) {
 
 namespace {
 
-// Scratch of the batch lane: next-state words and tile lists.
+// Scratch of the batch lane: next-state words, changed-tile and item lists.
 size_t batch_bytes(const kz_request &r) {
   const size_t words = (size_t)r.n * (size_t)r.row_words;
-  return up(words * sizeof(uint64_t)) + up(2 * words * sizeof(int));
+  return up(words * sizeof(uint64_t)) + 2 * up(2 * words * sizeof(int));
 }
 
 // Scratch of the single-graph lane: kz_kernelize's workspace.
@@ -373,6 +374,8 @@ int kz_server_submit(kz_server *s, const kz_request *req, uint64_t *ticket) {
   const kz_request &r = *req;
   if (r.n < 0 || r.k < 1 || r.row_words < 0 || (r.n > 0 && (!r.rows || !r.colour || !r.vmask || !r.emask)))
     return KZ_EINVAL;
+  // the batch lane's outputs must not share a 128-byte line with other data
+  if ((uintptr_t)r.vmask % 128 || (uintptr_t)r.emask % 128) return KZ_EINVAL;
   const bool big = r.n >= kSplitN || r.k > kzi::kBatchK || r.row_words > kzi::kBatchR;
   size_t bytes = batch_bytes(r);
   if (big && single_bytes(s->wctx[0], r, &bytes) != KZ_OK) return KZ_EINVAL;
