@@ -149,6 +149,22 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
                  void *ws, size_t ws_bytes, uint8_t *vmask, void *emask,
                  void *stream, kz_result *res);
 
+/* The same as kz_kernelize, with the library's own workspace instead of a
+ * caller's: for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  It
+ * allocates nothing and calls no allocating routine.  The workspace is a
+ * fixed array of KZ_NOALLOC_SCRATCH_BYTES in device memory, one per GPU,
+ * held until the process ends; a graph whose kz_workspace_bytes exceeds it
+ * gets KZ_EWORKSPACE before any device work (use kz_kernelize with a larger
+ * workspace).  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on a GPU (from two threads, or on two streams without ordering
+ * between them) race and give undefined results.  Contents left by the
+ * previous call are ignored (every kernel initialises what it reads).
+ * Arguments, outputs, errors and blocking behaviour as kz_kernelize. */
+#define KZ_NOALLOC_SCRATCH_BYTES (64u << 20)
+int kz_kernelize_noalloc(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k,
+                         uint8_t *vmask, void *emask, void *stream, kz_result *res);
+
 /* Edge-test implementation used by kz_kernelize for KZ_DENSE_U8 and
  * KZ_BITSET_U64 input (CSR always uses its own):
  *   KZ_EDGE_BITSET  (default) witness search on the bit rows: per third

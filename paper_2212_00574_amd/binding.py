@@ -22,7 +22,9 @@ EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_
             "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
             "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
-            "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_set_edge_path")
+            "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_set_edge_path",
+            "kz_kernelize_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20   # KZ_NOALLOC_SCRATCH_BYTES
 KZ_EDGE_BITSET, KZ_EDGE_MFMA_I8 = 0, 1
 KZ_EAGAIN = -9
 KZ_ETOOLARGE = -10
@@ -83,6 +85,8 @@ def _load() -> C.CDLL:
     lib.kz_kernelize.restype = C.c_int
     lib.kz_kernelize.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, C.c_size_t, vp, vp, vp,
                                  C.POINTER(kz_result)]
+    lib.kz_kernelize_noalloc.restype = C.c_int
+    lib.kz_kernelize_noalloc.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, vp, vp, C.POINTER(kz_result)]
     lib.kz_batch_workspace_bytes.restype = C.c_int
     lib.kz_batch_workspace_bytes.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_size_t)]
     lib.kz_kernelize_batch.restype = C.c_int
@@ -159,6 +163,13 @@ def kz_kernelize(ctx: int, graph: kz_graph, colour_ptr: int, k: int, ws_ptr: int
     res = kz_result()
     LIB.kz_kernelize(ctx, C.byref(graph), colour_ptr, int(k), ws_ptr, int(ws_bytes), vmask_ptr,
                      emask_ptr, stream, C.byref(res))
+    return res
+
+
+def kz_kernelize_noalloc(ctx: int, graph: kz_graph, colour_ptr: int, k: int, vmask_ptr: int, emask_ptr: int,
+                         stream: int) -> kz_result:
+    res = kz_result()
+    LIB.kz_kernelize_noalloc(ctx, C.byref(graph), colour_ptr, int(k), vmask_ptr, emask_ptr, stream, C.byref(res))
     return res
 
 

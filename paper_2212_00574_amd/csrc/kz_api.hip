@@ -6,13 +6,37 @@
 // read of the pass counters, until a pass removes nothing.
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "kz.h"
 #include "kz_internal.h"
 
+// Workspace of kz_kernelize_noalloc: one copy per GPU, held until the process
+// ends.  Host code never uses this name as a device address; it uses the
+// address hipGetSymbolAddress returned on that device (scratch_ptr below).
+static __device__ __align__(256) unsigned char kz_scratch[KZ_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of kz_scratch on each device, once looked up
+
+// Looks up kz_scratch's address on `device` (which must be current) the
+// first time; KZ_EHIP if the runtime cannot give it.
+int scratch_lookup(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return KZ_EHIP;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(kz_scratch)) != hipSuccess || !p) return KZ_EHIP;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return KZ_OK;
+}
 
 hipEvent_t take_event(kz_ctx *c) {
   hipEvent_t e = nullptr;
@@ -356,6 +380,7 @@ int kz_create(kz_ctx **out, int device) {
   if (!c) return KZ_ENOMEM;
   c->device = device;
   c->pinned = nullptr;
+  c->scratch = nullptr;
   c->prof = false;
   c->batch_cfg_set = false;
   c->batch_cfg = kzi::BatchConfig{16, 4, 1, 0, 0};
@@ -374,6 +399,12 @@ int kz_create(kz_ctx **out, int device) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
+  // the device's copy of the no-allocation workspace, looked up while the
+  // device is current
+  if (scratch_lookup(device, &c->scratch) != KZ_OK) {
+    kz_destroy(c);
+    return KZ_EHIP;
+  }
   *out = c;
   return KZ_OK;
 }
@@ -713,3 +744,18 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
 }
 
 }  // extern "C"
+
+extern "C" int kz_kernelize_noalloc(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k,
+                                    uint8_t *vmask, void *emask, void *stream, kz_result *res) {
+  kz_result r{};
+  r.status = KZ_EINVAL;
+  if (!ctx || !ctx->scratch || !shape_ok(g, k)) return finish(res, r);
+  const bool mfma = ctx->edge_path == KZ_EDGE_MFMA_I8 && g->format != KZ_CSR;
+  if (plan_sizes(g, k, mfma).total > (size_t)KZ_NOALLOC_SCRATCH_BYTES) {
+    r.status = KZ_EWORKSPACE;
+    return finish(res, r);
+  }
+  // every kernel of the path initialises what it reads from the workspace,
+  // so the previous call's contents need no clearing
+  return kz_kernelize(ctx, g, colour, k, ctx->scratch, (size_t)KZ_NOALLOC_SCRATCH_BYTES, vmask, emask, stream, res);
+}

@@ -244,5 +244,6 @@ struct kz_ctx {
   bool batch_cfg_set;
   int cus;        // compute units of the device
   int edge_path;  // KZ_EDGE_BITSET or KZ_EDGE_MFMA_I8
+  void *scratch;  // device address of the no-allocation workspace on this device
 };
 
