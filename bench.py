@@ -1,13 +1,28 @@
 """Benchmark: colour-index kernelization to the fixpoint on one MI355X.
 
-A step is one full kz_kernelize call (validation, every pass to the fixpoint,
-outputs) on inputs already resident in device memory.  The default workload
-is the mid-size graph: k = 10 colour classes x 300 vertices, inter-class edge
-probability 0.6, one planted 10-clique, class-major uint64 bit rows.
+Default run (no --workload): the headline line on the largest single-graph
+workload, config 3a (k = 20 colour classes x 1000 vertices, inter-class edge
+probability 0.3, class-major uint64 bit rows, 5.7e7 edges), with two
+sub-objects in the same JSON line:
 
-Prints one JSON line.  ``value`` is edge tests per second, counting the
-edge tests of the exact worklists (every edge in the first pass; in pass r+1
-the edges with an endpoint that lost an edge in round r).
+* ``batch`` -- config 4: 4096 graphs in one persistent launch under a
+  captured hipGraph (batched graphs/s) against one-graph-at-a-time calls of
+  the single-graph path on the same device-resident inputs;
+* ``serve`` -- config 5: the 50,000-request stream through the server:
+  closed-loop requests/s S, then Poisson arrivals at 0.5 S and 0.8 S with
+  p50/p99 latency, and one-request-at-a-time calls on the same inputs.
+
+A step of the headline is one full kz_kernelize call (validation, every pass
+to the fixpoint, outputs) on inputs already resident in device memory;
+``value`` is edge tests per second, counting the edge tests of the exact
+worklists (every edge in the first pass; in pass r+1 the edges with an
+endpoint that lost an edge in round r).  --workload c1 | c2 | c3a | c3b |
+c4 | c5 runs one workload alone (used for the rocprofv3 summaries).
+
+Inputs are seeded and synthetic (the generator of paper_2212_00574_amd/
+inputs.py; kz_gen_bitset materialises the same graphs on the device).  The
+CPU oracle runs only in the cpu_baseline leg, in a child process pinned to
+one core.
 """
 from __future__ import annotations
 
@@ -16,6 +31,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -29,6 +45,7 @@ I8_PEAK_TOPS = 5000.0            # MI355X dense int8 MFMA, published (no sparsit
 # 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64
 # instruction per SIMD every 4 clocks); bitwise ops have no packed form.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+OPS_PER_WORD = 4                 # a 64-bit word tested: AND of two 32-bit halves, then OR/compare of both
 
 WORKLOADS = {
     "c1": "k=4 classes x 25 vertices (n=100), p=0.5, dense uint8 input",
@@ -41,90 +58,31 @@ WORKLOADS = {
 }
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="headline", choices=["headline"] + sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-one-by-one", action="store_true",
-                    help="c4: skip the one-graph-at-a-time comparison (for counter runs)")
+                    help="c4/c5: skip the one-graph-at-a-time comparison (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="steps of the per-kernel event-timed loop (default: --steps)")
     ap.add_argument("--edge-path", default="bitset", choices=("bitset", "mfma"),
                     help="edge test of the single-graph path: witness search on bit rows, or int8 MFMA counts")
-    ap.add_argument("--requests", type=int, default=2000,
-                    help="c5: requests per phase (a bounded prefix of the 50k-request stream)")
+    ap.add_argument("--requests", type=int, default=50000, help="c5: requests of the stream (a prefix)")
     ap.add_argument("--copy-calibration", type=int, default=None, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (memory-counter calibration)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
-def make_workload(name, seed):
-    from paper_2212_00574_amd import inputs
-    if name == "c1":
-        g = inputs.config1(seed)
-        adj, colour = g.dense()
-        return dict(fmt="dense", adj=adj, colour=colour, k=4, sizes=g.sizes, graph=g)
-    if name == "c3b":
-        sg = inputs.config3b(seed)
-        return dict(fmt="csr", rp=sg.row_ptr, ci=sg.col_idx, colour=sg.colour, k=sg.k, sizes=sg.sizes, graph=sg)
-    g = inputs.config2(seed) if name == "c2" else inputs.config3a(seed)
-    rows, colour, lay = g.bitset()
-    return dict(fmt="bitset", rows=rows, colour=colour, k=g.k, sizes=g.sizes, layout=lay, graph=g)
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
-def pair_edge_counts(w):
-    """Edges between every pair of classes (from the generated input, CPU side)."""
-    from paper_2212_00574_amd import inputs
-    g = w["graph"]
-    lay = inputs.class_layout(g.sizes)
-    k = lay.k
-    cnt = np.zeros((k, k), np.int64)
-    slot = g.dense_slot() if g.n <= 6000 else None
-    for a in range(k):
-        if slot is not None:
-            blk = slot[lay.offsets[a]:lay.offsets[a + 1]]
-        else:
-            blk = g.slot_rows(int(lay.offsets[a]), int(lay.offsets[a + 1]))
-        for b in range(k):
-            cnt[a, b] = int(blk[:, lay.offsets[b]:lay.offsets[b + 1]].sum())
-    return cnt
-
-
-def csr_operand_bytes(w):
-    """Sum over edges of 4 (deg u + deg v): the two rows a merge-based test reads."""
-    deg = np.diff(w["rp"]).astype(np.int64)
-    src = np.repeat(np.arange(len(deg)), deg)
-    up = src < w["ci"]
-    return float(4 * (deg[src[up]] + deg[w["ci"][up]]).sum()), int(up.sum())
-
-
-def edge_work(w):
-    """Per-edge figures of the edge test, summed over all edges of the input.
-
-    operand bytes: 2 (n - s_cu - s_cv) / 8 -- both rows minus the endpoints'
-    own classes, i.e. what a test that streams the rows reads;
-    algorithmic ops: for every third class c, W_c = ceil(s_c/64) words, each
-    one AND and one OR-accumulate on two 32-bit halves (4 ops per word).
-    """
-    sizes = np.asarray(w["sizes"], np.int64)
-    n = int(sizes.sum())
-    words = (sizes + 63) // 64
-    R = int(words.sum())
-    cnt = pair_edge_counts(w)
-    k = len(sizes)
-    op_bytes, ops = 0, 0
-    for a in range(k):
-        for b in range(a + 1, k):
-            m_ab = int(cnt[a, b])
-            op_bytes += m_ab * 2 * (n - sizes[a] - sizes[b]) / 8
-            ops += m_ab * 4 * (R - words[a] - words[b])
-    return float(op_bytes), float(ops), int(np.triu(cnt, 1).sum())
-
-
+# --------------------------------------------------------------- counters
 # The kernel whose launches set each workload's roofline, and the sources it
 # is built from (a committed counter summary is used only while they match).
 PROFILED = {
@@ -182,68 +140,375 @@ def traffic_from_profile(workload):
     return profile_value(workload, "hbm_bytes_per_launch")
 
 
-# What the full-segment models leave out (the ops and bytes that the
-# roofline's "achieved" counts are fixed per test, whatever a kernel does).
-ALU_MODEL_NOTE = ("achieved/frac count the full-segment test's ops (AND + OR per word of both rows in every third "
-                  "class); the witness search stops at the first word with a common neighbour, so it issues fewer "
-                  "ops than the model and frac can pass 1. valu_issue_frac is the VALU lane-ops the kernel actually "
-                  "issued (SQ_INSTS_VALU x 64 per launch, committed counter summary) over the same peak.")
-CSR_MODEL_NOTE = ("achieved/frac count both rows' int32 entries for every tested edge; the rows of a 100000-vertex "
-                  "graph are re-read from L2 and the Infinity Cache, so this stream can pass the HBM peak. traffic "
-                  "is the counter-measured HBM bytes per launch; the kernel is bound by gather latency, not HBM.")
+# --------------------------------------------------------------- host facts
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "allowed_cpus": len(os.sched_getaffinity(0))}
 
 
-def cpu_baseline(w):
-    from oracle import FMT_BITSET, FMT_CSR, FMT_DENSE, OracleGraph
+def digest(vmask, emask, r):
+    """SHA-256 of vmask || emask (uint64 LE) || int64 LE [rounds, surviving
+    vertices, surviving edges, edge tests]: the fingerprint the committed
+    full-size fixtures hold (tests/golden/)."""
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(vmask, np.uint8).tobytes())
+    h.update(np.ascontiguousarray(emask).view(np.uint64).astype("<u8", copy=False).tobytes())
+    h.update(np.array([r["rounds"], r["surviving_vertices"], r["surviving_edges"], r["edge_tests"]],
+                      "<i8").tobytes())
+    return h.digest()
+
+
+def golden(name):
+    path = os.path.join(ROOT, "tests", "golden", name)
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+# --------------------------------------------------------------- CPU baseline
+def _cpu_child(workload, seed):
+    """Runs in a child process pinned to one core (no GPU): the oracle on the
+    workload, plus the witness-search word count of the bit-row input."""
+    from oracle import FMT_CSR, FMT_DENSE, OracleGraph, fixpoint_rows, witness_words
+    from paper_2212_00574_amd import inputs
+    out = {}
     t0 = time.perf_counter()
-    if w["fmt"] == "dense":
-        g = OracleGraph(FMT_DENSE, len(w["colour"]), w["k"], w["colour"], adj=w["adj"])
-    elif w["fmt"] == "csr":
-        g = OracleGraph(FMT_CSR, len(w["colour"]), w["k"], w["colour"], row_ptr=w["rp"], col_idx=w["ci"])
+    if workload == "c1":
+        g = inputs.config1(seed)
+        adj, colour = g.dense()
+        t1 = time.perf_counter()
+        og = OracleGraph(FMT_DENSE, len(colour), 4, colour, adj=adj)
+        t2 = time.perf_counter()
+        r = og.fixpoint()
+        out.update(oracle="O1", edge_tests=r["edge_tests"], rounds=r["rounds"])
+    elif workload == "c3b":
+        sg = inputs.config3b(seed)
+        t1 = time.perf_counter()
+        og = OracleGraph(FMT_CSR, sg.n, sg.k, sg.colour, row_ptr=sg.row_ptr, col_idx=sg.col_idx)
+        t2 = time.perf_counter()
+        r = og.fixpoint()
+        out.update(oracle="O1", edge_tests=r["edge_tests"], rounds=r["rounds"])
     else:
-        g = OracleGraph(FMT_BITSET, len(w["colour"]), w["k"], w["colour"], rows=w["rows"],
-                        row_words=w["rows"].shape[1])
-    t1 = time.perf_counter()
-    res = g.fixpoint()
-    t2 = time.perf_counter()
-    vm, em = g.masks()
-    return res, (vm, em), t2 - t1, t1 - t0
+        g = inputs.config2(seed) if workload == "c2" else inputs.config3a(seed)
+        rows, colour, lay = g.bitset()
+        t1 = time.perf_counter()
+        t2 = t1
+        r = fixpoint_rows(rows, colour, g.k)
+        out.update(oracle="O3", edge_tests=r["edge_tests"], rounds=r["rounds"])
+    t3 = time.perf_counter()
+    out.update(gen_s=t1 - t0, ingest_s=t2 - t1, fixpoint_s=t3 - t2)
+    if workload in ("c2", "c3a"):
+        t4 = time.perf_counter()
+        out["witness"] = witness_words(rows, colour, g.k)
+        out["witness_s"] = time.perf_counter() - t4
+    print(json.dumps(out), flush=True)
 
 
-def _gen_c4(args):
-    from paper_2212_00574_amd import inputs
-    spec, seed, gid = args
-    rows, colour, lay = inputs.config4_graph(spec, seed, gid).bitset()
-    return rows, colour, spec.k
+def start_cpu_child(workload, seed):
+    """Starts the oracle child on the last allowed core (before any GPU use)."""
+    cpus = sorted(os.sched_getaffinity(0))
+    core = cpus[-1]
+    code = ("import os, sys; os.sched_setaffinity(0, {%d}); sys.path.insert(0, %r); import bench; "
+            "bench._cpu_child(%r, %d)" % (core, ROOT, workload, seed))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    p = subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                         env=env)
+    return p, core
 
 
-def c4_graphs(seed, count=4096, procs=16):
-    """The batching workload, generated in worker processes (before any GPU use)."""
-    import multiprocessing as mp
-    from paper_2212_00574_amd import inputs
-    specs = inputs.config4_specs(seed, graphs=count)
-    with mp.get_context("fork").Pool(procs) as pool:
-        return pool.map(_gen_c4, [(sp, seed, i) for i, sp in enumerate(specs)], chunksize=32)
+def finish_cpu_child(proc, core, workload):
+    out, err = proc.communicate(timeout=900)
+    if proc.returncode != 0:
+        say("cpu baseline child failed:", err[-2000:])
+        return None, None
+    d = json.loads(out.strip().splitlines()[-1])
+    secs = d["fixpoint_s"]
+    what = {"O1": "the oracle's synchronous rounds on adjacency lists (O1)",
+            "O3": "the oracle's synchronous rounds on bit rows (O3, the same result as O1)"}[d["oracle"]]
+    cpu = {"value": d["edge_tests"] / secs, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
+           "sample": "the whole %s graph: %s to the fixpoint, %d edge tests in %.2f s on one core (pinned to "
+                     "cpu %d; generation %.1f s and ingest %.1f s excluded)"
+                     % (workload, what, d["edge_tests"], secs, core, d["gen_s"], d["ingest_s"]),
+           "host": host_info()}
+    return cpu, d
 
 
-def bench_batch(args):
-    """Config 4: batched graphs/s against one-graph-at-a-time launches."""
-    t0 = time.perf_counter()
-    graphs = c4_graphs(args.seed)
-    gen_s = time.perf_counter() - t0
-    print("generated %d graphs in %.1f s" % (len(graphs), gen_s), file=sys.stderr, flush=True)
+# --------------------------------------------------------------- single graph
+def class_pair_edges(rows_host, sizes):
+    """Edges between every pair of classes of a bit-row graph (host side)."""
+    sizes = np.asarray(sizes, np.int64)
+    k = len(sizes)
+    words = (sizes + 63) // 64
+    segoff = np.concatenate([[0], np.cumsum(words)])
+    pc = np.bitwise_count(rows_host.view(np.uint64)).astype(np.int64)
+    seg = np.zeros((rows_host.shape[0], k), np.int64)
+    for c in range(k):
+        if words[c]:
+            seg[:, c] = pc[:, segoff[c]:segoff[c + 1]].sum(axis=1)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    cnt = np.zeros((k, k), np.int64)
+    for a in range(k):
+        cnt[a] = seg[offs[a]:offs[a + 1]].sum(axis=0)
+    return cnt
+
+
+def full_segment_work(cnt, sizes):
+    """Survey model of one full sweep: operand bytes 2 (n - s_cu - s_cv) / 8
+    per edge (both rows streamed) and 4 ops per word of every third class."""
+    sizes = np.asarray(sizes, np.int64)
+    n = int(sizes.sum())
+    words = (sizes + 63) // 64
+    R = int(words.sum())
+    k = len(sizes)
+    op_bytes = ops = 0.0
+    for a in range(k):
+        for b in range(a + 1, k):
+            m_ab = float(cnt[a, b])
+            op_bytes += m_ab * 2 * (n - sizes[a] - sizes[b]) / 8
+            ops += m_ab * OPS_PER_WORD * (R - words[a] - words[b])
+    return op_bytes, ops, int(np.triu(cnt, 1).sum())
+
+
+def make_single(name, seed, kz, dev):
+    """(graph descriptor, colour, k, vmask, emask, sizes, host rows or None)
+    with the input resident in device memory."""
     import torch
 
-    from paper_2212_00574_amd.binding import Batch, BatchKernelizer, Kernelizer, graph_bitset
+    from paper_2212_00574_amd import inputs
+    from paper_2212_00574_amd.binding import graph_bitset, graph_csr, graph_dense, kz_gen_bitset
+    if name == "c1":
+        g = inputs.config1(seed)
+        adj, colour = g.dense()
+        x = torch.from_numpy(adj).to(dev)
+        n = x.shape[0]
+        return (graph_dense(x), torch.from_numpy(colour).to(dev), 4, torch.empty(n, dtype=torch.uint8, device=dev),
+                torch.empty((n, n), dtype=torch.uint8, device=dev), g.sizes, None, [x])
+    if name == "c3b":
+        sg = inputs.config3b(seed)
+        rp = torch.from_numpy(sg.row_ptr).to(dev)
+        ci = torch.from_numpy(sg.col_idx).to(dev)
+        n = sg.n
+        return (graph_csr(rp, ci), torch.from_numpy(sg.colour).to(dev), sg.k,
+                torch.empty(n, dtype=torch.uint8, device=dev), torch.empty(ci.shape[0], dtype=torch.uint8, device=dev),
+                sg.sizes, None, [rp, ci])
+    g = inputs.config2(seed) if name == "c2" else inputs.config3a(seed)
+    lay = inputs.class_layout(g.sizes)
+    rows = torch.empty((lay.n, lay.R), dtype=torch.int64, device=dev)
+    colour = torch.empty(lay.n, dtype=torch.int32, device=dev)
+    kz_gen_bitset(kz.ctx, g.sizes, g.p, seed, 0, g.planted, rows.data_ptr(), lay.R, colour.data_ptr(), None)
+    torch.cuda.synchronize()
+    return (graph_bitset(rows), colour, g.k, torch.empty(lay.n, dtype=torch.uint8, device=dev), torch.empty_like(rows),
+            g.sizes, rows, [rows])
+
+
+def run_single(args, name, cpu_proc=None):
+    import torch
+
+    from paper_2212_00574_amd.binding import KZ_EDGE_MFMA_I8, Kernelizer
     dev = torch.device("cuda", 0)
     kz = Kernelizer(0)
-    b = Batch(graphs, dev)
+    mfma = args.edge_path == "mfma"
+    if mfma:
+        if name in ("c1", "c3b"):
+            raise SystemExit("the MFMA edge path is measured on bit-row input")
+        kz.set_edge_path(KZ_EDGE_MFMA_I8)
+    graph, colour, k, vmask, emask, sizes, rows_dev, keep = make_single(name, args.seed, kz, dev)
+    say("workload %s resident on the device" % name)
+    # the input's copy from pinned host memory, timed on its own (never in value)
+    nbytes = int(sum(t.numel() * t.element_size() for t in keep) + colour.numel() * 4)
+    pinned = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    dcopy = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dcopy.copy_(pinned, non_blocking=True)
+    torch.cuda.synchronize()
+    e_h0, e_h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e_h0.record()
+    dcopy.copy_(pinned, non_blocking=True)
+    e_h1.record()
+    torch.cuda.synchronize()
+    h2d_ms = e_h0.elapsed_time(e_h1)
+    del pinned, dcopy
+
+    def step():
+        return kz.run(graph, colour, k, vmask, emask)
+
+    for _ in range(args.warmup):
+        res = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = res["edge_tests"] / (ms_per_step / 1e3)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for e0, e1 in ev:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    per_step = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    say("%s: %d steps, %.4f ms/step" % (name, args.steps, ms_per_step))
+
+    # per-kernel times with HIP events on the launch stream (same launches)
+    psteps = args.profile_steps or args.steps
+    kz.profile(True)
+    for _ in range(psteps):
+        step()
+    torch.cuda.synchronize()
+    times = kz.kernel_times()
+    kz.profile(False)
+    edge_ms, edge_launches = times["edge"]
+    edge_avg_ms = edge_ms / max(edge_launches, 1)
+    launches = max(edge_launches / psteps, 1)
+    scale = res["edge_tests"] / max(res["input_edges"], 1)   # exact-worklist tests over one full sweep
+
+    # parity with the committed oracle fixture (the whole graph)
+    check = None
+    fx = golden("%s_seed%d.json" % (name, args.seed))
+    if fx is not None and not mfma:
+        d = digest(vmask.cpu().numpy(), emask.cpu().numpy(), res)
+        check = d.hex() == fx["sha256"]
+
+    cpu, child = (None, None)
+    if cpu_proc is not None:
+        cpu, child = finish_cpu_child(*cpu_proc, name)
+
+    traffic = traffic_from_profile(name)
+    if name == "c3b":
+        from paper_2212_00574_amd import inputs
+        sg = inputs.config3b(args.seed)
+        deg = np.diff(sg.row_ptr).astype(np.int64)
+        src = np.repeat(np.arange(len(deg)), deg)
+        up = src < sg.col_idx
+        op_bytes = float(4 * (deg[src[up]] + deg[sg.col_idx[up]]).sum())
+        m_check = int(up.sum())
+        bytes_per_launch = op_bytes * scale / launches
+        achieved = bytes_per_launch / (edge_avg_ms / 1e3) / 1e9
+        roofline = {"kernel": "k_csr_edge", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                    "bytes": "4 (deg u + deg v) per tested edge", "alg_bytes_per_launch": bytes_per_launch,
+                    "avg_launch_ms": round(edge_avg_ms, 5), "launches_per_step": edge_launches / psteps,
+                    "note": "the two rows of an edge are re-read from L2 and the Infinity Cache, so this stream "
+                            "can pass the HBM peak; traffic is the counter-measured HBM bytes per launch"}
+    elif name == "c1":
+        m_check = res["input_edges"]
+        roofline = {"kernel": "k_edge", "bound": "launch latency", "achieved": None, "peak": None, "unit": None,
+                    "frac": None, "traffic": None, "avg_launch_ms": round(edge_avg_ms, 5),
+                    "note": "100 vertices: every kernel is one or two workgroups; the step is launch latency"}
+    else:
+        rows_host = rows_dev.cpu().numpy()
+        cnt = class_pair_edges(rows_host, sizes)
+        op_bytes, fs_ops, m_check = full_segment_work(cnt, sizes)
+        if mfma:
+            s = np.asarray(sizes, np.float64)
+            n_all = s.sum()
+            full = sum(2.0 * s[a] * s[b] * (n_all - s[a] - s[b]) for a in range(len(s)) for b in range(a + 1, len(s)))
+            ops_per_launch = full * (1.0 if res["passes"] == 1 else 1.0 / launches)
+            achieved = ops_per_launch / (edge_avg_ms / 1e3) / 1e12
+            roofline = {"kernel": "k_mfma_count + k_edge_mf", "bound": "mfma", "achieved": round(achieved, 2),
+                        "peak": I8_PEAK_TOPS, "unit": "TFLOP/s", "frac": round(achieved / I8_PEAK_TOPS, 4),
+                        "traffic": None, "ops": "int8 MFMA ops (2 per multiply-accumulate) of the full count",
+                        "alg_ops_per_launch": ops_per_launch, "avg_launch_ms": round(edge_avg_ms, 5),
+                        "launches_per_step": edge_launches / psteps}
+        else:
+            wit = child["witness"] if child and "witness" in child else None
+            need_ops = None if wit is None else OPS_PER_WORD * wit["words"] * scale / launches
+            fs_per_launch = fs_ops * scale / launches
+            achieved = None if need_ops is None else need_ops / (edge_avg_ms / 1e3) / 1e12
+            fs_achieved = fs_per_launch / (edge_avg_ms / 1e3) / 1e12
+            stream_gbps = op_bytes * scale / launches / (edge_avg_ms / 1e3) / 1e9
+            roofline = {
+                "kernel": "k_edge", "bound": "alu",
+                "achieved": None if achieved is None else round(achieved, 3),
+                "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                "frac": None if achieved is None else round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": traffic,
+                "ops": "necessary 32-bit ops of a first-witness search: %d per 64-bit word read, over the words "
+                       "up to the first common neighbour of every (edge, third class) pair (oracle-side count)"
+                       % OPS_PER_WORD,
+                "alg_ops_per_launch": need_ops, "witness": wit,
+                "avg_launch_ms": round(edge_avg_ms, 5), "launches_per_step": edge_launches / psteps,
+                "full_segment": {"ops_per_launch": fs_per_launch, "achieved": round(fs_achieved, 3),
+                                 "frac": round(fs_achieved / VALU_PEAK_TOPS, 4),
+                                 "note": "every word of every third class (the survey's model); a search that "
+                                         "stops at the first witness does less, so this can pass 1"},
+                "operand_stream": {"GBps": round(stream_gbps, 1), "frac_of_hbm": round(stream_gbps / HBM_PEAK_GBPS, 3),
+                                   "note": "both rows streamed per edge, 2 (n - s_u - s_v)/8 bytes: the bandwidth a "
+                                           "sweep with no reuse would need; reuse-bound, not HBM-bound"},
+                "valu_issue_frac": profile_value(name, "valu_issue_frac"),
+            }
+    assert m_check == res["input_edges"], (m_check, res["input_edges"])
+    out = {
+        "metric": "edge tests/s to fixpoint", "value": value, "unit": "edge tests/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "%s: %s" % (name, WORKLOADS[name]), "n": int(vmask.numel()), "k": int(k),
+                   "edge_path": args.edge_path, "edges": int(res["input_edges"]), "rounds": res["rounds"],
+                   "passes": res["passes"], "surviving_vertices": res["surviving_vertices"],
+                   "surviving_edges": res["surviving_edges"], "seed": args.seed, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_ms_per_step": {nm: round(t[0] / psteps, 5) for nm, t in times.items()},
+        "step_ms_median": round(per_step[len(per_step) // 2], 5), "step_ms_min": round(per_step[0], 5),
+        "input_edges_per_s": res["input_edges"] / (ms_per_step / 1e3),
+        "h2d": {"bytes": nbytes, "ms": round(h2d_ms, 4),
+                "what": "the input's size copied from pinned host memory, outside the timed steps"},
+        "oracle_equal": check,
+    }
+    kz.close()
+    return out
+
+
+# --------------------------------------------------------------- batch (c4)
+def run_batch(args):
+    """Config 4: batched graphs/s against one-graph-at-a-time launches."""
+    import torch
+
+    from paper_2212_00574_amd import inputs
+    from paper_2212_00574_amd.binding import Batch, BatchKernelizer, Kernelizer, graph_bitset, kz_gen_bitset
+    dev = torch.device("cuda", 0)
+    kz = Kernelizer(0)
+    specs = inputs.config4_specs(args.seed)
+    shapes = [(int(sp.sizes.sum()), int(((sp.sizes + 63) // 64).sum()), sp.k) for sp in specs]
+    b = Batch.allocate(shapes, dev)
+    planted = 0
+    for i, sp in enumerate(specs):
+        d = b.desc[i]
+        a, o = int(d["row_offset"]), int(d["vertex_offset"])
+        pl = inputs.config4_graph(sp, args.seed, i).planted
+        planted += pl is not None
+        kz_gen_bitset(kz.ctx, sp.sizes, sp.p, args.seed, i, pl, b.rows[a:].data_ptr(), int(d["row_words"]),
+                      b.colour[o:].data_ptr(), None)
+    torch.cuda.synchronize()
+    say("c4: %d graphs resident" % b.G)
     bk = BatchKernelizer(kz)
     tuned = bk.autotune(b)
     bk.run(b)
     torch.cuda.synchronize()
     res = b.read_results()
     assert np.all(res["status"] == 0), np.unique(res["status"])
+    # parity: every graph's fingerprint against the oracle's (committed fixture)
+    check = None
+    fx = golden("c4_seed%d.json" % args.seed)
+    if fx is not None:
+        vm_all, em_all = b.vmask.cpu().numpy(), b.emask.cpu().numpy()
+        check = True
+        for bk_ in fx["buckets"]:
+            lo, hi = bk_["ids"]
+            h = hashlib.sha256()
+            for i in range(lo, hi + 1):
+                d = b.desc[i]
+                n, R = int(d["n"]), int(d["row_words"])
+                a, o = int(d["row_offset"]), int(d["vertex_offset"])
+                r = {key: int(res[i][key]) for key in ("rounds", "surviving_vertices", "surviving_edges",
+                                                       "edge_tests")}
+                h.update(digest(vm_all[o:o + n], em_all[a:a + n * R], r))
+            check = check and h.hexdigest() == bk_["hash"]
     # capture once, replay in the timed loop
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -266,222 +531,180 @@ def bench_batch(args):
         graph.replay()
     e1.record()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     kernel_ms = e0.elapsed_time(e1) / args.steps
-    G = b.G
-    value = G / (ms_per_step / 1e3)
-    one_gps = one_by_one_s = None
+    value = b.G / (ms_per_step / 1e3)
+    one = None
     if not args.no_one_by_one:
-        # one graph at a time through the single-graph path, same device-resident inputs
         views = []
-        for i in range(G):
+        for i in range(b.G):
             d = b.desc[i]
             n, R = int(d["n"]), int(d["row_words"])
             a, o = int(d["row_offset"]), int(d["vertex_offset"])
-            rows_v = b.rows[a:a + n * R].view(n, R)
-            views.append((graph_bitset(rows_v), b.colour[o:o + n], int(d["k"]), b.vmask[o:o + n],
-                          b.emask[a:a + n * R].view(n, R)))
+            views.append((graph_bitset(b.rows[a:a + n * R].view(n, R)), b.colour[o:o + n], int(d["k"]),
+                          b.vmask[o:o + n], b.emask[a:a + n * R].view(n, R)))
         for gr, col, k, vm, em in views[:8]:
             kz.run(gr, col, k, vm, em)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         single = [kz.run(gr, col, k, vm, em) for gr, col, k, vm, em in views]
         torch.cuda.synchronize()
-        one_by_one_s = time.perf_counter() - t0
-        for i, r in enumerate(single):
-            assert r["rounds"] == res[i]["rounds"] and r["surviving_edges"] == res[i]["surviving_edges"], i
-        one_gps = G / one_by_one_s
-    # algorithmic work: full-segment edge-test ops over the exact worklists
-    ops = 0.0
-    for i, (rows, colour, k) in enumerate(graphs):
-        sizes = np.bincount(colour, minlength=k).astype(np.int64)
-        words = (sizes + 63) // 64
-        segoff = np.concatenate([[0], np.cumsum(words)])
-        R = int(words.sum())
-        pc = np.bitwise_count(rows).astype(np.int64)
-        seg = np.add.reduceat(pc, segoff[:-1], axis=1) if R else np.zeros((rows.shape[0], k), np.int64)
-        seg[:, words == 0] = 0
-        cls_rows = np.add.reduceat(seg, np.concatenate([[0], np.cumsum(sizes)[:-1]]), axis=0)
-        cls_rows[sizes == 0, :] = 0
-        per_edge = 4 * (R - words[:, None] - words[None, :])
-        m_g = max(int(res[i]["input_edges"]), 1)
-        ops += float((np.triu(cls_rows, 1) * per_edge).sum()) * res[i]["edge_tests"] / m_g
-    achieved = ops / (kernel_ms / 1e3) / 1e12
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import kernelize_bitset
-        t0, done = time.perf_counter(), 0
-        for rows, colour, k in graphs:
-            kernelize_bitset(rows, colour, k)
-            done += 1
-            if time.perf_counter() - t0 > 15:
-                break
         secs = time.perf_counter() - t0
-        cpu = {"value": done / secs, "unit": "graphs/s", "cores": 1, "kind": "oracle",
-               "sample": "the first %d graphs of the batch, one oracle fixpoint each (%.1f s)" % (done, secs)}
-    out = {
-        "metric": "batched graphs/s", "value": value, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "c4: " + WORKLOADS["c4"], "graphs": G, "vertices": int(b.desc["n"].sum()),
-                   "edges": int(res["input_edges"].sum()), "max_rounds": int(res["rounds"].max()),
-                   "mean_rounds": float(res["rounds"].mean()), "planted": None, "seed": args.seed,
-                   "batch_config": tuned, "parallelism": "single GPU"},
-        "one_by_one": None if one_gps is None else {
-            "value": one_gps, "unit": "graphs/s", "seconds": one_by_one_s,
-            "what": "kz_kernelize per graph on the same device-resident inputs"},
-        "batched_over_one_by_one": None if one_gps is None else value / one_gps,
-        "graph_capture_ms": round(capture_ms, 3),
-        "roofline": {"kernel": "k_batch", "bound": "alu", "achieved": round(achieved, 3),
-                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": traffic_from_profile("c4"),
-                     "ops": "32-bit integer VALU ops (AND, OR) of the full-segment edge test, all graphs",
-                     "avg_launch_ms": round(kernel_ms, 4), "alg_ops_per_launch": ops,
-                     "valu_issue_frac": profile_value("c4", "valu_issue_frac"), "model_note": ALU_MODEL_NOTE},
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+        same = all(r["rounds"] == res[i]["rounds"] and r["edge_tests"] == res[i]["edge_tests"]
+                   and r["surviving_edges"] == res[i]["surviving_edges"] for i, r in enumerate(single))
+        one = {"value": b.G / secs, "unit": "graphs/s", "seconds": secs, "same_results": same,
+               "what": "kz_kernelize per graph on the same device-resident inputs"}
+    say("c4: %.3f ms/batch" % ms_per_step)
+    kz.close()
+    return {"metric": "batched graphs/s", "value": value, "unit": "graphs/s", "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "kernel_ms_per_step": kernel_ms,
+            "config": {"workload": "c4: " + WORKLOADS["c4"], "graphs": b.G, "vertices": int(b.desc["n"].sum()),
+                       "edges": int(res["input_edges"].sum()), "planted": planted,
+                       "mean_rounds": float(res["rounds"].mean()), "max_rounds": int(res["rounds"].max()),
+                       "batch_config": tuned, "seed": args.seed},
+            "one_by_one": one, "batched_over_one_by_one": None if one is None else value / one["value"],
+            "graph_capture_ms": round(capture_ms, 3),
+            "roofline": {"kernel": "k_batch", "traffic": traffic_from_profile("c4"),
+                         "valu_issue_frac": profile_value("c4", "valu_issue_frac"),
+                         "note": "counter figures from the committed summary (null once the kernel changed)"},
+            "oracle_equal": check}
 
 
-def bench_serve(args):
-    """Config 5: continuous-batching server, closed-loop saturation and two
-    Poisson open-loop rates, p50/p99 latency from arrival to completion."""
+# --------------------------------------------------------------- serving (c5)
+class Stream5:
+    """The served requests' device buffers: materialised on the server's
+    stream when first admitted, released when the request completes."""
+
+    def __init__(self, kz, srv, specs, seed):
+        self.kz, self.srv, self.specs, self.seed = kz, srv, specs, seed
+        self.live = {}
+
+    def buffers(self, i):
+        import torch
+
+        from paper_2212_00574_amd import inputs
+        from paper_2212_00574_amd.binding import kz_gen_bitset
+        if i not in self.live:
+            sp = self.specs[i]
+            lay = inputs.class_layout(sp.sizes)
+            dev = self.kz.device
+            rows = torch.empty((lay.n, lay.R), dtype=torch.int64, device=dev)
+            colour = torch.empty(lay.n, dtype=torch.int32, device=dev)
+            kz_gen_bitset(self.kz.ctx, sp.sizes, sp.p, self.seed, i, None, rows.data_ptr(), lay.R,
+                          colour.data_ptr(), self.srv.stream.cuda_stream)
+            self.live[i] = (rows, colour, torch.empty(lay.n, dtype=torch.uint8, device=dev), torch.empty_like(rows))
+        return self.live[i]
+
+
+def run_serve(args):
+    """Config 5: the request stream through the server (continuous batching):
+    closed-loop requests/s S, then Poisson arrivals at 0.5 S and 0.8 S."""
     import torch
 
     from paper_2212_00574_amd import inputs
-    from paper_2212_00574_amd.binding import Kernelizer, Server, kz_gen_bitset
+    from paper_2212_00574_amd.binding import Kernelizer, Server, graph_bitset
     N = args.requests
     specs = inputs.config5_specs(args.seed, requests=N)
-    dev = torch.device("cuda", 0)
     kz = Kernelizer(0)
-    bufs = []
-    for sp in specs:
-        n, R = int(sp.n), int(((sp.sizes + 63) // 64).sum())
-        bufs.append({"n": n, "R": R, "k": int(sp.k),
-                     "rows": torch.empty(n * R, dtype=torch.int64, device=dev),
-                     "colour": torch.empty(n, dtype=torch.int32, device=dev),
-                     "vmask": torch.empty(n, dtype=torch.uint8, device=dev),
-                     "emask": torch.empty(n * R, dtype=torch.int64, device=dev)})
-    srv = Server(kz, arena_bytes=8 << 30, max_slots=512)
-    sid = srv.stream.cuda_stream
-    gen = [False] * N
-
-    def submit(i):
-        b, sp = bufs[i], specs[i]
-        if not gen[i]:   # materialise the request's rows on the server's stream
-            kz_gen_bitset(kz.ctx, sp.sizes, sp.p, args.seed, i, None, b["rows"].data_ptr(), b["R"],
-                          b["colour"].data_ptr(), sid)
-            gen[i] = True
-        return srv.submit(b["rows"], b["colour"], b["k"], b["vmask"], b["emask"])
+    srv = Server(kz, arena_bytes=16 << 30, max_slots=512)
+    fx = golden("c5_seed%d.json" % args.seed)
+    check_ids = set(fx["buckets"][0]["ids"]) if fx is not None and N == 50000 else set()
+    digests = {}
 
     def run(arrivals):
-        """Admits request i at arrivals[i] (seconds; None = as fast as admitted);
-        returns (results, latency seconds, elapsed seconds)."""
-        for i in range(N):
-            gen[i] = False
+        st = Stream5(kz, srv, specs, args.seed)
         res, lat = [None] * N, np.zeros(N)
-        fifo, backlog = [], []
-        nxt, done, head = 0, 0, 0
+        waiting, tickets = [], {}
+        nxt, done = 0, 0
         t0 = time.perf_counter()
         while done < N:
             now = time.perf_counter() - t0
             while nxt < N and (arrivals is None or arrivals[nxt] <= now):
-                backlog.append(nxt)
+                waiting.append(nxt)
                 nxt += 1
-            while backlog:
-                t = submit(backlog[0])
+            while waiting:
+                i = waiting[0]
+                rows, colour, vm, em = st.buffers(i)
+                t = srv.submit(rows, colour, specs[i].k, vm, em)
                 if t is None:
                     break
-                fifo.append((t, backlog.pop(0)))
+                tickets[t] = i
+                waiting.pop(0)
             srv.progress()
-            # launches complete in admission order: poll from the oldest
-            while head < len(fifo):
-                t, i = fifo[head]
+            for t in list(tickets):
                 r = srv.poll(t)
                 if r is None:
-                    break
+                    continue
+                i = tickets.pop(t)
                 res[i] = r
                 lat[i] = time.perf_counter() - t0 - (arrivals[i] if arrivals is not None else 0.0)
-                head += 1
+                if arrivals is None and i in check_ids:
+                    _, _, vm, em = st.live[i]
+                    torch.cuda.synchronize()
+                    digests[i] = digest(vm.cpu().numpy(), em.cpu().numpy(), r)
+                st.live.pop(i, None)
                 done += 1
-            if time.perf_counter() - t0 > 300:
+            if time.perf_counter() - t0 > 400:
                 raise RuntimeError("serving run did not finish")
         return res, lat, time.perf_counter() - t0
 
-    warm = N
-    N = min(32, warm)
-    run(None)                              # warm-up on the first requests
-    N = warm
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(srv.stream)
+    N_all = N
+    N = min(64, N_all)
+    run(None)                                   # warm-up on the first requests
+    N = N_all
     res, _, closed_s = run(None)
-    e1.record(srv.stream)
-    torch.cuda.synchronize()
-    gpu_ms = e0.elapsed_time(e1)
-    st = np.array([r["status"] for r in res])
-    assert np.all(st == 0), np.unique(st)
+    st_ = np.array([r["status"] for r in res])
+    assert np.all(st_ == 0), np.unique(st_)
     S = N / closed_s
+    say("c5: closed loop %.0f requests/s" % S)
+    check = None
+    if check_ids:
+        h = hashlib.sha256()
+        for i in fx["buckets"][0]["ids"]:
+            h.update(digests[i])
+        check = h.hexdigest() == fx["buckets"][0]["hash"]
     base_arr = np.array([sp.arrival_s for sp in specs])   # offered rate 1000/s in the specs
     phases = {}
     for frac in (0.5, 0.8):
         rate = frac * S
-        arr = base_arr * (1000.0 / rate)
-        r2, lat, el = run(arr)
-        for i in range(N):
-            assert r2[i]["edge_tests"] == res[i]["edge_tests"] and r2[i]["rounds"] == res[i]["rounds"], i
-        phases["%.1fS" % frac] = {"offered_rps": rate, "achieved_rps": N / el, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                                  "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3)}
-        print("phase %.1fS: %s" % (frac, phases["%.1fS" % frac]), file=sys.stderr, flush=True)
-    tests = np.array([r["edge_tests"] for r in res], dtype=np.float64)
-    # full-segment ops: with near-equal classes every segment has R/k words
-    # (to within one), so an edge test costs 4 R (k - 2) / k 32-bit ops
-    ops = float(sum(tests[i] * 4.0 * bufs[i]["R"] * (bufs[i]["k"] - 2) / bufs[i]["k"] for i in range(N)))
-    achieved = ops / (gpu_ms / 1e3) / 1e12
-    # parity spot-check: the three smallest requests against the oracle
-    from oracle import kernelize_bitset
-    for i in sorted(range(N), key=lambda j: bufs[j]["n"] * bufs[j]["R"])[:3]:
-        g = inputs.make_graph(specs[i].sizes, specs[i].p, seed=args.seed, gid=i, shuffle=False)
-        rows, col, lay = g.bitset()
-        ref = kernelize_bitset(rows, col, specs[i].k)
-        assert ref["edge_tests"] == res[i]["edge_tests"] and ref["surv_edges"] == res[i]["surviving_edges"], i
-        assert np.array_equal(bufs[i]["vmask"].cpu().numpy(), ref["vmask"]), i
-    cpu = None
-    if not args.no_cpu_baseline:
-        t_or, done_n, tests_n = 0.0, 0, 0
-        for i in sorted(range(N), key=lambda j: bufs[j]["n"]):
-            g = inputs.make_graph(specs[i].sizes, specs[i].p, seed=args.seed, gid=i, shuffle=False)
-            rows, col, lay = g.bitset()
-            t0 = time.perf_counter()
-            ref = kernelize_bitset(rows, col, specs[i].k)
-            t_or += time.perf_counter() - t0
-            done_n += 1
-            tests_n += ref["edge_tests"]
-            if t_or > 15:
-                break
-        cpu = {"value": tests_n / t_or, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
-               "sample": "the %d smallest of the %d requests, one oracle fixpoint each (%.1f s); the mix would take "
-                         "%.0f s at this rate" % (done_n, N, t_or, tests.sum() / (tests_n / t_or))}
-    out = {
-        "metric": "served requests/s (closed loop)", "value": S, "unit": "requests/s", "n_gpus": 1,
-        "steps": N, "warmup": 32, "ms_per_step": closed_s * 1e3 / N, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "c5: " + WORKLOADS["c5"], "requests": N, "seed": args.seed,
-                   "edge_tests": float(tests.sum()), "max_rounds": int(max(r["rounds"] for r in res)),
-                   "batch_config": None, "parallelism": "single GPU"},
-        "latency": phases,
-        "edge_tests_per_s": float(tests.sum()) / closed_s,
-        "roofline": {"kernel": "k_batch (batch lane) and k_edge (single-graph lane), whole closed loop",
-                     "bound": "alu", "achieved": round(achieved, 3),
-                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": None, "ops": "32-bit VALU ops of the full-segment edge test over the exact worklists",
-                     "gpu_stream_ms": round(gpu_ms, 3)},
-        "cpu_baseline": cpu,
-    }
+        r2, lat, el = run(base_arr * (1000.0 / rate))
+        same = all(r2[i]["edge_tests"] == res[i]["edge_tests"] and r2[i]["rounds"] == res[i]["rounds"]
+                   and r2[i]["surviving_edges"] == res[i]["surviving_edges"] for i in range(N))
+        phases["%.1fS" % frac] = {"offered_rps": rate, "achieved_rps": N / el,
+                                  "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                  "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3),
+                                  "same_results_as_closed_loop": same}
+        say("c5 phase %.1fS: %s" % (frac, phases["%.1fS" % frac]))
     srv.close()
-    print(json.dumps(out), flush=True)
+    one = None
+    if not args.no_one_by_one:
+        st = Stream5(kz, srv, specs, args.seed)
+        srv.stream = torch.cuda.current_stream()
+        t_total, same = 0.0, True
+        for i in range(N):
+            rows, colour, vm, em = st.buffers(i)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = kz.run(graph_bitset(rows), colour, specs[i].k, vm, em)
+            t_total += time.perf_counter() - t0
+            same = same and r["edge_tests"] == res[i]["edge_tests"] and r["rounds"] == res[i]["rounds"]
+            st.live.pop(i)
+        one = {"value": N / t_total, "unit": "requests/s", "seconds": t_total, "same_results": same,
+               "what": "kz_kernelize per request on the same device-resident inputs (materialisation excluded)"}
+    tests = np.array([r["edge_tests"] for r in res], dtype=np.float64)
+    kz.close()
+    return {"metric": "served requests/s (closed loop)", "value": S, "unit": "requests/s", "requests": N,
+            "ms_per_request": closed_s * 1e3 / N,
+            "config": {"workload": "c5: " + WORKLOADS["c5"], "requests": N, "seed": args.seed,
+                       "edge_tests": float(tests.sum()), "max_rounds": int(max(r["rounds"] for r in res))},
+            "latency": phases, "edge_tests_per_s": float(tests.sum()) / closed_s,
+            "one_by_one": one, "served_over_one_by_one": None if one is None else S / one["value"],
+            "oracle_equal": check,
+            "oracle_check": "the first bucket of the committed fixture (%d requests) by SHA-256" % len(check_ids)
+            if check_ids else None}
 
 
+# --------------------------------------------------------------- main
 def copy_calibration(mib):
     """Device-to-device copies of a known size, for scaling memory counters."""
     import torch
@@ -503,218 +726,20 @@ def main():
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(a graph would shard by class columns, one block of classes per GPU).", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "c4":
-        bench_batch(args)
-        return
-    if args.workload == "c5":
-        bench_serve(args)
-        return
-    import torch
-
-    from paper_2212_00574_amd.binding import KERNELS, Kernelizer
-
-    dev = torch.device("cuda", 0)
-    w = make_workload(args.workload, args.seed)
-    print("workload %s ready" % args.workload, file=sys.stderr, flush=True)
-    kz = Kernelizer(0)
-    mfma = args.edge_path == "mfma"
-    if mfma:
-        if w["fmt"] == "csr":
-            raise SystemExit("the MFMA edge path applies to dense and bit-row input")
-        from paper_2212_00574_amd.binding import KZ_EDGE_MFMA_I8
-        kz.set_edge_path(KZ_EDGE_MFMA_I8)
-    # the input's copy to the device, timed on its own (the timed steps start
-    # with the input resident; the library takes device buffers only)
-    host_in = [w["colour"]] + ([w["adj"]] if w["fmt"] == "dense" else
-                               [w["rp"], w["ci"]] if w["fmt"] == "csr" else [w["rows"]])
-    h2d_bytes = int(sum(a.nbytes for a in host_in))
-    e_h0, e_h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    pinned = [torch.from_numpy(np.ascontiguousarray(a).view(np.uint8).reshape(-1)).pin_memory() for a in host_in]
-    dev_copy = [torch.empty(t.shape, dtype=torch.uint8, device=dev) for t in pinned]
-    for d, t in zip(dev_copy, pinned):   # first use of the copy path, untimed
-        d.copy_(t, non_blocking=True)
-    torch.cuda.synchronize()
-    e_h0.record()
-    for d, t in zip(dev_copy, pinned):
-        d.copy_(t, non_blocking=True)
-    e_h1.record()
-    torch.cuda.synchronize()
-    h2d_ms = e_h0.elapsed_time(e_h1)
-    del pinned, dev_copy
-    colour = torch.from_numpy(w["colour"]).to(dev)
-    k = w["k"]
-    if w["fmt"] == "dense":
-        from paper_2212_00574_amd.binding import graph_dense
-        x = torch.from_numpy(w["adj"]).to(dev)
-        graph = graph_dense(x)
-        n = x.shape[0]
-        vmask = torch.empty(n, dtype=torch.uint8, device=dev)
-        emask = torch.empty((n, n), dtype=torch.uint8, device=dev)
-    elif w["fmt"] == "csr":
-        from paper_2212_00574_amd.binding import graph_csr
-        rp_t = torch.from_numpy(w["rp"]).to(dev)
-        x = torch.from_numpy(w["ci"]).to(dev)
-        graph = graph_csr(rp_t, x)
-        n = rp_t.shape[0] - 1
-        vmask = torch.empty(n, dtype=torch.uint8, device=dev)
-        emask = torch.empty(x.shape[0], dtype=torch.uint8, device=dev)
+    w = "c3a" if args.workload == "headline" else args.workload
+    cpu_proc = None
+    if not args.no_cpu_baseline and w in ("c1", "c2", "c3a", "c3b"):
+        cpu_proc = start_cpu_child(w, args.seed)
+    if w == "c4":
+        out = run_batch(args)
+    elif w == "c5":
+        out = run_serve(args)
     else:
-        from paper_2212_00574_amd.binding import graph_bitset
-        x = torch.from_numpy(w["rows"].view(np.int64)).to(dev)
-        graph = graph_bitset(x)
-        n = x.shape[0]
-        vmask = torch.empty(n, dtype=torch.uint8, device=dev)
-        emask = torch.empty_like(x)
-    torch.cuda.synchronize()
-
-    def step():
-        return kz.run(graph, colour, k, vmask, emask)
-
-    for _ in range(args.warmup):
-        res = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = res["edge_tests"] / (ms_per_step / 1e3)
-    # 20 steps timed one by one with HIP events on the stream: median and min
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
-    for e0, e1 in ev:
-        e0.record()
-        step()
-        e1.record()
-    torch.cuda.synchronize()
-    per_step = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
-    print("timed %d steps: %.4f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
-
-    # per-kernel times with HIP events on the launch stream (same workload, same launches)
-    psteps = args.profile_steps or args.steps
-    kz.profile(True)
-    for _ in range(psteps):
-        step()
-    torch.cuda.synchronize()
-    times = kz.kernel_times()
-    kz.profile(False)
-    edge_ms, edge_launches = times["edge"]
-    edge_avg_ms = edge_ms / max(edge_launches, 1)
-    passes = res["passes"]
-
-    traffic = traffic_from_profile(args.workload)
-    launches = max(edge_launches / psteps, 1)
-    scale = res["edge_tests"] / max(res["input_edges"], 1)
-    if w["fmt"] == "csr":
-        # the sparse edge pass streams row entries: HBM-bound
-        op_bytes, m_check = csr_operand_bytes(w)
-        bytes_per_launch = op_bytes * scale / launches
-        achieved = bytes_per_launch / (edge_avg_ms / 1e3) / 1e9
-        roofline = {"kernel": "k_csr_edge", "bound": "hbm", "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                    "traffic": traffic, "alg_bytes_per_launch": bytes_per_launch,
-                    "bytes": "4 (deg u + deg v) per tested edge",
-                    "avg_launch_ms": round(edge_avg_ms, 5), "launches_per_step": edge_launches / psteps,
-                    "traffic_GBps": None if traffic is None else round(traffic / (edge_avg_ms / 1e3) / 1e9, 1),
-                    "model_note": CSR_MODEL_NOTE}
-    elif mfma:
-        # int8 MFMA counts: every pair of two classes against every third
-        # class, 2 ops per multiply-accumulate, over the first (full) pass;
-        # later passes recount only tiles with a touched block
-        _, _, m_check = edge_work(w)
-        sizes = np.asarray(w["sizes"], np.float64)
-        n_all = sizes.sum()
-        full = 0.0
-        for a in range(len(sizes)):
-            for b in range(a + 1, len(sizes)):
-                full += 2.0 * sizes[a] * sizes[b] * (n_all - sizes[a] - sizes[b])
-        ops_per_launch = full * (1.0 if res["passes"] == 1 else 1.0 / launches)
-        achieved = ops_per_launch / (edge_avg_ms / 1e3) / 1e12
-        roofline = {"kernel": "k_mfma_count + k_edge epilogue", "bound": "mfma", "achieved": round(achieved, 2),
-                    "peak": I8_PEAK_TOPS, "unit": "TFLOP/s", "frac": round(achieved / I8_PEAK_TOPS, 4),
-                    "traffic": None, "ops": "int8 MFMA ops (2 per multiply-accumulate) of the full-pass count",
-                    "alg_ops_per_launch": ops_per_launch, "avg_launch_ms": round(edge_avg_ms, 5),
-                    "launches_per_step": edge_launches / psteps}
-    else:
-        op_bytes, ops, m_check = edge_work(w)
-        # exact-worklist work over all passes: pass 1 tests every edge; later
-        # passes fewer (scaled by the tested-edge ratio)
-        ops_per_launch = ops * scale / launches
-        bytes_per_launch = op_bytes * scale / launches
-        achieved = ops_per_launch / (edge_avg_ms / 1e3) / 1e12
-        stream_gbps = bytes_per_launch / (edge_avg_ms / 1e3) / 1e9
-        roofline = {
-            "kernel": "k_edge",
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "TFLOP/s",
-            "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": traffic,
-            "ops": "32-bit integer VALU ops (AND, OR) of the full-segment edge test",
-            "alg_ops_per_launch": ops_per_launch,
-            "avg_launch_ms": round(edge_avg_ms, 5),
-            "launches_per_step": edge_launches / psteps,
-            "operand_stream_GBps": round(stream_gbps, 1),
-            "operand_stream_frac_of_hbm": round(stream_gbps / HBM_PEAK_GBPS, 3),
-            "valu_issue_frac": profile_value(args.workload, "valu_issue_frac"),
-            "model_note": ALU_MODEL_NOTE,
-        }
-
-    cpu = None
-    check = None
-    if not args.no_cpu_baseline and args.workload == "c3a":
-        # the whole graph would keep the oracle busy for minutes: time it on a
-        # smaller instance of the same recipe instead (k=20, p=0.3)
-        from paper_2212_00574_amd import inputs
-        gs = inputs.make_graph([200] * 20, 0.3, seed=args.seed, gid=1, shuffle=False)
-        rows_s, col_s, _ = gs.bitset()
-        sample = dict(fmt="bitset", rows=rows_s, colour=col_s, k=20)
-        ores, _, secs, load_s = cpu_baseline(sample)
-        cpu = {"value": ores["edge_tests"] / secs, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
-               "sample": "a smaller instance of the recipe (k=20 x 200, p=0.3), one oracle fixpoint "
-                         "(%d edge tests, %.1f s; ingest %.1f s excluded)" % (ores["edge_tests"], secs, load_s)}
-    elif not args.no_cpu_baseline:
-        ores, (ovm, oem), secs, load_s = cpu_baseline(w)
-        cpu = {"value": ores["edge_tests"] / secs, "unit": "edge tests/s", "cores": 1, "kind": "oracle",
-               "sample": "the whole %s graph, one oracle fixpoint (%d edge tests, %.1f s; ingest %.1f s excluded)"
-                         % (args.workload, ores["edge_tests"], secs, load_s)}
-        gvm = vmask.cpu().numpy()
-        gem = emask.cpu().numpy()
-        if w["fmt"] == "bitset":
-            gem = gem.view(np.uint64)
-        check = bool(np.array_equal(gvm, ovm) and np.array_equal(gem, oem)
-                     and ores["rounds"] == res["rounds"] and ores["edge_tests"] == res["edge_tests"])
-
-    out = {
-        "metric": "edge tests/s to fixpoint",
-        "value": value,
-        "unit": "edge tests/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "n": int(n), "k": int(k),
-                   "edge_path": args.edge_path,
-                   "edges": int(res["input_edges"]), "rounds": res["rounds"], "passes": passes,
-                   "surviving_vertices": res["surviving_vertices"], "surviving_edges": res["surviving_edges"],
-                   "seed": args.seed, "parallelism": "single GPU"},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "kernel_ms_per_step": {name: round(t[0] / psteps, 5) for name, t in times.items()},
-        "step_ms_median": round(per_step[len(per_step) // 2], 5),
-        "step_ms_min": round(per_step[0], 5),
-        "input_edges_per_s": res["input_edges"] / (ms_per_step / 1e3),
-        "h2d": {"bytes": h2d_bytes, "ms": round(h2d_ms, 4),
-                "what": "the input's copy from pinned host memory, outside the timed steps"},
-        "oracle_equal": check,
-    }
-    assert m_check == res["input_edges"], (m_check, res["input_edges"])
+        out = run_single(args, w, cpu_proc)
+        if args.workload == "headline":
+            out["batch"] = run_batch(args)
+            out["serve"] = run_serve(args)
+    out.setdefault("n_gpus", 1)
     print(json.dumps(out), flush=True)
 
 

@@ -28,6 +28,11 @@ something other than itself):
   seeded graphs of every shape the tests use, and by the same closed forms:
   Figure 8's hand-derived fixpoint, the k=3 kernel = union of triangles,
   complete multipartite graphs and the index-inequality family.
+* ``witness_words`` (a measurement, not a result: the words a first-witness
+  search reads over every (edge, third class) pair of the input) -- pinned
+  by a pure-Python count on small graphs and by closed forms (complete
+  multipartite graphs: one word per pair; a class emptied of common
+  neighbours: its whole segment, counted as a pair without a witness).
 * ``OracleGraph.failing`` -- vertex output pinned by Figure 8's round-1
   survivors (hand derivation); edge output pinned by the Figure 8 edges whose
   printed or derived index is below k-2 (all report 1), by complete
@@ -82,6 +87,8 @@ def _load():
     lib.kzo_failing.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
     lib.kzo_fixpoint_rows.restype = C.c_int
     lib.kzo_fixpoint_rows.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp]
+    lib.kzo_witness_words.restype = i64
+    lib.kzo_witness_words.argtypes = [i32, i32, vp, vp, i32, C.POINTER(i64), C.POINTER(i64)]
     _lib = lib
     return lib
 
@@ -240,3 +247,15 @@ def fixpoint_rows(rows, colour, k) -> dict:
         return dict(status=int(st))
     return dict(status=0, rounds=int(stats[0]), equals_input=int(stats[1]), surv_vertices=int(stats[2]),
                 surv_edges=int(stats[3]), edge_tests=int(stats[4]), vmask=vmask, emask=emask)
+
+
+def witness_words(rows, colour, k) -> dict:
+    """{"words", "pairs", "no_witness"}: over every edge u < v of a valid
+    bit-row input and every class other than the endpoints', the words read
+    in order up to the first common neighbour (whole segment if none)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    colour = np.ascontiguousarray(colour, dtype=np.int32)
+    pairs, nowit = C.c_int64(0), C.c_int64(0)
+    w = _load().kzo_witness_words(int(colour.size), int(k), _ptr(colour), _ptr(rows), int(rows.shape[1]),
+                                  C.byref(pairs), C.byref(nowit))
+    return {"words": int(w), "pairs": int(pairs.value), "no_witness": int(nowit.value)}

@@ -820,3 +820,51 @@ int kzo_fixpoint_rows(int32_t n, int32_t k, const int32_t *col, const uint64_t *
   free(first); free(seg); free(wcls); free(Fe); free(fv); free(touched);
   return ST_OK;
 }
+
+/* ------------------------------------------------- witness-search work */
+
+/* Measurement, not a result: over every edge {u,v} (u < v) of the input and
+ * every class c other than the endpoints' classes, the number of words of
+ * the two class-c segments that a search in word order reads up to and
+ * including the first word holding a common neighbour (the whole segment
+ * when there is none).  This is the least work of a test that stops at the
+ * first witness of each class (section 4.2's edge index only needs to know
+ * whether each class holds a common neighbour).  Input: the BITSET format,
+ * assumed valid (validate it with kzo_fixpoint_rows or kzo_load first).
+ * *pairs receives the number of (edge, class) pairs, *nowit those without a
+ * common neighbour. */
+int64_t kzo_witness_words(int32_t n, int32_t k, const int32_t *col, const uint64_t *rows, int32_t row_words,
+                          int64_t *pairs, int64_t *nowit) {
+  int64_t *first = (int64_t *)calloc((size_t)k + 1, sizeof(int64_t));
+  int64_t *seg = (int64_t *)calloc((size_t)k + 1, sizeof(int64_t));
+  if (!first || !seg) { free(first); free(seg); return -1; }
+  for (int32_t v = 0; v < n; ++v) first[col[v] + 1] += 1;
+  for (int32_t c = 0; c < k; ++c) {
+    seg[c + 1] = seg[c] + (first[c + 1] + 63) / 64;
+    first[c + 1] += first[c];
+  }
+  const int64_t R = row_words;
+  int64_t words = 0, np = 0, nw = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    const uint64_t *ru = rows + (int64_t)u * R;
+    for (int32_t cv = 0; cv < k; ++cv) {
+      for (int64_t j = 0; j < first[cv + 1] - first[cv]; ++j) {
+        int64_t v = first[cv] + j;
+        if (v <= u || !((ru[seg[cv] + j / 64] >> (j % 64)) & 1ull)) continue;
+        const uint64_t *rv = rows + v * R;
+        for (int32_t c = 0; c < k; ++c) {
+          if (c == col[u] || c == cv) continue;
+          int64_t w = seg[c];
+          while (w < seg[c + 1] && !(ru[w] & rv[w])) ++w;
+          if (w < seg[c + 1]) words += w - seg[c] + 1;
+          else { words += seg[c + 1] - seg[c]; ++nw; }
+          ++np;
+        }
+      }
+    }
+  }
+  free(first); free(seg);
+  *pairs = np;
+  *nowit = nw;
+  return words;
+}

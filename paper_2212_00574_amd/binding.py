@@ -447,6 +447,29 @@ class Batch:
         self.emask = torch.empty_like(self.rows)
         self.results = torch.zeros(max(G, 1) * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
 
+    @classmethod
+    def allocate(cls, shapes, device):
+        """A batch whose arenas are allocated but not filled: ``shapes`` is a
+        list of (n, row_words, k); the caller writes each graph's rows and
+        colours at its descriptor's offsets (for example with kz_gen_bitset)."""
+        self = cls.__new__(cls)
+        self.device = torch.device(device)
+        G = len(shapes)
+        desc = np.zeros(G, BATCH_GRAPH_DTYPE)
+        ro, vo = 0, 0
+        for i, (n, R, k) in enumerate(shapes):
+            desc[i] = (n, k, R, 0, ro, vo)
+            ro = _line_up(ro + n * R, LINE_WORDS)
+            vo = _line_up(vo + n, LINE_VERTICES)
+        self.G, self.desc = G, desc
+        self.rows = torch.zeros(max(ro, 1), dtype=torch.int64, device=self.device)
+        self.colour = torch.zeros(max(vo, 1), dtype=torch.int32, device=self.device)
+        self.desc_dev = torch.from_numpy(desc.view(np.uint8)).to(self.device)
+        self.vmask = torch.empty(max(vo, 1), dtype=torch.uint8, device=self.device)
+        self.emask = torch.empty_like(self.rows)
+        self.results = torch.zeros(max(G, 1) * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        return self
+
     def args(self):
         return (self.desc, self.desc_dev.data_ptr(), self.G, self.rows.data_ptr(), self.colour.data_ptr())
 

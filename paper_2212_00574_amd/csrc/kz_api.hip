@@ -157,7 +157,8 @@ kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k, bool mfma) {
   z.off_packed = take(dense ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
   z.off_spare = take(sizeof(uint64_t) * (size_t)n * (size_t)Rmax);
   z.off_fb = take(mfma ? sizeof(uint64_t) * (size_t)n * (size_t)Rmax : 0);
-  z.off_F = take(2 * sizeof(uint64_t) * (size_t)n * (size_t)k);
+  z.off_F = take(sizeof(uint64_t) * (size_t)n * (size_t)kzi::f_stride(k));
+  z.off_S = take(sizeof(uint64_t) * (size_t)n * (size_t)kzi::f_stride(k));
   z.total = o;
   return z;
 }
@@ -651,11 +652,13 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   p.packed = (uint64_t *)(base + z.off_packed);
   p.spare = (uint64_t *)(base + z.off_spare);
   p.F = (uint64_t *)(base + z.off_F);
+  p.S = (uint64_t *)(base + z.off_S);
   p.fb = (uint64_t *)(base + z.off_fb);
   p.n = n;
   p.k = k;
   p.Rmax = z.Rmax;
   p.nchunks = z.nchunks;
+  p.kF = kzi::f_stride(k);
   p.Tmax = z.Tmax;
 
   // Pass 1 reads the input rows (bitset: the caller's; dense: packed here)

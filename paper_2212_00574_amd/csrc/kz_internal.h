@@ -13,7 +13,8 @@ namespace kzi {
 
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlk = 64;           // slots per block == bits per word
-constexpr int kEdgeThreads = 256;  // 4 waves per edge tile
+constexpr int kEdgeThreads = 256;  // edge pass: 4 waves per workgroup
+constexpr long long kEdgeWaveTiles = 16384;  // tiles from which the edge pass gives a tile one wave, not four
 constexpr int kMfThreads = 256;    // MFMA count path: 4 waves per 128x128 group tile
 constexpr int kMfMaxWords = 2048;  // MFMA count path: row words it supports
 constexpr int kRankChunk = 256;    // vertices per stable-partition chunk
@@ -89,22 +90,35 @@ struct Plan {
   int2 *tiles;       // [Tmax] changed tiles of the current pass
   uint64_t *packed;  // [n*Rmax] dense input packed into bit rows (dense only)
   uint64_t *spare;   // [n*Rmax] second state buffer
-  uint64_t *F;       // [2*k*n] (F[2*(c*n+slot)], F[2*(c*n+slot)+1]): first two words of
-                     // the slot's class-c segment (0 where the segment is shorter)
+  uint64_t *F;       // [n*kF] F[slot*kF + c]: the first word of the slot's class-c segment
+                     // (0 for an empty class); all-ones for the slot's own class and
+                     // for c >= k (so those classes never fail a first-word test)
+  uint64_t *S;       // [n*kF] S[slot*kF + c]: the second word of the slot's class-c segment
+                     // (0 where the segment is shorter)
   uint64_t *fb;      // [n*Rmax] MFMA count path: fail bits of the pairs of a pass
   int32_t *src;      // [nnz] csr: row of every entry
   uint8_t *efail;    // [nnz] csr: entry failed the edge test this pass
   uint64_t *pm;      // [n*(KW+1)] csr: per vertex the KW words of classes holding an alive
                      // neighbour, then its colour (one record, one gather per endpoint)
   int n, k, Rmax, nchunks;
+  int kF;            // row stride of F: k rounded up to the edge pass's class chunk
   long long Tmax;    // Rmax*(Rmax-1)/2
 };
+
+// Classes per chunk of the bit-row edge test (the rows' first words of a
+// chunk are held in 2*KC registers), and the row stride of F that makes
+// every chunk's load of a row in bounds.
+__host__ __device__ inline int edge_chunk(int k) { return k <= 4 ? 4 : k <= 32 ? (k + 3) / 4 * 4 : 32; }
+__host__ __device__ inline int f_stride(int k) {
+  const int c = edge_chunk(k);
+  return (k + c - 1) / c * c;
+}
 
 struct WsSizes {
   size_t total;
   size_t off_counts, off_coff, off_soff, off_bcls, off_bstart, off_blen, off_hist, off_perm,
       off_inv, off_scls, off_valive, off_touched0, off_touched1, off_bt0, off_bt1, off_tiles,
-      off_packed, off_spare, off_F, off_fb, off_src, off_efail, off_pm;
+      off_packed, off_spare, off_F, off_S, off_fb, off_src, off_efail, off_pm;
   int Rmax, nchunks;
   long long Tmax;
 };

@@ -315,8 +315,8 @@ __global__ void __launch_bounds__(256) k_pack_dense(Plan p, const uint8_t *adj, 
 // (lane v = slot 64*block + v) and its 4 waves split the classes (wave w
 // walks c = w, w+4, ...); only alive vertices touched by the previous round
 // are tested.  For each tested row it also refreshes the first-word matrix
-// F[c][v] (the first two words of row v's class-c segment), which the edge
-// pass stages from.  Also resets the bookkeeping the edge pass of this pass
+// F[v*k + c] (the first word of row v's class-c segment), which the edge
+// pass tests first.  Also resets the bookkeeping the edge pass of this pass
 // fills.
 __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const uint64_t *__restrict__ src,
                                                 int pass) {
@@ -367,8 +367,10 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
         if (c >= k) break;
         const int w0 = lds_off ? sOff[c] : p.soff[c];
         const int w1 = lds_off ? sOff[c + 1] : p.soff[c + 1];
-        ulonglong2 *Fcv = (ulonglong2 *)p.F + ((long long)c * n + v);
-        if (active) *Fcv = make_ulonglong2(x0[g], x1[g]);
+        if (active) {
+          p.F[(long long)v * p.kF + c] = c == cv ? ~0ull : x0[g];
+          p.S[(long long)v * p.kF + c] = x1[g];
+        }
         if (c == cv) continue;
         // an empty class has no words: no neighbour possible
         bool nz = (x0[g] | x1[g]) != 0;
@@ -402,8 +404,8 @@ __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const u
 // fails when a class other than its own has no bit, or when some class is
 // empty.  Words of the row's own class must be zero (a nonzero one is
 // classified: self-loop, edge inside a class, or asymmetry), and so must
-// padding bits past a class's size.  The first two words of every segment
-// fill the first-word matrix F.  All loads of a piece are independent of
+// padding bits past a class's size.  The first word of every segment fills
+// the first-word matrix F.  All loads of a piece are independent of
 // each other, so one memory round serves the copy, the test and F.  Rh > 0:
 // the caller's row width (bit-row input; a layout whose classes do not add up
 // to it is flagged by the setup pass and nothing is written); 0: the setup
@@ -485,8 +487,8 @@ __global__ void __launch_bounds__(256) k_vertex_first(Plan p, const int *scls, c
   auto empty_class = [&](int c) {
     sEmpty = 1;
     for (int r = 0; r < nrows; ++r) {
-      p.F[2 * ((long long)c * n + v0 + r)] = 0ull;
-      p.F[2 * ((long long)c * n + v0 + r) + 1] = 0ull;
+      p.F[(long long)(v0 + r) * p.kF + c] = 0ull;
+      p.S[(long long)(v0 + r) * p.kF + c] = 0ull;
     }
   };
   if (lds_off) {
@@ -495,6 +497,11 @@ __global__ void __launch_bounds__(256) k_vertex_first(Plan p, const int *scls, c
   } else {
     for (int c = tid; c < k; c += 256)
       if (p.soff[c] == p.soff[c + 1]) empty_class(c);
+  }
+  // F's padding classes (k up to its row stride) pass every first-word test
+  {
+    const int pad = p.kF - k;
+    for (int i = tid; i < nrows * pad; i += 256) p.F[(long long)(v0 + i / pad) * p.kF + k + i % pad] = ~0ull;
   }
   __syncthreads();
   const bool any_empty = sEmpty != 0;
@@ -531,8 +538,9 @@ __global__ void __launch_bounds__(256) k_vertex_first(Plan p, const int *scls, c
       const int cvr = __builtin_amdgcn_readlane(sc, r);
       if (valid) {
         dst[(long long)v * R + w] = xi;
-        if (off < 2) p.F[2 * ((long long)cw * n + v) + off] = xi;
-        if (off == 0 && ends) p.F[2 * ((long long)cw * n + v) + 1] = 0ull;
+        if (off == 0) p.F[(long long)v * p.kF + cw] = cw == cvr ? ~0ull : xi;
+        if (off == 1) p.S[(long long)v * p.kF + cw] = xi;
+        if (off == 0 && ends) p.S[(long long)v * p.kF + cw] = 0ull;
         if (bl < 64 && (xi >> bl)) pr = max(pr, (int)P_EINVAL);
       }
       const unsigned long long nz = __ballot(valid && xi != 0);
@@ -583,238 +591,235 @@ __global__ void __launch_bounds__(256) k_vertex_first(Plan p, const int *scls, c
   if (lane == 0 && nf) atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 0), (unsigned long long)nf);
 }
 
-// The i-th class other than cx and cy (cx < cy): the third classes of a tile.
-__device__ __forceinline__ int third_class(int i, int cx, int cy) {
-  int c = i;
-  if (c >= cx) ++c;
-  if (c >= cy) ++c;
-  return c;
+// Reads lane l's 64-bit value into scalar registers.
+__device__ __forceinline__ unsigned long long lane64(unsigned long long x, int l) {
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, l);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
-// Edge test for every edge of one inter-class block pair (X, Y), X < Y.
-//
-// Lane v of each wave stands for slot bstart[Y]+v; wave w handles 16 rows u
-// of block X.  P(u) is the 64-bit set of v with {u,v} still passing.  The
-// tile walks its third classes (every class but class(X) and class(Y)) in
-// chunks of CH, staged from the first-word matrix: the first two words of
-// every row's class-c segment, row u's in LDS (read as broadcasts), row v's
-// in the lane's registers.  Level 1: the first words of u and v are ANDed
-// and a wave ballot gives the lanes with a common neighbour there; the
-// ballots of the chunk are ANDed.  Level 2, when some edge of u is not
-// covered: the same with the first two words.  Level 3 (rare): class by
-// class, the lanes still missing a witness scan the rest of the segment in
-// memory.  Padding slots of the last chunk hold all-ones words, so they never
-// drop a lane.  Wave 0 then turns the rows P(u) into the new word X of every
-// row v with a lane butterfly transpose (and, in pass 1, checks the input's
-// symmetry the same way).  When a bit of the tile changed, both copies of
-// its new bits go to `dst` (pass 1: the output state, which already holds a
-// copy of the input; later passes: scratch, and the tile is listed for the
-// apply pass).  MF: the witness search is replaced by the fail bits `fb` of
-// the MFMA count path (k_mfma_count), so both paths share this tile
-// epilogue.  Six-class chunks keep the kernel within 80 registers, so six
-// waves fit on a SIMD; eight-class chunks are held to five (96 registers),
-// which lets every tile of a 50-block row width be resident at once.
-template <bool FIRST, int CH, bool MF>
-__global__ void __launch_bounds__(kEdgeThreads, CH == 6 ? 6 : 5) k_edge(Plan p, const uint64_t *__restrict__ src,
-                                                       uint64_t *__restrict__ dst, int pass,
-                                                       const uint64_t *__restrict__ fb) {
-  Hdr *h = p.hdr;
-  const int k = p.k;
-  const int cur = pass & 1, nxt = cur ^ 1;
-  int X, Y;
-  tri_decode(xcd_remap(blockIdx.x, gridDim.x), p.Rmax, X, Y);
+// x with lane l's value replaced by the uniform value y.
+__device__ __forceinline__ unsigned long long set_lane64(unsigned long long x, unsigned long long y, int l,
+                                                         int lane) {
+  return lane == l ? y : x;
+}
+
+constexpr int kTileWaves = kEdgeThreads / kWave;  // waves per workgroup of the edge pass
+
+// What a wave knows about its tile (X, Y): blocks of two different classes,
+// lane l standing for row u = xs + l and for row v = ys + l.  A workgroup
+// takes kTileWaves / TW tiles, TW waves each.
+struct Tile {
+  int X, Y, xs, xl, ys, yl, cx, cy;
+  unsigned long long E;   // lane u: row u's word Y (its edges into block Y)
+  unsigned long long ET;  // lane v: row v's word X
+  unsigned long long TU, TV;  // rows of X / Y touched by the previous round (all in pass 1)
+};
+
+// Decodes this wave's tile and loads its words; false when the wave has no
+// inter-class tile to test in this pass (the same answer for the TW waves of
+// a tile).
+template <bool FIRST, int TW>
+__device__ __forceinline__ bool tile_begin(const Plan &p, const uint64_t *__restrict__ src, int cur, int lane,
+                                           Tile &T) {
+  const Hdr *h = p.hdr;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long t = xcd_remap(blockIdx.x, gridDim.x) * (kTileWaves / TW) + wid / TW;
+  if (t >= p.Tmax) return false;
+  tri_decode(t, p.Rmax, T.X, T.Y);
   // one round of independent loads (X, Y < Rmax: the block table is in
   // bounds even where this call's layout is shorter or invalid)
   const int bad = h->bad_colour | h->bad_layout, R = h->R;
-  const int cx = p.bcls[X], cy = p.bcls[Y];
-  const int xs = p.bstart[X], xl = p.blen[X];
-  const int ys = p.bstart[Y], yl = p.blen[Y];
-  const bool btouch = FIRST || (p.btouched[cur][X] | p.btouched[cur][Y]);
-  if (bad || Y >= R || cx == cy || !btouch) return;
-
-  constexpr int kWaves = kEdgeThreads / kWave;
-  constexpr int kRowsPerWave = kBlk / kWaves;
-  constexpr int kStage = (CH * kBlk + kEdgeThreads - 1) / kEdgeThreads;
-  __shared__ ulonglong2 sU[CH][kBlk];
-  __shared__ unsigned long long sV2[CH][kBlk];
-  __shared__ unsigned long long sE[kBlk], sP[kBlk];
-
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const unsigned long long ymask = yl == 64 ? ~0ull : ((1ull << yl) - 1);
-  const unsigned long long xmask = xl == 64 ? ~0ull : ((1ull << xl) - 1);
-  const int nthird = MF ? 0 : k - 2;
-  const int n = p.n;
-  const ulonglong2 *F = (const ulonglong2 *)p.F;
-  const int ur = tid & 63;                      // staging row of this thread
-  const int urc = ur < xl ? ur : xl - 1;        // clamped into the block
-  const int vrc = lane < yl ? lane : yl - 1;
-  const uint64_t *rowv = src + (long long)(ys + vrc) * R;
-
-  // Staging of one chunk of CH third classes from the first-word matrix:
-  // `issue` loads (the third classes follow from cx and cy alone, so these
-  // loads go out together with the tile's own), `stage` writes row u's two
-  // first words to LDS (read as broadcasts) and keeps row v's first word in
-  // the lane's registers.  Padding slots of the last chunk hold all-ones.
-  // Row v's second words go to LDS too, class j by wave j % kWaves.
-  constexpr int kV2 = (CH + kWaves - 1) / kWaves;
-  ulonglong2 uu[kStage];
-  unsigned long long vv[CH], vy[kV2];
-  auto issue = [&](int q) {
-#pragma unroll
-    for (int e2 = 0; e2 < kStage; ++e2) {
-      const int e = tid + e2 * kEdgeThreads;
-      const int i = q + (e < CH * kBlk ? e >> 6 : 0);
-      const int c = i < nthird ? third_class(i, cx, cy) : 0;
-      uu[e2] = F[(long long)c * n + xs + urc];
-    }
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const int c = q + j < nthird ? third_class(q + j, cx, cy) : 0;
-      vv[j] = F[(long long)c * n + ys + vrc].x;
-    }
-#pragma unroll
-    for (int jj = 0; jj < kV2; ++jj) {
-      const int j = wid + jj * kWaves;
-      const int c = j < CH && q + j < nthird ? third_class(q + j, cx, cy) : 0;
-      vy[jj] = F[(long long)c * n + ys + vrc].y;
-    }
-  };
-  auto stage = [&](int q) {
-#pragma unroll
-    for (int e2 = 0; e2 < kStage; ++e2) {
-      const int e = tid + e2 * kEdgeThreads;
-      if (e < CH * kBlk) {
-        const int j = e >> 6;
-        sU[j][ur] = q + j < nthird ? uu[e2] : make_ulonglong2(~0ull, ~0ull);
-      }
-    }
-#pragma unroll
-    for (int jj = 0; jj < kV2; ++jj) {
-      const int j = wid + jj * kWaves;
-      if (j < CH) sV2[j][lane] = q + j < nthird ? (lane < yl ? vy[jj] : 0ull) : ~0ull;
-    }
-#pragma unroll
-    for (int j = 0; j < CH; ++j) vv[j] = q + j < nthird ? (lane < yl ? vv[j] : 0ull) : ~0ull;
-  };
-
-  // row index clamped into the block so the load is always in bounds
-  const unsigned long long e0 = tid < kBlk ? src[(long long)(xs + urc) * R + Y] : 0ull;
-  if (nthird > 0) issue(0);
-  const unsigned long long ET = lane < yl ? rowv[X] : 0ull;  // used by the transpose
+  T.cx = p.bcls[T.X];
+  T.cy = p.bcls[T.Y];
+  T.xs = p.bstart[T.X];
+  T.xl = p.blen[T.X];
+  T.ys = p.bstart[T.Y];
+  T.yl = p.blen[T.Y];
+  const bool btouch = FIRST || (p.btouched[cur][T.X] | p.btouched[cur][T.Y]);
+  if (bad || T.Y >= R || T.cx == T.cy || !btouch) return false;
+  const unsigned long long ymask = T.yl == 64 ? ~0ull : ((1ull << T.yl) - 1);
+  const int urc = lane < T.xl ? lane : T.xl - 1, vrc = lane < T.yl ? lane : T.yl - 1;  // clamped rows
+  const unsigned long long e = src[(long long)(T.xs + urc) * R + T.Y];
+  const unsigned long long et = src[(long long)(T.ys + vrc) * R + T.X];
+  T.E = lane < T.xl ? e & ymask : 0ull;
+  T.ET = lane < T.yl ? et : 0ull;
   // pairs to re-test: those with a touched endpoint (all of them in pass 1);
   // the others keep their outcome, so masks and rounds equal full sweeps
-  const unsigned long long TU = FIRST ? ~0ull : __ballot(lane < xl && p.touched[cur][xs + lane]);
-  const unsigned long long TV = FIRST ? ~0ull : __ballot(lane < yl && p.touched[cur][ys + lane]);
-  if (tid < kBlk) {
-    sE[tid] = tid < xl ? e0 : 0ull;
-    sP[tid] = tid < xl ? (e0 & ymask) : 0ull;
-  }
-  if (MF) {
-    // pairs with a touched endpoint take the MFMA path's outcome; the others
-    // keep theirs (each thread updates the word it wrote itself)
-    if (tid < xl) {
-      const unsigned long long Pt = ((TU >> tid) & 1ull) ? ~0ull : TV;
-      sP[tid] &= ~(fb[(long long)(xs + tid) * R + Y] & Pt);
-    }
-  }
-  for (int q = 0; q < nthird; q += CH) {
-    if (q > 0) {
-      issue(q);
-      __syncthreads();  // every wave is done with the previous chunk
-    }
-    stage(q);
-    __syncthreads();    // also publishes sE / sP before the first chunk
-    // P of the wave's rows, lane i holding row wid*kRowsPerWave + i: one LDS
-    // read per chunk instead of one per row (a row's P changes only in its
-    // own iteration below)
-    const unsigned long long Pw = sP[wid * kRowsPerWave + (lane & (kRowsPerWave - 1))];
-    for (int ui = 0; ui < kRowsPerWave; ++ui) {
-      const int u = wid * kRowsPerWave + ui;
-      if (u >= xl) break;
-      unsigned long long P = ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(Pw >> 32), ui) << 32) |
-                             (unsigned)__builtin_amdgcn_readlane((int)Pw, ui);
-      const unsigned long long Pt = P & (((TU >> u) & 1ull) ? ~0ull : TV);
-      if (!Pt) continue;
-      unsigned long long all = ~0ull;
-      {
-        unsigned long long a[CH];
-#pragma unroll
-        for (int j = 0; j < CH; ++j) a[j] = sU[j][u].x;
-#pragma unroll
-        for (int j = 0; j < CH; ++j) all &= __ballot((a[j] & vv[j]) != 0ull);
-      }
-      if (!(Pt & ~all)) continue;
-      // level 2: the first two words (re-read from LDS; rare)
-      all = ~0ull;
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        const ulonglong2 a = sU[j][u];
-        all &= __ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
-      }
-      if (!(Pt & ~all)) continue;
-      // level 3: class by class, scanning the rest of the segment
-      const uint64_t *rowu = src + (long long)(xs + u) * R;
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        if (q + j >= nthird) break;
-        const ulonglong2 a = sU[j][u];
-        unsigned long long miss = Pt & ~__ballot(((a.x & vv[j]) | (a.y & sV2[j][lane])) != 0ull);
-        const int c = third_class(q + j, cx, cy);
-        const int w1 = p.soff[c + 1];
-        for (int w = p.soff[c] + 2; w < w1 && miss; ++w) {
-          const unsigned long long x = rowu[w];
-          const unsigned long long y = ((miss >> lane) & 1ull) ? rowv[w] : 0ull;
-          miss &= ~__ballot((x & y) != 0ull);
-        }
-        P &= ~miss;
-      }
-      if (lane == 0) sP[u] = P;
-    }
-  }
-  __syncthreads();
+  T.TU = FIRST ? ~0ull : __ballot(lane < T.xl && p.touched[cur][T.xs + lane]);
+  T.TV = FIRST ? ~0ull : __ballot(lane < T.yl && p.touched[cur][T.ys + lane]);
+  return true;
+}
 
-  if (wid != 0) return;
-
-  // wave 0: lane v gets bit v of every P(u) -- the new word X of row v --
-  // and, in pass 1, of every E(u), to check that the rows are symmetric
-  const int v = lane;
-  const unsigned long long newET = wave_transpose64(sP[lane], lane) & xmask;
+// The tile's next state from P (lane u: the pairs of row u that still pass,
+// a subset of E): wave-transposes P into the new word X of every row v (and,
+// in pass 1, E against the rows' word X to check symmetry), writes both
+// copies of the tile when a bit changed (pass 1: into the output state,
+// which already holds the input; later passes: into scratch, the tile
+// listed for the apply pass), marks touched rows and blocks, and counts the
+// removed edges and the exact-worklist tests.
+template <bool FIRST>
+__device__ __forceinline__ void tile_finish(const Plan &p, uint64_t *__restrict__ dst, const Tile &T,
+                                            unsigned long long P, int cur, int lane) {
+  Hdr *h = p.hdr;
+  const int R = h->R, nxt = cur ^ 1, slot = blockIdx.x % kCtrSlots;
+  const unsigned long long xmask = T.xl == 64 ? ~0ull : ((1ull << T.xl) - 1);
+  const unsigned long long newET = wave_transpose64(P, lane) & xmask;
   if (FIRST) {
-    const unsigned long long trE = wave_transpose64(sE[lane], lane);
-    if (v < yl && ((trE ^ ET) & xmask)) atomicMax(&h->prio, P_EASYM);
+    const unsigned long long trE = wave_transpose64(T.E, lane);
+    if (lane < T.yl && ((trE ^ T.ET) & xmask)) atomicMax(&h->prio, P_EASYM);
   }
-  const unsigned long long Eu = sE[lane] & ymask, Pu = sP[lane];
-  const bool chU = lane < xl && Eu != Pu;
-  const bool chV = v < yl && (ET & xmask) != newET;
+  const bool chU = lane < T.xl && T.E != P;
+  const bool chV = lane < T.yl && (T.ET & xmask) != newET;
   const unsigned long long bu = __ballot(chU), bv = __ballot(chV);
   if (bu | bv) {
-    if (lane < xl) dst[(long long)(xs + lane) * R + Y] = Pu;
-    if (v < yl) dst[(long long)(ys + v) * R + X] = newET;
-    if (chU) p.touched[nxt][xs + lane] = 1;
-    if (chV) p.touched[nxt][ys + v] = 1;
-    const int rem = wave_sum(lane < xl ? __popcll(Eu & ~Pu) : 0);
+    if (lane < T.xl) dst[(long long)(T.xs + lane) * R + T.Y] = P;
+    if (lane < T.yl) dst[(long long)(T.ys + lane) * R + T.X] = newET;
+    if (chU) p.touched[nxt][T.xs + lane] = 1;
+    if (chV) p.touched[nxt][T.ys + lane] = 1;
+    const int rem = wave_sum(lane < T.xl ? __popcll(T.E & ~P) : 0);
     if (lane == 0) {
-      if (bu) p.btouched[nxt][X] = 1;
-      if (bv) p.btouched[nxt][Y] = 1;
+      if (bu) p.btouched[nxt][T.X] = 1;
+      if (bv) p.btouched[nxt][T.Y] = 1;
       if (!FIRST) {
         const int pos = atomicAdd(&h->tile_count, 1);
-        p.tiles[pos] = make_int2(X, Y);
+        p.tiles[pos] = make_int2(T.X, T.Y);
       }
-      atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 1), (unsigned long long)rem);
+      atomicAdd(&h->ctr(cur, slot, 1), (unsigned long long)rem);
     }
   }
   // exact worklist size: edges of this tile with a touched endpoint
-  int cnt;
-  if (FIRST) {
-    cnt = wave_sum(lane < xl ? __popcll(Eu) : 0);
-  } else {
-    const int tU = lane < xl ? p.touched[cur][xs + lane] : 0;
-    const int tV = v < yl ? p.touched[cur][ys + v] : 0;
-    const unsigned long long TV = __ballot(tV != 0);
-    cnt = wave_sum(lane < xl ? __popcll(Eu & (tU ? ~0ull : TV)) : 0);
+  const int cnt = wave_sum(lane < T.xl ? __popcll(T.E & (((T.TU >> lane) & 1ull) ? ~0ull : T.TV)) : 0);
+  if (lane == 0 && cnt) atomicAdd(&h->ctr(cur, slot, 2), (unsigned long long)cnt);
+}
+
+// Edge test (witness search) for every edge of one inter-class block pair
+// (X, Y), X < Y.  Edge {u,v} fails when some class other than class(X) and
+// class(Y) holds no common neighbour.  The first-word matrix F (F[v*kF + c]
+// = the first word of row v's class-c segment) feeds the common case: per
+// chunk of KC classes, lane v holds its row's first words in registers; for
+// each row u, u's first words of the chunk come in as one block of scalar
+// loads (the address is uniform), and one AND, a compare and a wave ballot
+// per class give the lanes with a common neighbour there.  No class needs a
+// special case in this loop: F holds all-ones for a row's own class and for
+// the padding classes past k, and the registers of class(X) are set to
+// all-ones once per chunk, so the tile's own two classes and the padding
+// pass (class(Y) is v's own class), and an empty class holds zero words.
+// The one exception is a row u with no neighbour in the first word of
+// class(Y): its ballots for that class are empty, and the row takes the rare
+// path below like a row with a miss.  A lane that is still an edge and has
+// no witness in some third class's first word tries the second words (the
+// second-word matrix S, laid out like F and as small, so both sides come
+// from the L2), then scans the rest of the segment in the rows.  TW = 1: the
+// four waves of a workgroup test four neighbouring tiles (same X, so their
+// scalar loads share the cache), with no LDS and no barrier; TW = 4 (graphs
+// with few tiles): the workgroup's waves split one tile's rows u, 16 each,
+// so four times as many waves hide the scalar loads' latency, and wave 0
+// finishes the tile from the rows' results gathered in LDS.
+template <bool FIRST, int KC, int TW>
+__global__ void __launch_bounds__(kEdgeThreads) k_edge(Plan p, const uint64_t *__restrict__ src,
+                                                       uint64_t *__restrict__ dst, int pass,
+                                                       const uint64_t *__restrict__ F,
+                                                       const uint64_t *__restrict__ S) {
+  static_assert(TW == 1 || TW == kTileWaves, "a tile takes one wave or the whole workgroup");
+  const int lane = threadIdx.x & 63, cur = pass & 1;
+  Tile T;
+  if (!tile_begin<FIRST, TW>(p, src, cur, lane, T)) return;
+  const int k = p.k, kF = p.kF, R = p.hdr->R;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int u0 = TW == 1 ? 0 : wid * (kBlk / TW), u1 = TW == 1 ? T.xl : min(u0 + kBlk / TW, T.xl);
+  const int vrc = lane < T.yl ? lane : T.yl - 1;
+  const uint64_t *rowv = src + (long long)(T.ys + vrc) * R;
+  const uint64_t *Sv = S + (long long)(T.ys + vrc) * kF;
+  unsigned long long P = T.E;
+  for (int q = 0; q < k; q += KC) {
+    // third classes of the tile in this chunk
+    const int hi = min(q + KC, k);
+    const int nthird = hi - q - (T.cx >= q && T.cx < hi) - (T.cy >= q && T.cy < hi);
+    if (nthird <= 0) continue;
+    const uint64_t *Fv = F + (long long)(T.ys + vrc) * kF + q;
+    unsigned long long vf[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) vf[j] = q + j == T.cx ? ~0ull : Fv[j];
+    unsigned third = 0;  // chunk positions of the tile's third classes
+#pragma unroll
+    for (int j = 0; j < KC; ++j)
+      if (q + j < k && q + j != T.cx && q + j != T.cy) third |= 1u << j;
+    const uint64_t *Fu = F + (long long)(T.xs + u0) * kF + q;  // row u's first words: uniform, scalar loads
+    for (int u = u0; u < u1; ++u, Fu += kF) {
+      unsigned long long Pu = lane64(P, u);
+      const unsigned long long Pt = Pu & (((T.TU >> u) & 1ull) ? ~0ull : T.TV);
+      if (!Pt) continue;
+      unsigned long long uf[KC];
+#pragma unroll
+      for (int j = 0; j < KC; ++j) uf[j] = Fu[j];
+      // lanes with a witness in every class of each quarter of the chunk
+      constexpr int KQ = KC / 4;
+      unsigned long long all[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+#pragma unroll
+      for (int j = 0; j < KC; ++j) all[j / KQ] &= __ballot((uf[j] & vf[j]) != 0ull);
+      if (!(Pt & ~(all[0] & all[1] & all[2] & all[3]))) continue;
+      // some edge of u lacks a witness in a first word: in each quarter with
+      // a miss, third class by third class (u's word reloaded, so the hot
+      // loop's scalar registers need not live on into this path), the
+      // second words (S sits in the L2), then the rest of the segment in the
+      // rows; every load is made only by the lanes still missing a witness
+      const uint64_t *Su = S + (long long)(T.xs + u) * kF;
+      const uint64_t *rowu = src + (long long)(T.xs + u) * R;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if (!(Pt & ~all[g])) continue;
+#pragma unroll
+        for (int jj = 0; jj < KQ; ++jj) {
+          const int j = g * KQ + jj;
+          const unsigned long long ufj = __builtin_nontemporal_load(Fu + j);
+          unsigned long long m = Pt & ~__ballot((ufj & vf[j]) != 0ull);
+          if (!m || !((third >> j) & 1u)) continue;
+          const int c = q + j;
+          const bool mine = (m >> lane) & 1ull;
+          const unsigned long long x2 = mine ? Su[c] : 0ull, y2 = mine ? Sv[c] : 0ull;
+          m &= ~__ballot((x2 & y2) != 0ull);
+          if (!m) continue;
+          const int w1 = p.soff[c + 1];
+          for (int w = p.soff[c] + 2; w < w1 && m; ++w) {
+            const bool still = (m >> lane) & 1ull;
+            const unsigned long long x = still ? rowu[w] : 0ull, y = still ? rowv[w] : 0ull;
+            m &= ~__ballot((x & y) != 0ull);
+          }
+          Pu &= ~m;
+        }
+      }
+      P = set_lane64(P, Pu, u, lane);
+    }
   }
-  if (lane == 0 && cnt) atomicAdd(&h->ctr(cur, blockIdx.x % kCtrSlots, 2), (unsigned long long)cnt);
+  if (TW > 1) {
+    // gather the rows' results (lane u of the wave that owns row u)
+    __shared__ unsigned long long sP[kBlk];
+    if (lane >= u0 && lane < u0 + kBlk / TW) sP[lane] = P;
+    __syncthreads();
+    if (wid != 0) return;
+    P = sP[lane];
+  }
+  tile_finish<FIRST>(p, dst, T, P, cur, lane);
+}
+
+// The MFMA count path's tile epilogue: the pairs with a touched endpoint
+// take the fail bits `fb` that k_mfma_count computed (same layout as the
+// rows); the others keep their outcome.
+template <bool FIRST>
+__global__ void __launch_bounds__(kEdgeThreads) k_edge_mf(Plan p, const uint64_t *__restrict__ src,
+                                                          uint64_t *__restrict__ dst, int pass,
+                                                          const uint64_t *__restrict__ fb) {
+  const int lane = threadIdx.x & 63, cur = pass & 1;
+  Tile T;
+  if (!tile_begin<FIRST, 1>(p, src, cur, lane, T)) return;
+  const int R = p.hdr->R;
+  unsigned long long P = T.E;
+  if (lane < T.xl) {
+    const unsigned long long Pt = ((T.TU >> lane) & 1ull) ? ~0ull : T.TV;
+    P &= ~(fb[(long long)(T.xs + lane) * R + T.Y] & Pt);
+  }
+  tile_finish<FIRST>(p, dst, T, P, cur, lane);
 }
 
 // ---------------------------------------------------------------- MFMA count path
@@ -1057,34 +1062,49 @@ void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uin
 
 void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first, hipStream_t s) {
   if (p.Tmax <= 0) return;
-  const dim3 grid((unsigned)p.Tmax);
-  // chunk of third classes: whichever of 6 and 8 pads the k-2 classes least
-  const int nthird = p.k > 2 ? p.k - 2 : 0;
-  const bool six = (nthird + 5) / 6 * 6 < (nthird + 7) / 8 * 8;
-  const uint64_t *nofb = nullptr;
-#define KZ_EDGE(F, C) hipLaunchKernelGGL((k_edge<F, C, false>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, nofb)
-  if (first) {
-    if (six) KZ_EDGE(true, 6);
-    else KZ_EDGE(true, 8);
-  } else {
-    if (six) KZ_EDGE(false, 6);
-    else KZ_EDGE(false, 8);
+  const uint64_t *F = p.F, *S = p.S;
+  // a wave per tile when there are tiles enough to fill the chip many times
+  // over, else a workgroup per tile
+  const bool wide = p.Tmax < kEdgeWaveTiles;
+  const dim3 grid((unsigned)(wide ? p.Tmax : (p.Tmax + kTileWaves - 1) / kTileWaves));
+  // classes per chunk: edge_chunk(k), which F's row stride is a multiple of
+#define KZ_EDGE(FI, KC)                                                                                       \
+  do {                                                                                                        \
+    if (wide)                                                                                                 \
+      hipLaunchKernelGGL((k_edge<FI, KC, kTileWaves>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, F, S); \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_edge<FI, KC, 1>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, F, S);       \
+  } while (0)
+#define KZ_EDGE_K(FI)                \
+  switch (edge_chunk(p.k)) {         \
+    case 4: KZ_EDGE(FI, 4); break;   \
+    case 8: KZ_EDGE(FI, 8); break;   \
+    case 12: KZ_EDGE(FI, 12); break; \
+    case 16: KZ_EDGE(FI, 16); break; \
+    case 20: KZ_EDGE(FI, 20); break; \
+    case 24: KZ_EDGE(FI, 24); break; \
+    case 28: KZ_EDGE(FI, 28); break; \
+    default: KZ_EDGE(FI, 32); break; \
   }
+  if (first) {
+    KZ_EDGE_K(true)
+  } else {
+    KZ_EDGE_K(false)
+  }
+#undef KZ_EDGE_K
 #undef KZ_EDGE
 }
 
 void launch_edge_pass_mfma(const Plan &p, const uint64_t *src, uint64_t *dst, uint64_t *fb, int pass, bool first,
                            hipStream_t s) {
   if (p.Tmax <= 0) return;
-  const dim3 grid((unsigned)p.Tmax);
+  const dim3 grid((unsigned)p.Tmax), tgrid((unsigned)((p.Tmax + kTileWaves - 1) / kTileWaves));
   if (first) {
     hipLaunchKernelGGL((k_mfma_count<true>), grid, dim3(kMfThreads), 0, s, p, src, fb, pass);
-    hipLaunchKernelGGL((k_edge<true, 8, true>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass,
-                       (const uint64_t *)fb);
+    hipLaunchKernelGGL((k_edge_mf<true>), tgrid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, (const uint64_t *)fb);
   } else {
     hipLaunchKernelGGL((k_mfma_count<false>), grid, dim3(kMfThreads), 0, s, p, src, fb, pass);
-    hipLaunchKernelGGL((k_edge<false, 8, true>), grid, dim3(kEdgeThreads), 0, s, p, src, dst, pass,
-                       (const uint64_t *)fb);
+    hipLaunchKernelGGL((k_edge_mf<false>), tgrid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, (const uint64_t *)fb);
   }
 }
 

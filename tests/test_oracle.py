@@ -580,3 +580,65 @@ def test_o3_empty_class_empties_the_graph_in_one_round(k):
     rows, col, _, _ = to_rows(adj, colour, k)
     r = same_as_o1(rows, col, k)
     assert r["rounds"] == 1 and r["surv_vertices"] == 0 and r["surv_edges"] == 0
+
+
+# ------------------------------------- witness-search work (a measurement)
+from oracle import witness_words  # noqa: E402
+
+
+def python_witness_words(rows, col, k):
+    lay = inputs.class_layout(np.bincount(col, minlength=k))
+    slot = inputs.unpack_rows(rows, lay)
+    words = pairs = nowit = 0
+    n = slot.shape[0]
+    for u in range(n):
+        for v in range(u + 1, n):
+            if not slot[u, v]:
+                continue
+            for c in range(k):
+                if c in (col[u], col[v]):
+                    continue
+                W = int(lay.words[c])
+                found = None
+                for w in range(W):
+                    lo = int(lay.offsets[c]) + 64 * w
+                    hi = min(lo + 64, int(lay.offsets[c + 1]))
+                    if np.any(slot[u, lo:hi] & slot[v, lo:hi]):
+                        found = w
+                        break
+                words += W if found is None else found + 1
+                nowit += found is None
+                pairs += 1
+    return {"words": words, "pairs": pairs, "no_witness": nowit}
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_witness_words_matches_a_python_count(seed):
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(3, 6))
+    sizes = rng.integers(1, 150, size=k)
+    g = inputs.make_graph(sizes, float(rng.uniform(0.05, 0.3)), seed=seed, gid=4, shuffle=False)
+    rows, col, lay = g.bitset()
+    assert witness_words(rows, col, k) == python_witness_words(rows, col, k)
+
+
+def test_witness_words_closed_forms():
+    # complete multipartite: every pair has a witness in the first word
+    k, s = 4, 70
+    colour = np.repeat(np.arange(k), s).astype(np.int32)
+    adj = (colour[:, None] != colour[None, :]).astype(np.uint8)
+    rows, col, _, lay = to_rows(adj, colour, k)
+    m = len(edges_of(adj))
+    assert witness_words(rows, col, k) == {"words": m * (k - 2), "pairs": m * (k - 2), "no_witness": 0}
+    # only the second word of class 3 (slots 64..69) touches classes 0..2: the
+    # pairs of an edge inside classes 0..2 with class 3 read both words
+    adj2 = adj.copy()
+    c3 = np.nonzero(colour == 3)[0]
+    adj2[np.ix_(c3[:64], np.arange(adj.shape[0]))] = 0
+    adj2[np.ix_(np.arange(adj.shape[0]), c3[:64])] = 0
+    rows, col, _, lay = to_rows(adj2, colour, k)
+    r = witness_words(rows, col, k)
+    inner = 3 * s * s                      # edges among classes 0..2
+    outer = len(edges_of(adj2)) - inner    # edges with an endpoint in class 3
+    assert r["pairs"] == inner * 2 + outer * 2
+    assert r["words"] == inner * (1 + 2) + outer * 2 and r["no_witness"] == 0
