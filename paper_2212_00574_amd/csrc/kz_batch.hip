@@ -89,6 +89,30 @@ __device__ __forceinline__ void ast(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Release and acquire at agent scope, each with its wait.  A release writes
+// this XCD's L2 back (buffer_wbl2) and must not let the atomic that
+// publishes become visible before that write-back has landed; the sequence
+// the compiler emits for a release atomic on gfx950 issues the atomic right
+// after buffer_wbl2 with no wait in between, and a workgroup on another XCD
+// can then see the published word while the words it guards (a counter
+// reset, next-state words, list entries) are still on their way.  So the
+// release is a fence followed by an explicit wait for every outstanding
+// memory operation (the write-back included), and the publishing atomic is
+// relaxed.  The acquire writes back first (the invalidate keeps dirty
+// lines, stale bytes and all, so a line must be clean when it arrives),
+// then invalidates, and waits for both before the workgroup's barrier lets
+// other waves load.
+__device__ __forceinline__ void release_agent() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+__device__ __forceinline__ void acquire_agent() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 // What a workgroup keeps in LDS about the job it works on.
 struct BatchLds {
   int coff[kBatchK + 1], soff[kBatchK + 1];
@@ -461,7 +485,8 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
     if (tid == 0) {
       const unsigned long long cw = ((unsigned long long)p << (2 * kItemBits)) |
                                     ((unsigned long long)ni << kItemBits) | (unsigned long long)S.cnt;
-      __hip_atomic_exchange(&J->claim, cw, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      release_agent();
+      __hip_atomic_exchange(&J->claim, cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&a.board[V.g & (kBatchBoard - 1)], V.g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -493,9 +518,12 @@ __device__ bool start_job(const BatchArgs &a, BatchLds &S, int g) {
   const GView V = gview(a, g);
   // layout: colours are sorted class by class; class c starts at the first
   // vertex whose colour is >= c (binary search)
+  // the layout copies in LDS are about to be overwritten: they no longer
+  // belong to the job named in S.job (a later claim must reload them)
   if (tid == 0) {
     S.bad_colour = 0;
     S.bad_layout = 0;
+    S.job = -1;
   }
   __syncthreads();
   for (int v = tid; v < n; v += NW * kWave) {
@@ -585,6 +613,11 @@ template <int NW>
 __device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
   const int tid = threadIdx.x;
   BatchJob *J = a.jobs + g;
+  // Every wave enters on S.got == 0, read after the previous barrier; thread
+  // 0 rewrites S.got below, so it waits until each wave has made that read
+  // (a late wave would otherwise see the new value, skip this function and
+  // its barriers, and stay one barrier out of step with the others).
+  __syncthreads();
   if (tid == 0) {
     unsigned long long old = __hip_atomic_load(&J->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int got = 0, cp = 0;
@@ -607,7 +640,7 @@ __device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
     S.reload = 0;
     if (got) {
       if (!(S.job == g && S.pass == cp)) {
-        __threadfence();  // acquire: the pass was listed by another workgroup
+        acquire_agent();  // the pass was listed by another workgroup
         S.reload = S.job != g ? 2 : 1;
         S.job = g;
         S.pass = cp;
@@ -692,11 +725,12 @@ __device__ bool retire(const GView &V, BatchLds &S) {
   __syncthreads();
   if (tid == 0) {
     const unsigned add = (unsigned)S.cnt;
-    const unsigned now = __hip_atomic_fetch_add(&J->done, add, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + add;
+    release_agent();
+    const unsigned now = __hip_atomic_fetch_add(&J->done, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
     S.last = (int)now == S.nitems;
     // acquire what the other workgroups wrote (and drop this CU's cached
     // copies of the job's merged state)
-    if (S.last) __threadfence();
+    if (S.last) acquire_agent();
     S.got = 0;
   }
   __syncthreads();

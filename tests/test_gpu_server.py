@@ -219,3 +219,79 @@ def test_server_large_and_generated(kz):
         assert np.array_equal(emask.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R), ref["emask"])
     check(small, res_small, "small")
     srv.close()
+
+
+def test_server_trickle_shared_passes(kz):
+    """Requests submitted one at a time, each launched at once: the graphs
+    run nearly alone on the device, so the idle workgroups of every XCD join
+    their passes (many claims, many carriers on other XCDs).  The results
+    must equal those of the same requests with every pass kept by one
+    workgroup, which a sample pins to the oracle."""
+    from paper_2212_00574_amd.binding import kz_batch_get_config, kz_batch_set_config
+    say("server: trickled requests with shared passes")
+    rng = np.random.default_rng(31)
+    specs = []
+    for i in range(600):
+        k = int(rng.integers(4, 28))
+        sizes = rng.integers(20, 90, size=k)
+        specs.append((sizes, float(rng.uniform(0.15, 0.7)), i))
+    bufs = []
+    srv = Server(kz, arena_bytes=1 << 30, max_slots=64)
+    for sizes, p, gid in specs:
+        lay = inputs.class_layout(sizes)
+        rows = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+        colour = torch.empty(lay.n, dtype=torch.int32, device=DEV)
+        kz_gen_bitset(kz.ctx, sizes, p, 31, gid, None, rows.data_ptr(), lay.R, colour.data_ptr(),
+                      srv.stream.cuda_stream)
+        bufs.append((rows, colour, len(sizes), lay))
+    cfg0 = kz_batch_get_config(kz.ctx)
+
+    def serve(share, trickle):
+        kz_batch_set_config(kz.ctx, dict(cfg0, share=share))
+        out, masks, tickets = [None] * len(bufs), [], {}
+        t0 = time.time()
+
+        def collect():   # a request holds its slot until it is polled
+            for t in list(tickets):
+                r = srv.poll(t)
+                if r is not None:
+                    out[tickets.pop(t)] = r
+
+        for i, (rows, colour, k, lay) in enumerate(bufs):
+            vm = torch.empty(lay.n, dtype=torch.uint8, device=DEV)
+            em = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+            t = srv.submit(rows, colour, k, vm, em)
+            while t is None:
+                collect()
+                assert time.time() - t0 < 120, "admission did not resume"
+                t = srv.submit(rows, colour, k, vm, em)
+            tickets[t] = i
+            masks.append((vm, em))
+            if trickle:
+                srv.progress()
+        while tickets:
+            collect()
+            assert time.time() - t0 < 120, "requests did not complete"
+        return out, [(vm.cpu().numpy(), em.cpu().numpy()) for vm, em in masks]
+
+    try:
+        ref, ref_m = serve(2, False)
+        say("  every pass solo: done")
+        for share in (0, 1):
+            got, got_m = serve(share, True)
+            say("  trickled, share mode %d: done" % share)
+            for i in range(len(bufs)):
+                for key in ("status", "rounds", "surviving_vertices", "surviving_edges", "edge_tests"):
+                    assert got[i][key] == ref[i][key], (share, i, key, got[i][key], ref[i][key])
+                assert np.array_equal(got_m[i][0], ref_m[i][0]), (share, i)
+                assert np.array_equal(got_m[i][1], ref_m[i][1]), (share, i)
+    finally:
+        kz_batch_set_config(kz.ctx, cfg0)
+    for i in range(0, len(bufs), 100):
+        rows, colour, k, lay = bufs[i]
+        o = kernelize_bitset(rows.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R), colour.cpu().numpy(), k)
+        assert ref[i]["rounds"] == o["rounds"] and ref[i]["edge_tests"] == o["edge_tests"], i
+        assert ref[i]["surviving_edges"] == o["surv_edges"], i
+        assert np.array_equal(ref_m[i][0], o["vmask"]), i
+        assert np.array_equal(ref_m[i][1].view(np.uint64).reshape(lay.n, lay.R), o["emask"]), i
+    srv.close()
