@@ -111,12 +111,12 @@ def source_hash(workload="c2"):
     return h.hexdigest()[:16]
 
 
-def profile_value(workload, key):
+def profile_value(workload, key, kernel=None):
     """A figure ("- key: value") of the committed counter summary
-    profiles/<kernel>_<workload>.md of the workload's roofline kernel; None
-    when absent or when the kernel's sources changed since the counters were
-    taken ("- source_sha: S")."""
-    kernel = PROFILED.get(workload, PROFILED["c2"])[0]
+    profiles/<kernel>_<workload>.md (default: the workload's roofline
+    kernel); None when absent or when the kernel's sources changed since the
+    counters were taken ("- source_sha: S")."""
+    kernel = kernel or PROFILED.get(workload, PROFILED["c2"])[0]
     path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
@@ -443,6 +443,21 @@ def run_single(args, name, cpu_proc=None):
                 "valu_issue_frac": profile_value(name, "valu_issue_frac"),
             }
     assert m_check == res["input_edges"], (m_check, res["input_edges"])
+    stream = None
+    if name in ("c2", "c3a") and not mfma and res["passes"] == 1:
+        # pass 1's streaming kernel: reads the rows and colours, writes the
+        # state, the first- and second-word matrices and the vertex mask
+        n_v, r_w = int(vmask.numel()), int(rows_dev.numel()) // max(int(vmask.numel()), 1)
+        chunk = 4 if k <= 4 else ((k + 3) // 4 * 4 if k <= 32 else 32)
+        kf = (k + chunk - 1) // chunk * chunk
+        vbytes = 16.0 * n_v * r_w + 16.0 * n_v * kf + 5.0 * n_v
+        v_ms = times["vertex"][0] / max(times["vertex"][1], 1)
+        v_gbps = vbytes / (v_ms / 1e3) / 1e9
+        stream = {"kernel": "k_vertex_first", "bound": "hbm", "achieved": round(v_gbps, 1), "peak": HBM_PEAK_GBPS,
+                  "unit": "GB/s", "frac": round(v_gbps / HBM_PEAK_GBPS, 4), "alg_bytes_per_launch": vbytes,
+                  "bytes": "rows read + state written (8 n R each), F and S written (8 n kF each), colours and mask",
+                  "avg_launch_ms": round(v_ms, 5),
+                  "traffic": profile_value(name, "hbm_bytes_per_launch", "k_vertex_first")}
     out = {
         "metric": "edge tests/s to fixpoint", "value": value, "unit": "edge tests/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -452,6 +467,7 @@ def run_single(args, name, cpu_proc=None):
                    "passes": res["passes"], "surviving_vertices": res["surviving_vertices"],
                    "surviving_edges": res["surviving_edges"], "seed": args.seed, "parallelism": "single GPU"},
         "roofline": roofline,
+        "stream_kernel": stream,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": {nm: round(t[0] / psteps, 5) for nm, t in times.items()},
         "step_ms_median": round(per_step[len(per_step) // 2], 5), "step_ms_min": round(per_step[0], 5),
