@@ -89,6 +89,10 @@ def _load():
     lib.kzo_fixpoint_rows.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp]
     lib.kzo_witness_words.restype = i64
     lib.kzo_witness_words.argtypes = [i32, i32, vp, vp, i32, C.POINTER(i64), C.POINTER(i64)]
+    lib.kzo_dom_vertex.restype = C.c_int
+    lib.kzo_dom_vertex.argtypes = [i32, vp, vp, vp]
+    lib.kzo_dom_edge.restype = C.c_int
+    lib.kzo_dom_edge.argtypes = [i32, vp, vp]
     _lib = lib
     return lib
 
@@ -259,3 +263,34 @@ def witness_words(rows, colour, k) -> dict:
     w = _load().kzo_witness_words(int(colour.size), int(k), _ptr(colour), _ptr(rows), int(rows.shape[1]),
                                   C.byref(pairs), C.byref(nowit))
     return {"words": int(w), "pairs": int(pairs.value), "no_witness": int(nowit.value)}
+
+
+# ---- dominance (section 4.3), kz_oracle_ext.c
+def _dense01(adj):
+    a = np.ascontiguousarray(adj, dtype=np.uint8).copy()
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    return a, n
+
+
+def dom_vertex(adj):
+    """Sweeps of Algorithm 1 (Definition 4.3.1, read as documented in
+    kz_oracle_ext.c) to a fixpoint.  Returns (adjacency after deletion,
+    alive mask, stats dict)."""
+    a, n = _dense01(adj)
+    alive = np.zeros(n, np.uint8)
+    st = np.zeros(4, np.int64)
+    _load().kzo_dom_vertex(n, _ptr(a), _ptr(alive), _ptr(st))
+    return a, alive, {"sweeps": int(st[0]), "deleted_vertices": int(st[1]), "deleted_edges": int(st[2]),
+                      "steps": int(st[3])}
+
+
+def dom_edge(adj):
+    """Sweeps of Algorithm 2 (Definition 4.3.2, read as documented in
+    kz_oracle_ext.c) to a fixpoint.  Returns (adjacency after deletion,
+    stats dict)."""
+    a, n = _dense01(adj)
+    st = np.zeros(2, np.int64)
+    _load().kzo_dom_edge(n, _ptr(a), _ptr(st))
+    return a, {"sweeps": int(st[0]), "deleted_edges": int(st[1])}
+

@@ -1,0 +1,141 @@
+/*
+ * kz_oracle_ext.c -- plain CPU oracles for the reductions and searches that
+ * sit beside colour-index pruning.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code with the GPU library.  Graphs are a
+ * dense n*n matrix of 0/1 bytes (adj[v*n+w]), symmetric, zero diagonal.
+ *
+ * Dominance (thesis section 4.3).
+ *
+ *   Definition 4.3.1: node b dominates node a when a and b are distinct and
+ *   not adjacent and N(a) is a subset of N(b).  A dominated node is deleted
+ *   with its edges.  (Non-adjacency is implied by the subset: if a and b were
+ *   adjacent, b would be in N(a) but not in N(b).)
+ *
+ *   Definition 4.3.2: for distinct a, u, b, the edge {u,b} dominates the
+ *   edge {a,u} when b is not a neighbour of a and the common neighbourhood
+ *   N(a) & N(u) is a subset of N(u) & N(b), i.e. of N(b).  The dominated edge
+ *   is deleted; a and u stay.  (The thesis writes the first condition as
+ *   "b is not in N(a) & N(b)", which holds in every simple graph; it is read
+ *   as "b is not in N(a)", the condition that lets {u,b} replace {a,u} in a
+ *   clique.)
+ *
+ *   Algorithm 1 (vertex dominance), as read here: for every node b in index
+ *   order (skipping deleted ones), for every node a in index order: if b
+ *   dominates a in the current graph, delete a at once (so later tests see
+ *   the smaller graph).  The printed listing loops over a in N(node) and
+ *   tests "N(a) & N(node)" with no comparison; both contradict Definition
+ *   4.3.1 and are read as its non-adjacency and subset test.
+ *
+ *   Algorithm 2 (edge dominance), as read here: for every node a in index
+ *   order, for every neighbour u of a in index order, for every neighbour b
+ *   of u in index order with b != a: if b is not a neighbour of a and
+ *   N(a) & N(u) is a subset of N(b) (current graph), delete the edge {a,u}
+ *   and go on with the next u.  The printed listing's condition 1 ("b in
+ *   N(a) & N(u)") contradicts Definition 4.3.2 and is read as "b not in
+ *   N(a)"; its condition 2 compares a set with itself and is read as the
+ *   definition's inclusion; it deletes "{a,b}", read as the dominated edge
+ *   {a,u}.
+ *
+ *   One run of either algorithm is a sweep; sweeps repeat until one deletes
+ *   nothing.  Each deletion keeps some maximum clique (a clique through the
+ *   deleted vertex or edge trades a for b), so the clique number never
+ *   changes; vertex dominance may delete some k-cliques, which is why it is
+ *   kept apart from the clique-preserving colour-index path.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* b dominates a in the current graph (Definition 4.3.1). */
+static int vertex_dominates(int32_t n, const uint8_t *adj, const uint8_t *alive, int32_t b, int32_t a) {
+  if (a == b || !alive[a] || !alive[b] || adj[(int64_t)a * n + b]) return 0;
+  for (int32_t x = 0; x < n; ++x)
+    if (adj[(int64_t)a * n + x] && !adj[(int64_t)b * n + x]) return 0;
+  return 1;
+}
+
+static int64_t delete_vertex(int32_t n, uint8_t *adj, uint8_t *alive, int32_t a) {
+  int64_t removed = 0;
+  alive[a] = 0;
+  for (int32_t x = 0; x < n; ++x) {
+    if (adj[(int64_t)a * n + x]) {
+      adj[(int64_t)a * n + x] = 0;
+      adj[(int64_t)x * n + a] = 0;
+      ++removed;
+    }
+  }
+  return removed;
+}
+
+/* Sweeps of Algorithm 1 until one deletes nothing.  adj is updated in place
+ * (deleted vertices lose their edges); alive[v] = 1 for survivors.
+ * stats: [0] sweeps that deleted something, [1] deleted vertices,
+ * [2] deleted edges, [3] steps (node b) that deleted something. */
+int kzo_dom_vertex(int32_t n, uint8_t *adj, uint8_t *alive, int64_t *stats) {
+  int64_t sweeps = 0, dv = 0, de = 0, steps = 0;
+  for (int32_t v = 0; v < n; ++v) alive[v] = 1;
+  for (;;) {
+    int any = 0;
+    for (int32_t b = 0; b < n; ++b) {
+      if (!alive[b]) continue;
+      int here = 0;
+      for (int32_t a = 0; a < n; ++a) {
+        if (vertex_dominates(n, adj, alive, b, a)) {
+          de += delete_vertex(n, adj, alive, a);
+          ++dv;
+          here = 1;
+        }
+      }
+      steps += here;
+      any |= here;
+    }
+    if (!any) break;
+    ++sweeps;
+  }
+  stats[0] = sweeps;
+  stats[1] = dv;
+  stats[2] = de;
+  stats[3] = steps;
+  return 0;
+}
+
+/* The edge {u,b} dominates {a,u} in the current graph (Definition 4.3.2). */
+static int edge_dominates(int32_t n, const uint8_t *adj, int32_t a, int32_t u, int32_t b) {
+  if (b == a || b == u || a == u) return 0;
+  if (!adj[(int64_t)a * n + u] || !adj[(int64_t)u * n + b] || adj[(int64_t)a * n + b]) return 0;
+  for (int32_t x = 0; x < n; ++x)
+    if (adj[(int64_t)a * n + x] && adj[(int64_t)u * n + x] && !adj[(int64_t)b * n + x]) return 0;
+  return 1;
+}
+
+/* Sweeps of Algorithm 2 until one deletes nothing.  adj is updated in place.
+ * stats: [0] sweeps that deleted something, [1] deleted edges. */
+int kzo_dom_edge(int32_t n, uint8_t *adj, int64_t *stats) {
+  int64_t sweeps = 0, de = 0;
+  for (;;) {
+    int any = 0;
+    for (int32_t a = 0; a < n; ++a) {
+      for (int32_t u = 0; u < n; ++u) {
+        if (!adj[(int64_t)a * n + u]) continue;
+        for (int32_t b = 0; b < n; ++b) {
+          if (!adj[(int64_t)u * n + b]) continue;
+          if (edge_dominates(n, adj, a, u, b)) {
+            adj[(int64_t)a * n + u] = 0;
+            adj[(int64_t)u * n + a] = 0;
+            ++de;
+            any = 1;
+            break;
+          }
+        }
+      }
+    }
+    if (!any) break;
+    ++sweeps;
+  }
+  stats[0] = sweeps;
+  stats[1] = de;
+  return 0;
+}

@@ -1,0 +1,190 @@
+"""Pins of the dominance oracle (section 4.3, Definitions 4.3.1 and 4.3.2,
+Algorithms 1 and 2 as read in oracle/kz_oracle_ext.c), checked against
+hand derivations and against properties the definitions fix -- not against
+a second copy of the same loops:
+
+* hand-derived results on small graphs, including ones where the order of
+  the sweep decides the result (twins, a deletion that enables a later one);
+* the clique number never changes (brute force over vertex subsets): every
+  single deletion trades a for b inside any clique through it;
+* the result is a fixpoint: no surviving vertex (edge) is dominated, checked
+  with Python sets;
+* vertex dominance leaves an induced subgraph, edge dominance a spanning
+  subgraph, both symmetric, and the counts add up.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import dom_edge, dom_vertex
+
+
+def graph(n, edges):
+    a = np.zeros((n, n), np.uint8)
+    for u, v in edges:
+        a[u, v] = a[v, u] = 1
+    return a
+
+
+def edges_of(a):
+    n = a.shape[0]
+    return {(u, v) for u in range(n) for v in range(u + 1, n) if a[u, v]}
+
+
+def omega(a, alive=None):
+    n = a.shape[0]
+    vs = [v for v in range(n) if alive is None or alive[v]]
+    best = 1 if vs else 0
+    for r in range(2, len(vs) + 1):
+        found = any(all(a[x, y] for x, y in itertools.combinations(c, 2)) for c in itertools.combinations(vs, r))
+        if not found:
+            break
+        best = r
+    return best
+
+
+def nbrs(a, v):
+    return {w for w in range(a.shape[0]) if a[v, w]}
+
+
+def random_graph(rng, n, p):
+    a = (rng.random((n, n)) < p).astype(np.uint8)
+    a = np.triu(a, 1)
+    return a + a.T
+
+
+# ---------------------------------------------------------------- vertex
+def test_vertex_cycle_of_four():
+    # step b=0 deletes 2 (N(2) = {1,3} = N(0)); only then is N(3) = {0} a
+    # subset of N(1) = {0}, so step b=1 deletes 3
+    a, alive, st = dom_vertex(graph(4, [(0, 1), (1, 2), (2, 3), (3, 0)]))
+    assert alive.tolist() == [1, 1, 0, 0]
+    assert edges_of(a) == {(0, 1)}
+    assert st == {"sweeps": 1, "deleted_vertices": 2, "deleted_edges": 3, "steps": 2}
+
+
+def test_vertex_twins_keep_the_first():
+    # 0 and 1 both see only 2: step b=0 deletes 1, and 0 survives (deleting
+    # both at once would lose every edge of the graph)
+    a, alive, st = dom_vertex(graph(3, [(0, 2), (1, 2)]))
+    assert alive.tolist() == [1, 0, 1]
+    assert edges_of(a) == {(0, 2)}
+    assert st["deleted_vertices"] == 1 and st["deleted_edges"] == 1
+
+
+def test_vertex_dominated_by_a_later_node():
+    # step b=0 finds nothing (N(1) = {2,3}, N(3) = {1}); step b=1 deletes
+    # a=0 < b (N(0) = {2} is in N(1)); then N(2) = {1} and step b=2 deletes
+    # its twin 3 (N(3) = {1})
+    a, alive, st = dom_vertex(graph(4, [(0, 2), (1, 2), (1, 3)]))
+    assert alive.tolist() == [0, 1, 1, 0]
+    assert edges_of(a) == {(1, 2)}
+    assert st["steps"] == 2
+
+
+def test_vertex_edgeless_and_star_and_complete():
+    _, alive, st = dom_vertex(graph(4, []))
+    assert alive.tolist() == [1, 0, 0, 0] and st["deleted_edges"] == 0
+    _, alive, _ = dom_vertex(graph(4, [(0, 1), (0, 2), (0, 3)]))
+    assert alive.tolist() == [1, 1, 0, 0]
+    k4 = graph(4, itertools.combinations(range(4), 2))
+    a, alive, st = dom_vertex(k4)
+    assert alive.all() and (a == k4).all() and st["sweeps"] == 0
+
+
+# ---------------------------------------------------------------- edge
+def test_edge_path_of_three():
+    # a=0, u=1, b=2: N(0) & N(1) is empty, so {1,2} dominates {0,1}
+    a, st = dom_edge(graph(3, [(0, 1), (1, 2)]))
+    assert edges_of(a) == {(1, 2)}
+    assert st == {"sweeps": 1, "deleted_edges": 1}
+
+
+def test_edge_k4_minus_an_edge():
+    # a=0: u=2, b=1: N(0) & N(2) = {3} is in N(1) -> delete {0,2};
+    #      u=3, b=1: N(0) & N(3) is now empty -> delete {0,3};
+    # the triangle {1,2,3} has no non-adjacent b left
+    a, st = dom_edge(graph(4, [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]))
+    assert edges_of(a) == {(1, 2), (1, 3), (2, 3)}
+    assert st["deleted_edges"] == 2
+
+
+def test_edge_triangle_and_complete_are_kept():
+    for n in (3, 5):
+        k = graph(n, itertools.combinations(range(n), 2))
+        a, st = dom_edge(k)
+        assert (a == k).all() and st["deleted_edges"] == 0
+
+
+# ---------------------------------------------------------------- properties
+def vertex_fixpoint_ok(a, alive):
+    n = a.shape[0]
+    for b in range(n):
+        for x in range(n):
+            if x == b or not alive[b] or not alive[x] or a[x, b]:
+                continue
+            if nbrs(a, x) <= nbrs(a, b):
+                return False
+    return True
+
+
+def edge_fixpoint_ok(a):
+    n = a.shape[0]
+    for x in range(n):
+        for u in nbrs(a, x):
+            common = nbrs(a, x) & nbrs(a, u)
+            for b in nbrs(a, u):
+                if b != x and not a[x, b] and common <= nbrs(a, b):
+                    return False
+    return True
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_vertex_properties(seed):
+    rng = np.random.default_rng(seed)
+    multi = 0
+    for _ in range(40):
+        n = int(rng.integers(1, 10))
+        g = random_graph(rng, n, float(rng.uniform(0.15, 0.9)))
+        a, alive, st = dom_vertex(g)
+        assert (a == a.T).all() and not a.diagonal().any()
+        keep = alive.astype(bool)
+        assert (a[np.ix_(keep, keep)] == g[np.ix_(keep, keep)]).all()   # induced subgraph
+        assert not a[~keep].any()
+        assert st["deleted_vertices"] == n - int(keep.sum())
+        assert st["deleted_edges"] == len(edges_of(g)) - len(edges_of(a))
+        assert keep.sum() >= min(n, 1)
+        assert omega(a, alive) == omega(g)
+        assert vertex_fixpoint_ok(a, alive)
+        multi += st["sweeps"] >= 2
+    assert multi >= 1   # some graph needs a second sweep
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_edge_properties(seed):
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(40):
+        n = int(rng.integers(2, 10))
+        g = random_graph(rng, n, float(rng.uniform(0.2, 0.9)))
+        a, st = dom_edge(g)
+        assert (a == a.T).all() and not a.diagonal().any()
+        assert not (a & ~g.astype(bool)).any()                              # only deletions
+        assert st["deleted_edges"] == len(edges_of(g)) - len(edges_of(a))
+        assert omega(a) == omega(g)
+        assert edge_fixpoint_ok(a)
+
+
+def test_edge_second_sweeps_reach_the_fixpoint():
+    # a deletion late in a sweep can make an earlier edge dominated (about 2 %
+    # of these graphs); the fixpoint check must still hold for them
+    rng = np.random.default_rng(7)
+    multi = 0
+    for _ in range(600):
+        n = int(rng.integers(3, 12))
+        g = random_graph(rng, n, float(rng.uniform(0.2, 0.9)))
+        a, st = dom_edge(g)
+        if st["sweeps"] >= 2:
+            multi += 1
+            assert edge_fixpoint_ok(a) and omega(a) == omega(g)
+    assert multi >= 3

@@ -9,6 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "kz_oracle.c")
+EXT = os.path.join(ROOT, "oracle", "kz_oracle_ext.c")
 
 MUTANTS = {
     "edge_threshold_k_minus_1": (
@@ -45,17 +46,55 @@ MUTANTS = {
 }
 
 
+# Mistakes planted in kz_oracle_ext.c (dominance, clique search, struction,
+# colourings); its pins are tests/test_oracle_ext.py.
+EXT_MUTANTS = {
+    "dom_vertex_subset_reversed": (
+        "    if (adj[(int64_t)a * n + x] && !adj[(int64_t)b * n + x]) return 0;",
+        "    if (adj[(int64_t)b * n + x] && !adj[(int64_t)a * n + x]) return 0;"),
+    "dom_vertex_only_later_nodes": (
+        "      for (int32_t a = 0; a < n; ++a) {\n        if (vertex_dominates",
+        "      for (int32_t a = b + 1; a < n; ++a) {\n        if (vertex_dominates"),
+    "dom_vertex_edges_left_at_the_neighbours": (
+        "      adj[(int64_t)x * n + a] = 0;\n      ++removed;", "      ++removed;"),
+    "dom_vertex_single_sweep": ("    if (!any) break;\n    ++sweeps;\n  }\n  stats[0] = sweeps;\n  stats[1] = dv;",
+                                "    break;\n  }\n  stats[0] = sweeps;\n  stats[1] = dv;"),
+    "dom_edge_whole_neighbourhood": (
+        "    if (adj[(int64_t)a * n + x] && adj[(int64_t)u * n + x] && !adj[(int64_t)b * n + x]) return 0;",
+        "    if (adj[(int64_t)a * n + x] && !adj[(int64_t)b * n + x]) return 0;"),
+    "dom_edge_one_direction": ("            adj[(int64_t)u * n + a] = 0;\n", ""),
+    "dom_edge_single_sweep": ("    if (!any) break;\n    ++sweeps;\n  }\n  stats[0] = sweeps;\n  stats[1] = de;",
+                              "    break;\n  }\n  stats[0] = sweeps;\n  stats[1] = de;"),
+}
+
+
+def run_mutant(name, path, old, new, tests, tmp_path):
+    text = open(path).read()
+    assert text.count(old) == 1, "mutation site not found: " + name
+    srcs = []
+    for f in (SRC, EXT):
+        if f == path:
+            m = tmp_path / os.path.basename(f)
+            m.write_text(text.replace(old, new))
+            srcs.append(str(m))
+        else:
+            srcs.append(f)
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-std=c11", "-O1", "-fPIC", "-shared", "-o", str(lib)] + srcs, check=True)
+    env = dict(os.environ, KZ_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", tests)],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "pins did not catch mutant %s:\n%s" % (name, r.stdout[-2000:])
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(name, tmp_path):
     old, new = MUTANTS[name]
-    text = open(SRC).read()
-    assert text.count(old) == 1, "mutation site not found: " + name
-    src = tmp_path / "mutant.c"
-    src.write_text(text.replace(old, new))
-    lib = tmp_path / "libmutant.so"
-    subprocess.run(["gcc", "-std=c11", "-O1", "-fPIC", "-shared", "-o", str(lib), str(src)], check=True)
-    env = dict(os.environ, KZ_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle.py")],
-                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, "pins did not catch mutant %s:\n%s" % (name, r.stdout[-2000:])
+    run_mutant(name, SRC, old, new, "test_oracle.py", tmp_path)
+
+
+@pytest.mark.parametrize("name", sorted(EXT_MUTANTS))
+def test_ext_pins_catch_planted_mistake(name, tmp_path):
+    old, new = EXT_MUTANTS[name]
+    run_mutant(name, EXT, old, new, "test_oracle_ext.py", tmp_path)
