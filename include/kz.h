@@ -360,6 +360,55 @@ int kz_profile_read(const kz_ctx *ctx, int kernel, double *total_ms, int64_t *la
 int kz_gen_bitset(kz_ctx *ctx, int32_t k, const int32_t *sizes, double p, uint32_t seed, uint32_t gid,
                   const int32_t *planted, uint64_t *rows, int32_t row_words, int32_t *colour, void *stream);
 
+/* ------------------------------------------------------------ dominance
+ * Dominance reductions (thesis section 4.3).  A different method from the
+ * colour index and kept apart from it: it uses no colouring, and vertex
+ * dominance may delete k-cliques (never all of the largest ones -- every
+ * deletion trades a for b inside any clique through it, so the clique number
+ * is unchanged).
+ *   KZ_DOM_VERTEX  Definition 4.3.1, Algorithm 1: node b dominates node a
+ *                  when they are not adjacent and N(a) is a subset of N(b).
+ *                  A sweep visits b in index order; each step deletes, with
+ *                  their edges, the nodes b dominates in the current graph.
+ *   KZ_DOM_EDGE    Definition 4.3.2, Algorithm 2: for distinct a, u, b the
+ *                  edge {u,b} dominates {a,u} when b is not a neighbour of a
+ *                  and N(a) & N(u) is a subset of N(b).  A sweep visits the
+ *                  pairs (a, u), u a neighbour of a, in index order and
+ *                  deletes {a,u} when some b makes it dominated in the
+ *                  current graph (a and u stay).
+ * Sweeps repeat until one deletes nothing.
+ *   rows: device uint64[n * row_words], bit w % 64 of word w / 64 of row v
+ *         set iff {v, w} is an edge; row_words >= ceil(n / 64) and <= 1024
+ *         (else KZ_ETOOLARGE); symmetric (KZ_EASYM), no self-loop
+ *         (KZ_ESELFLOOP), no bit at or beyond n (KZ_EINVAL);
+ *   ws, ws_bytes: device workspace of kz_dom_workspace_bytes() bytes,
+ *         256-byte aligned;
+ *   vmask: device uint8[n], 1 = node kept;
+ *   emask: device uint64[n * row_words], the adjacency left, same layout
+ *         (may be the rows buffer itself);
+ *   res: host struct receiving the counts.
+ * Blocking: the sweep is a chain of parallel scans, each followed by one
+ * small readback; returns after the fixpoint.  Outputs are unspecified
+ * when the status is not KZ_OK. */
+#define KZ_DOM_VERTEX 0
+#define KZ_DOM_EDGE 1
+
+typedef struct kz_dom_result {
+  int32_t status;
+  int32_t sweeps;            /* sweeps that deleted something               */
+  int64_t deleted_vertices;
+  int64_t deleted_edges;     /* undirected; vertex mode: edges of deleted
+                                nodes                                       */
+  int64_t input_edges;       /* undirected                                  */
+  int64_t events;            /* steps (vertex) or edges (edge) that deleted
+                                something                                   */
+  int64_t scans;             /* parallel scans run                          */
+} kz_dom_result;
+
+int kz_dom_workspace_bytes(int32_t n, size_t *bytes);
+int kz_dominance(kz_ctx *ctx, int32_t mode, int32_t n, const uint64_t *rows, int32_t row_words, void *ws,
+                 size_t ws_bytes, uint8_t *vmask, uint64_t *emask, void *stream, kz_dom_result *res);
+
 #ifdef __cplusplus
 }
 #endif

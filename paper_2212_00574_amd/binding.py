@@ -23,7 +23,7 @@ EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_
             "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
             "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_set_edge_path",
-            "kz_kernelize_noalloc")
+            "kz_kernelize_noalloc", "kz_dom_workspace_bytes", "kz_dominance")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # KZ_NOALLOC_SCRATCH_BYTES
 KZ_EDGE_BITSET, KZ_EDGE_MFMA_I8 = 0, 1
 KZ_EAGAIN = -9
@@ -44,6 +44,18 @@ class kz_result(C.Structure):
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class kz_dom_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("sweeps", C.c_int32), ("deleted_vertices", C.c_int64),
+                ("deleted_edges", C.c_int64), ("input_edges", C.c_int64), ("events", C.c_int64),
+                ("scans", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+KZ_DOM_VERTEX, KZ_DOM_EDGE = 0, 1
 
 
 class kz_request(C.Structure):
@@ -120,6 +132,11 @@ def _load() -> C.CDLL:
     lib.kz_set_edge_path.argtypes = [vp, C.c_int32]
     lib.kz_gen_bitset.restype = C.c_int
     lib.kz_gen_bitset.argtypes = [vp, C.c_int32, vp, C.c_double, C.c_uint32, C.c_uint32, vp, vp, C.c_int32, vp, vp]
+    lib.kz_dom_workspace_bytes.restype = C.c_int
+    lib.kz_dom_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.kz_dominance.restype = C.c_int
+    lib.kz_dominance.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int32, vp, C.c_size_t, vp, vp, vp,
+                                 C.POINTER(kz_dom_result)]
     return lib
 
 
@@ -240,6 +257,23 @@ def kz_set_edge_path(ctx: int, path: int) -> None:
     st = LIB.kz_set_edge_path(ctx, int(path))
     if st != KZ_OK:
         raise KzError(st, "kz_set_edge_path")
+
+
+def kz_dom_workspace_bytes(n: int) -> int:
+    need = C.c_size_t(0)
+    st = LIB.kz_dom_workspace_bytes(int(n), C.byref(need))
+    if st != KZ_OK:
+        raise KzError(st, "kz_dom_workspace_bytes")
+    return int(need.value)
+
+
+def kz_dominance(ctx: int, mode: int, n: int, rows: int | None, row_words: int, ws: int, ws_bytes: int,
+                 vmask: int | None, emask: int | None, stream: int | None) -> kz_dom_result:
+    """Dominance reductions on device bit rows (see kz.h); the result's status is the return value."""
+    res = kz_dom_result()
+    LIB.kz_dominance(ctx, int(mode), int(n), rows, int(row_words), ws, int(ws_bytes), vmask, emask, stream,
+                     C.byref(res))
+    return res
 
 
 def kz_server_fixed_bytes(max_slots: int) -> int:
@@ -405,6 +439,22 @@ class Kernelizer:
         emask = torch.empty_like(rows)
         res = self.run(graph_bitset(rows), colour, k, vmask, emask, **kw)
         return vmask, emask, res
+
+
+    def dominance(self, rows: torch.Tensor, mode: int, stream: torch.cuda.Stream | None = None,
+                  check: bool = True):
+        """Dominance reductions (KZ_DOM_VERTEX or KZ_DOM_EDGE) on plain bit
+        rows int64 [n, R] (R >= ceil(n/64)): (vmask u8[n], emask int64[n, R],
+        result dict)."""
+        n, R = int(rows.shape[0]), int(rows.shape[1]) if rows.dim() == 2 else 0
+        vmask = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        emask = torch.empty((max(n, 1), max(R, 1)), dtype=torch.int64, device=self.device)
+        ws = torch.empty(max(kz_dom_workspace_bytes(n), 256), dtype=torch.uint8, device=self.device)
+        res = kz_dominance(self.ctx, mode, n, _dev_ptr(rows), R, ws.data_ptr(), ws.numel(), _dev_ptr(vmask),
+                           _dev_ptr(emask), _stream_handle(stream, self.device))
+        if check and res.status != KZ_OK:
+            raise KzError(res.status, "kz_dominance")
+        return vmask[:n], emask[:n], res.as_dict()
 
 
 LINE_WORDS, LINE_VERTICES = 16, 128   # a graph's arena ranges start on a 128-byte line

@@ -375,3 +375,59 @@ def config5_specs(seed: int = 0, requests: int = 50_000, rate_hz: float = 1000.0
         t += float(rng.exponential(1.0 / rate_hz))
         out.append(ServeSpec(n, k, sizes, p, t))
     return out
+
+
+# ---------------------------------------------------------------- dominance
+# Uncoloured graphs for the dominance reductions.  The thesis evaluates them
+# on ten saved random graphs of 100, 300, ..., 1900 vertices whose edge count
+# is a fixed function of n (its table gives n(n-5)/2: 4750 at n = 100,
+# 44250 at 300, ...), built by first laying a path through every vertex in
+# order and then adding edges that are not uniformly random: some vertices
+# tend to take more edges than others.  Recipe here (the thesis's files are
+# not available): the path {i, i+1} is always present; vertex v gets a
+# tendency t_v = u_v ** 2, u_v uniform on [0, 1); of the other pairs, the
+# C(n,2) - m that stay absent are drawn without replacement with weight
+# (1 - t_a)(1 - t_b) + 1e-3, so vertices with a high tendency keep more
+# edges.  m defaults to n(n-5)/2 (clipped to [n-1, C(n,2)]).
+def dominance_graph(n: int, seed: int = 0, m: int | None = None) -> np.ndarray:
+    """Dense uint8 [n, n] adjacency (symmetric, zero diagonal)."""
+    n = int(n)
+    adj = np.zeros((n, n), np.uint8)
+    if n < 2:
+        return adj
+    full = n * (n - 1) // 2
+    m = full if m is None and n < 6 else (n * (n - 5) // 2 if m is None else int(m))
+    m = min(max(m, n - 1), full)
+    rng = _rng(0xD0, seed, n)
+    t = rng.random(n) ** 2
+    iu, ju = np.triu_indices(n, 1)
+    off_path = ju != iu + 1
+    a, b = iu[off_path], ju[off_path]
+    absent = full - m
+    keep = np.ones(a.size, bool)
+    if absent > 0:
+        w = (1.0 - t[a]) * (1.0 - t[b]) + 1e-3
+        drop = rng.choice(a.size, size=absent, replace=False, p=w / w.sum())
+        keep[drop] = False
+    adj[a[keep], b[keep]] = 1
+    adj[np.arange(n - 1), np.arange(1, n)] = 1
+    return adj | adj.T
+
+
+def dense_to_rows(adj: np.ndarray) -> np.ndarray:
+    """Plain bit rows uint64 [n, ceil(n/64)] of a dense 0/1 adjacency (bit w % 64
+    of word w // 64 of row v is adj[v, w])."""
+    n = adj.shape[0]
+    R = max((n + 63) // 64, 1)
+    padded = np.zeros((n, R * 64), np.uint8)
+    padded[:, :n] = adj
+    bits = np.packbits(padded.reshape(n, R, 64)[:, :, ::-1], axis=2).reshape(n, R, 8)
+    return bits[:, :, ::-1].copy().view("<u8").reshape(n, R)
+
+
+def rows_to_dense(rows: np.ndarray, n: int) -> np.ndarray:
+    """Inverse of dense_to_rows."""
+    rows = np.ascontiguousarray(rows).view(np.uint64).reshape(n, -1)
+    b = rows.view(np.uint8).reshape(n, -1, 8)[:, :, ::-1]
+    bits = np.unpackbits(b, axis=2)[:, :, ::-1].reshape(n, -1)
+    return bits[:, :n].astype(np.uint8)
