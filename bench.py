@@ -55,7 +55,11 @@ WORKLOADS = {
     "c4": "4096 graphs, k~U{4..16}, class sizes~U{8..128}, p~U[0.2,0.8], 10% planted k-clique, uint64 bit rows",
     "c5": "served requests: n log-uniform [200,20000], k~U{5..30} near-equal classes, p~U[0.1,0.9], Poisson "
           "arrivals, uint64 bit rows materialised on the device at arrival",
+    "dom": "dominance reductions (section 4.3), vertex and edge mode, on the thesis's ten evaluation sizes "
+           "n = 100, 300, ..., 1900 with n(n-5)/2 edges (path plus skewed edges), plain bit rows",
 }
+DOM_SIZES = list(range(100, 2000, 200))
+DOM_CPU_EDGE_SIZES = (100, 300, 500, 700, 900)   # edge-mode oracle sample: about 14 s on one core
 
 
 def parse(argv=None):
@@ -87,7 +91,6 @@ def say(*a):
 # is built from (a committed counter summary is used only while they match).
 PROFILED = {
     "c1": ("k_edge", ("kz_kernels.hip", "kz_internal.h")),
-    "c2": ("k_edge", ("kz_kernels.hip", "kz_internal.h")),
     "c3a": ("k_edge", ("kz_kernels.hip", "kz_internal.h")),
     "c3b": ("k_csr_edge", ("kz_csr.hip", "kz_internal.h")),
     "c4": ("k_batch", ("kz_batch.hip", "kz_internal.h")),
@@ -102,11 +105,11 @@ def _code_only(text):
     return " ".join(text.split())
 
 
-def source_hash(workload="c2"):
+def source_hash(workload="c3a"):
     """Hash of the code (comments and layout ignored) the workload's roofline
     kernel is built from."""
     h = hashlib.sha256()
-    for f in PROFILED.get(workload, PROFILED["c2"])[1]:
+    for f in PROFILED.get(workload, PROFILED["c3a"])[1]:
         h.update(_code_only(open(os.path.join(ROOT, "paper_2212_00574_amd", "csrc", f)).read()).encode())
     return h.hexdigest()[:16]
 
@@ -116,7 +119,7 @@ def profile_value(workload, key, kernel=None):
     profiles/<kernel>_<workload>.md (default: the workload's roofline
     kernel); None when absent or when the kernel's sources changed since the
     counters were taken ("- source_sha: S")."""
-    kernel = kernel or PROFILED.get(workload, PROFILED["c2"])[0]
+    kernel = kernel or PROFILED.get(workload, PROFILED["c3a"])[0]
     path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
@@ -236,6 +239,35 @@ def finish_cpu_child(proc, core, workload):
                      % (workload, what, d["edge_tests"], secs, core, d["gen_s"], d["ingest_s"]),
            "host": host_info()}
     return cpu, d
+
+
+def _dom_cpu_child(seed):
+    """Child process pinned to one core: the dominance oracle's times (vertex
+    mode on every evaluation graph, edge mode on DOM_CPU_EDGE_SIZES)."""
+    from oracle import dom_edge, dom_vertex
+    from paper_2212_00574_amd import inputs
+    out = {"vertex": {}, "edge": {}}
+    for n in DOM_SIZES:
+        adj = inputs.dominance_graph(n, seed)
+        t0 = time.perf_counter()
+        dom_vertex(adj)
+        out["vertex"][n] = time.perf_counter() - t0
+        if n in DOM_CPU_EDGE_SIZES:
+            t0 = time.perf_counter()
+            dom_edge(adj)
+            out["edge"][n] = time.perf_counter() - t0
+    print(json.dumps(out), flush=True)
+
+
+def start_dom_cpu_child(seed):
+    cpus = sorted(os.sched_getaffinity(0))
+    core = cpus[-2] if len(cpus) > 1 else cpus[-1]
+    code = ("import os, sys; os.sched_setaffinity(0, {%d}); sys.path.insert(0, %r); import bench; "
+            "bench._dom_cpu_child(%d)" % (core, ROOT, seed))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    p = subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                         env=env)
+    return p, core
 
 
 # --------------------------------------------------------------- single graph
@@ -720,6 +752,80 @@ def run_serve(args):
             if check_ids else None}
 
 
+# --------------------------------------------------------------- dominance
+def run_dom(args, cpu_proc=None):
+    """Dominance reductions (section 4.3) on the ten evaluation graphs, both
+    modes: per-graph times (median of up to three calls after one warm-up;
+    each call runs the whole fixpoint and reads the counts back), parity with
+    the oracle's full-size fixture, and the oracle's times on a sample."""
+    import hashlib
+
+    import torch
+
+    from paper_2212_00574_amd import inputs
+    from paper_2212_00574_amd.binding import KZ_DOM_EDGE, KZ_DOM_VERTEX, Kernelizer
+    kz = Kernelizer(0)
+    fx = golden("dom_seed%d.json" % args.seed)
+    ref = {(r["mode"], r["n"]): r for r in fx["graphs"]} if fx else {}
+    graphs = {}
+    for n in DOM_SIZES:
+        rows = inputs.dense_to_rows(inputs.dominance_graph(n, args.seed)).view(np.int64)
+        graphs[n] = torch.from_numpy(rows).to(kz.device)
+    torch.cuda.synchronize()
+    out = {"metric": "dominance fixpoint time on the ten evaluation graphs", "unit": "ms", "higher_is_better": False,
+           "config": {"workload": "dom: " + WORKLOADS["dom"], "sizes": DOM_SIZES, "seed": args.seed},
+           "bound": "latency: a sweep is a chain of dependent steps (each step's tests run on one workgroup); "
+                    "no HBM or ALU roof applies"}
+    equal = bool(ref)
+    reps = max(1, min(args.steps, 3))
+    for name, mode in (("vertex", KZ_DOM_VERTEX), ("edge", KZ_DOM_EDGE)):
+        per = {}
+        for n, rows in graphs.items():
+            times = []
+            for rep in range(reps + 1):
+                t0 = time.perf_counter()
+                vm, em, r = kz.dominance(rows, mode)
+                t1 = time.perf_counter()
+                if rep:
+                    times.append((t1 - t0) * 1e3)
+            h = hashlib.sha256()
+            h.update(vm.cpu().numpy().astype(np.uint8).tobytes())
+            h.update(em.cpu().numpy().view(np.uint64).astype("<u8").tobytes())
+            h.update(np.array([r["sweeps"], r["deleted_vertices"], r["deleted_edges"], r["events"]], "<i8").tobytes())
+            rec = ref.get((name, n))
+            if rec is None or rec["sha256"] != h.hexdigest():
+                equal = False
+            per[n] = {"ms": round(float(np.median(times)), 4), "sweeps": r["sweeps"],
+                      "deleted_vertices": r["deleted_vertices"], "deleted_edges": r["deleted_edges"],
+                      "edges": r["input_edges"]}
+        out[name] = {"total_ms": round(sum(v["ms"] for v in per.values()), 3), "graphs": per}
+        say("dom %s: %.2f ms for the ten graphs" % (name, out[name]["total_ms"]))
+    out["oracle_equal"] = equal
+    out["oracle_check"] = "SHA-256 of vmask || surviving rows || counts against tests/golden/dom_seed%d.json" % args.seed
+    cpu = None
+    if cpu_proc is not None:
+        proc, core = cpu_proc
+        o, err = proc.communicate(timeout=900)
+        if proc.returncode == 0:
+            d = json.loads(o.strip().splitlines()[-1])
+            v_s = sum(d["vertex"].values())
+            e_s = sum(d["edge"].values())
+            e_gpu = sum(out["edge"]["graphs"][int(n)]["ms"] for n in d["edge"]) / 1e3
+            cpu = {"value": round(v_s * 1e3, 3), "unit": "ms (vertex mode, ten graphs)", "cores": 1, "kind": "oracle",
+                   "edge_mode_ms": round(e_s * 1e3, 1),
+                   "sample": "vertex mode on all ten graphs; edge mode on n = %s only (%.1f s; the GPU takes %.1f ms "
+                             "on the same five); pinned to cpu %d" % (", ".join(map(str, DOM_CPU_EDGE_SIZES)),
+                                                                      e_s, e_gpu * 1e3, core),
+                   "edge_gpu_speedup_on_sample": round(e_s / e_gpu, 1) if e_gpu else None,
+                   "vertex_gpu_speedup": round(v_s / (out["vertex"]["total_ms"] / 1e3), 2),
+                   "host": host_info()}
+        else:
+            say("dominance cpu child failed:", err[-1000:])
+    out["cpu_baseline"] = cpu
+    kz.close()
+    return out
+
+
 # --------------------------------------------------------------- main
 def copy_calibration(mib):
     """Device-to-device copies of a known size, for scaling memory counters."""
@@ -743,18 +849,23 @@ def main():
               "(a graph would shard by class columns, one block of classes per GPU).", file=sys.stderr)
         sys.exit(2)
     w = "c3a" if args.workload == "headline" else args.workload
-    cpu_proc = None
+    cpu_proc = dom_proc = None
     if not args.no_cpu_baseline and w in ("c1", "c2", "c3a", "c3b"):
         cpu_proc = start_cpu_child(w, args.seed)
+    if not args.no_cpu_baseline and (w == "dom" or args.workload == "headline"):
+        dom_proc = start_dom_cpu_child(args.seed)
     if w == "c4":
         out = run_batch(args)
     elif w == "c5":
         out = run_serve(args)
+    elif w == "dom":
+        out = run_dom(args, dom_proc)
     else:
         out = run_single(args, w, cpu_proc)
         if args.workload == "headline":
             out["batch"] = run_batch(args)
             out["serve"] = run_serve(args)
+            out["dominance"] = run_dom(args, dom_proc)
     out.setdefault("n_gpus", 1)
     print(json.dumps(out), flush=True)
 

@@ -94,21 +94,72 @@ __global__ void __launch_bounds__(256) k_dom_setup(const uint64_t *__restrict__ 
 }
 
 // ---- vertex dominance (Definition 4.3.1): the whole fixpoint, one workgroup
+//
+// Most steps delete nothing, so the waves first test consecutive steps at
+// once (wave w: does node b0 + w dominate anyone?), on the same graph; the
+// first step in sweep order that does is then run in full by the whole
+// workgroup, and the scan goes on right after it.  Steps before it saw the
+// graph the sequential sweep would have shown them (nothing was deleted in
+// between); the results of the steps after it are dropped.
 __global__ void __launch_bounds__(1024) k_dom_vertex_run(uint64_t *__restrict__ st, uint8_t *__restrict__ alive,
                                                          int n, int R, DomHdr *h) {
+  __shared__ uint64_t AL[kDomMaxWords];  // live nodes (bit v of word v / 64)
   __shared__ uint64_t rb[kDomMaxWords], D[kDomMaxWords];
+  __shared__ int dw[kDomMaxWords];       // the words of D that hold a deleted node
   __shared__ unsigned long long nv, ne;
-  __shared__ int any_sweep;
-  const int tid = threadIdx.x;
+  __shared__ int any_sweep, ndw;
+  __shared__ unsigned hits;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
   if (h->prio != P_NONE) return;
+  for (int w = tid; w < R; w += blockDim.x) {
+    const int lo = 64 * w;
+    AL[w] = lo + 64 <= n ? ~0ull : lo < n ? (1ull << (n - lo)) - 1 : 0ull;
+  }
   long long sweeps = 0, steps = 0;
   for (;;) {
     // every thread has read the previous sweep's flag before it is reset
     __syncthreads();
     if (tid == 0) any_sweep = 0;
-    for (int b = 0; b < n; ++b) {
+    int b0 = 0;
+    while (b0 < n) {
+      if (tid == 0) hits = 0;
       __syncthreads();
-      if (!alive[b]) continue;
+      // scan: wave w tests step b0 + w; its lanes take the row words of the
+      // live non-neighbours of b and test those nodes one by one
+      {
+        const int b = b0 + wid;
+        if (b < n && ((AL[b >> 6] >> (b & 63)) & 1ull)) {
+          const uint64_t *rbg = st + (long long)b * R;
+          bool hit = false;
+          for (int w = lane; w < R && !hit; w += kWave) {
+            uint64_t cand = AL[w] & ~rbg[w];
+            if (w == (b >> 6)) cand &= ~(1ull << (b & 63));
+            while (cand && !hit) {
+              const int a = 64 * w + __builtin_ctzll(cand);
+              cand &= cand - 1;
+              const uint64_t *ra = st + (long long)a * R;
+              bool sub = true;
+              for (int w2 = 0; w2 < R; ++w2) {
+                if (ra[w2] & ~rbg[w2]) {
+                  sub = false;
+                  break;
+                }
+              }
+              hit = sub;
+            }
+          }
+          if (__ballot(hit) != 0ull && lane == 0) atomicOr(&hits, 1u << wid);
+        }
+      }
+      __syncthreads();
+      const unsigned hm = hits;
+      if (!hm) {
+        b0 += nwaves;
+        continue;
+      }
+      const int b = b0 + __builtin_ctz(hm);
+      // the step in full: every node b dominates, deleted with its edges
       for (int w = tid; w < R; w += blockDim.x) {
         rb[w] = st[(long long)b * R + w];
         D[w] = 0;
@@ -116,38 +167,49 @@ __global__ void __launch_bounds__(1024) k_dom_vertex_run(uint64_t *__restrict__ 
       if (tid == 0) {
         nv = 0;
         ne = 0;
+        ndw = 0;
       }
       __syncthreads();
-      for (int a = tid; a < n; a += blockDim.x) {
-        if (a == b || !alive[a] || ((rb[a >> 6] >> (a & 63)) & 1ull)) continue;
-        const uint64_t *ra = st + (long long)a * R;
-        bool sub = true;
-        unsigned long long deg = 0;
-        for (int w = 0; w < R; ++w) {
-          const uint64_t x = ra[w];
-          deg += __popcll(x);
-          if (x & ~rb[w]) {
-            sub = false;
-            break;
+      for (int w = tid; w < R; w += blockDim.x) {
+        uint64_t cand = AL[w] & ~rb[w];
+        if (w == (b >> 6)) cand &= ~(1ull << (b & 63));
+        while (cand) {
+          const int a = 64 * w + __builtin_ctzll(cand);
+          cand &= cand - 1;
+          const uint64_t *ra = st + (long long)a * R;
+          bool sub = true;
+          unsigned long long deg = 0;
+          for (int w2 = 0; w2 < R; ++w2) {
+            const uint64_t x = ra[w2];
+            deg += __popcll(x);
+            if (x & ~rb[w2]) {
+              sub = false;
+              break;
+            }
+          }
+          if (sub) {
+            D[w] |= 1ull << (a & 63);   // word w belongs to this thread alone
+            atomicAdd(&nv, 1ull);
+            atomicAdd(&ne, deg);
           }
         }
-        if (sub) {
-          atomicOr((unsigned long long *)&D[a >> 6], 1ull << (a & 63));
-          atomicAdd(&nv, 1ull);
-          atomicAdd(&ne, deg);
-        }
+        if (D[w]) dw[atomicAdd(&ndw, 1)] = w;
       }
       __syncthreads();
-      if (nv == 0) continue;
-      // the deleted nodes lose their rows; their neighbours (all in N(b)) lose them
+      // the deleted nodes lose their rows and their place in AL; their
+      // neighbours (all in N(b)) lose them, in the words listed in dw
+      const int nd = ndw;
+      for (int w = tid; w < R; w += blockDim.x) AL[w] &= ~D[w];
       for (int x = tid; x < n; x += blockDim.x) {
         uint64_t *rx = st + (long long)x * R;
         if ((D[x >> 6] >> (x & 63)) & 1ull) {
           alive[x] = 0;
           for (int w = 0; w < R; ++w) rx[w] = 0;
         } else if ((rb[x >> 6] >> (x & 63)) & 1ull) {
-          for (int w = 0; w < R; ++w)
+          for (int i = 0; i < nd; ++i) {
+            const int w = dw[i];
             if (rx[w] & D[w]) rx[w] &= ~D[w];
+          }
         }
       }
       if (tid == 0) {
@@ -156,6 +218,9 @@ __global__ void __launch_bounds__(1024) k_dom_vertex_run(uint64_t *__restrict__ 
         any_sweep = 1;
         ++steps;
       }
+      b0 = b + 1;
+      // every thread has read `hits` and the step is applied before the next scan
+      __syncthreads();
     }
     __syncthreads();
     if (!any_sweep) break;

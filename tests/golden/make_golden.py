@@ -2,7 +2,7 @@
 ``oracle/`` for results and ``paper_2212_00574_amd.inputs`` for the seeded
 graphs).  Run from the repository root:
 
-    python tests/golden/make_golden.py [c3a|c4|c5 ...] [--procs 8]
+    python tests/golden/make_golden.py [c3a|c4|c5|dom ...] [--procs 8]
 
 Every graph's record is the SHA-256 digest of
 
@@ -23,6 +23,14 @@ Workloads (seed 0):
        10% planted cliques), buckets of 64 graphs;
   c5   of the 50,000 served requests: every request with n <= 5000, a
        seeded 2% of the others and the 100 largest, buckets of 256.
+  dom  the dominance reductions (section 4.3) on the thesis's ten evaluation
+       sizes n = 100, 300, ..., 1900 (inputs.dominance_graph, seed 0), vertex
+       and edge mode; per graph and mode the SHA-256 of
+           vmask (n bytes) || surviving adjacency as plain bit rows (n *
+           ceil(n/64) little-endian uint64 words) || int64 LE [sweeps,
+           deleted vertices, deleted edges, events]
+       (events: steps that deleted nodes, or deleted edges), from
+       oracle.dom_vertex / oracle.dom_edge.
 """
 from __future__ import annotations
 
@@ -41,7 +49,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from oracle import fixpoint_rows  # noqa: E402
+from oracle import dom_edge, dom_vertex, fixpoint_rows  # noqa: E402
 from paper_2212_00574_amd import inputs  # noqa: E402
 
 SEED = 0
@@ -89,6 +97,35 @@ def _one(task):
 
 
 _C5 = None
+DOM_SIZES = list(range(100, 2000, 200))
+
+
+def dom_digest(vmask, adj, sweeps, dv, de, events) -> bytes:
+    n = adj.shape[0]
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(vmask, np.uint8).tobytes())
+    h.update(inputs.dense_to_rows(adj).astype("<u8", copy=False).tobytes())
+    h.update(np.array([sweeps, dv, de, events], "<i8").tobytes())
+    assert n == len(vmask)
+    return h.digest()
+
+
+def _dom_one(task):
+    mode, n = task
+    adj = inputs.dominance_graph(n, SEED)
+    t0 = time.time()
+    if mode == "vertex":
+        out, alive, st = dom_vertex(adj)
+        d = dom_digest(alive, out, st["sweeps"], st["deleted_vertices"], st["deleted_edges"], st["steps"])
+        rec = {"sweeps": st["sweeps"], "deleted_vertices": st["deleted_vertices"],
+               "deleted_edges": st["deleted_edges"], "events": st["steps"]}
+    else:
+        out, st = dom_edge(adj)
+        d = dom_digest(np.ones(n, np.uint8), out, st["sweeps"], 0, st["deleted_edges"], st["deleted_edges"])
+        rec = {"sweeps": st["sweeps"], "deleted_vertices": 0, "deleted_edges": st["deleted_edges"],
+               "events": st["deleted_edges"]}
+    rec.update(mode=mode, n=n, edges=int(adj.sum()) // 2, sha256=d.hex(), oracle_s=round(time.time() - t0, 3))
+    return rec
 
 
 def buckets(results, size):
@@ -136,6 +173,14 @@ def main():
                                "p~U[0.1,0.9]; coverage: every request with n <= 5000, a seeded 2% of the rest, "
                                "the 100 largest", "seed": SEED, "requests": 50000, "covered": len(ids),
                    "bucket": C5_BUCKET, "buckets": buckets(res, C5_BUCKET)}
+        elif which == "dom":
+            tasks = sorted([(m, n) for m in ("vertex", "edge") for n in DOM_SIZES], key=lambda t: -t[1])
+            with mp.get_context("fork").Pool(args.procs) as pool:
+                res = pool.map(_dom_one, tasks, chunksize=1)
+            res.sort(key=lambda r: (r["mode"], r["n"]))
+            doc = {"workload": "dominance (section 4.3) on the ten evaluation sizes n = 100..1900, "
+                               "m = n(n-5)/2, path plus skewed edges (inputs.dominance_graph)", "seed": SEED,
+                   "graphs": res}
         else:
             raise SystemExit("unknown workload " + which)
         path = os.path.join(HERE, "%s_seed%d.json" % (which, SEED))

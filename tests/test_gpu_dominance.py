@@ -143,3 +143,29 @@ def test_in_place_and_statuses(kz):
     assert status(g, rw=1100) == KZ_ETOOLARGE    # rows beyond 1024 words
     assert status(g, wsb=16) == -6              # KZ_EWORKSPACE
     assert status(g, mode=7) == KZ_EINVAL
+
+
+def test_evaluation_set_full_size(kz):
+    """The thesis's ten evaluation sizes (n = 100..1900), both modes, against
+    the oracle's fixture (tests/golden/dom_seed0.json, written by
+    tests/golden/make_golden.py dom): SHA-256 of vmask || surviving bit rows ||
+    [sweeps, deleted vertices, deleted edges, events]."""
+    import hashlib
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "dom_seed0.json")))
+    for rec in fx["graphs"]:
+        n = rec["n"]
+        say("dominance full size:", rec["mode"], n)
+        adj = inputs.dominance_graph(n, fx["seed"])
+        rows = torch.from_numpy(inputs.dense_to_rows(adj).view(np.int64)).to(DEV)
+        mode = KZ_DOM_VERTEX if rec["mode"] == "vertex" else KZ_DOM_EDGE
+        vm, em, res = kz.dominance(rows, mode)
+        torch.cuda.synchronize()
+        h = hashlib.sha256()
+        h.update(vm.cpu().numpy().astype(np.uint8).tobytes())
+        h.update(em.cpu().numpy().view(np.uint64).astype("<u8").tobytes())
+        h.update(np.array([res["sweeps"], res["deleted_vertices"], res["deleted_edges"], res["events"]],
+                          "<i8").tobytes())
+        assert res["input_edges"] == rec["edges"], rec
+        assert h.hexdigest() == rec["sha256"], (rec, res)
