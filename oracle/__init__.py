@@ -93,6 +93,8 @@ def _load():
     lib.kzo_dom_vertex.argtypes = [i32, vp, vp, vp]
     lib.kzo_dom_edge.restype = C.c_int
     lib.kzo_dom_edge.argtypes = [i32, vp, vp]
+    lib.kzo_find_clique.restype = C.c_int
+    lib.kzo_find_clique.argtypes = [i32, vp, vp, i32, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -293,4 +295,22 @@ def dom_edge(adj):
     st = np.zeros(2, np.int64)
     _load().kzo_dom_edge(n, _ptr(a), _ptr(st))
     return a, {"sweeps": int(st[0]), "deleted_edges": int(st[1])}
+
+
+# ---- k-clique search on a (kernelized) graph, kz_oracle_ext.c
+def find_clique(adj, colour, k, alive=None):
+    """The lexicographically smallest k-clique (class 0's vertex first) among
+    the live vertices of a legally k-coloured dense graph: (clique int32[k]
+    or None, nodes).  nodes counts the partial picks the plain class-order
+    search extends (a measure, not a result)."""
+    a = np.ascontiguousarray(adj, dtype=np.uint8)
+    n = a.shape[0]
+    col = np.ascontiguousarray(colour, dtype=np.int32)
+    al = None if alive is None else np.ascontiguousarray(alive, dtype=np.uint8)
+    out = np.zeros(max(int(k), 1), np.int32)
+    nodes = np.zeros(1, np.int64)
+    f = _load().kzo_find_clique(n, _ptr(a), _ptr(col), int(k), _ptr(al), _ptr(out), _ptr(nodes))
+    if f < 0:
+        raise MemoryError("oracle: allocation failed")
+    return (out[:k].copy() if f else None), int(nodes[0])
 

@@ -139,3 +139,43 @@ int kzo_dom_edge(int32_t n, uint8_t *adj, int64_t *stats) {
   stats[1] = de;
   return 0;
 }
+
+/*
+ * k-clique search (the thesis's problem statement: the kernel is handed to
+ * a standard solver that looks for a k-clique; section 4.2 names the
+ * problem, no solver is given).  On a legally k-coloured graph a k-clique
+ * holds one vertex of every class.  The search picks a vertex of class 0,
+ * then of class 1, ... in increasing index order, each adjacent to every
+ * vertex picked before, among the live vertices (alive[v] != 0; all when
+ * alive is NULL).  The first complete pick is the lexicographically smallest
+ * k-clique (ordered by class 0's vertex, then class 1's, ...).
+ *   adj: n*n bytes, colour: int32[n] in [0, k), clique: int32[k] out.
+ * Returns 1 and fills clique when one exists, 0 otherwise; *nodes counts the
+ * partial picks extended (a measure of the search, not a result).
+ */
+static int clique_rec(int32_t n, const uint8_t *adj, const int32_t *colour, int32_t k, const uint8_t *alive,
+                      int32_t c, int32_t *pick, int64_t *nodes) {
+  if (c == k) return 1;
+  for (int32_t v = 0; v < n; ++v) {
+    if (colour[v] != c || (alive && !alive[v])) continue;
+    int ok = 1;
+    for (int32_t j = 0; j < c && ok; ++j) ok = adj[(int64_t)pick[j] * n + v] != 0;
+    if (!ok) continue;
+    pick[c] = v;
+    ++*nodes;
+    if (clique_rec(n, adj, colour, k, alive, c + 1, pick, nodes)) return 1;
+  }
+  return 0;
+}
+
+int kzo_find_clique(int32_t n, const uint8_t *adj, const int32_t *colour, int32_t k, const uint8_t *alive,
+                    int32_t *clique, int64_t *nodes) {
+  *nodes = 0;
+  if (k < 1) return 0;
+  int32_t *pick = (int32_t *)calloc((size_t)k, sizeof(int32_t));
+  if (!pick) return -1;
+  const int found = clique_rec(n, adj, colour, k, alive, 0, pick, nodes);
+  for (int32_t c = 0; c < k; ++c) clique[c] = found ? pick[c] : -1;
+  free(pick);
+  return found;
+}

@@ -188,3 +188,80 @@ def test_edge_second_sweeps_reach_the_fixpoint():
             multi += 1
             assert edge_fixpoint_ok(a) and omega(a) == omega(g)
     assert multi >= 3
+
+
+# ---------------------------------------------------------------- clique search
+from oracle import FMT_DENSE, OracleGraph, find_clique  # noqa: E402
+
+
+def coloured_graph(rng, sizes, p, plant=False):
+    sizes = [int(s) for s in sizes]
+    n = sum(sizes)
+    colour = np.repeat(np.arange(len(sizes), dtype=np.int32), sizes)
+    a = (rng.random((n, n)) < p).astype(np.uint8)
+    a = np.triu(a, 1)
+    a = a + a.T
+    a[colour[:, None] == colour[None, :]] = 0
+    if plant and all(sizes):
+        pick = [int(rng.integers(0, s)) + int(np.sum(sizes[:c])) for c, s in enumerate(sizes)]
+        for x, y in itertools.combinations(pick, 2):
+            a[x, y] = a[y, x] = 1
+    return a, colour
+
+
+def brute_smallest(a, colour, k, alive=None):
+    classes = [[v for v in range(a.shape[0]) if colour[v] == c and (alive is None or alive[v])] for c in range(k)]
+    for tup in itertools.product(*classes):     # lexicographic in class order
+        if all(a[x, y] for x, y in itertools.combinations(tup, 2)):
+            return list(tup)
+    return None
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_clique_search_is_the_brute_force_smallest(seed):
+    rng = np.random.default_rng(300 + seed)
+    found = 0
+    for _ in range(60):
+        k = int(rng.integers(1, 5))
+        sizes = rng.integers(1, 5, size=k)
+        a, colour = coloured_graph(rng, sizes, float(rng.uniform(0.3, 0.95)), plant=bool(rng.random() < 0.3))
+        alive = (rng.random(a.shape[0]) < 0.85).astype(np.uint8) if rng.random() < 0.5 else None
+        got, nodes = find_clique(a, colour, k, alive)
+        ref = brute_smallest(a, colour, k, alive)
+        assert (got is None) == (ref is None)
+        if ref is not None:
+            found += 1
+            assert got.tolist() == ref
+            assert nodes >= k
+    assert found >= 20
+
+
+def test_clique_search_agrees_with_the_clique_count():
+    # OracleGraph.kcliques (pinned by closed forms and itertools in
+    # test_oracle.py) counts k-cliques; the search finds one iff it is > 0
+    rng = np.random.default_rng(17)
+    for _ in range(40):
+        k = int(rng.integers(2, 6))
+        sizes = rng.integers(2, 8, size=k)
+        a, colour = coloured_graph(rng, sizes, float(rng.uniform(0.2, 0.8)))
+        og = OracleGraph(FMT_DENSE, a.shape[0], k, colour, adj=a)
+        count = og.kcliques()[0]
+        got, _ = find_clique(a, colour, k)
+        assert (got is not None) == (count > 0)
+        if got is not None:
+            assert len(set(colour[got].tolist())) == k
+            assert all(a[x, y] for x, y in itertools.combinations(got.tolist(), 2))
+
+
+def test_clique_search_complete_multipartite_and_live_mask():
+    sizes = [3, 1, 4, 2]
+    a, colour = coloured_graph(np.random.default_rng(0), sizes, 1.0)
+    got, nodes = find_clique(a, colour, 4)
+    assert got.tolist() == [0, 3, 4, 8] and nodes == 4          # first vertex of every class
+    alive = np.ones(a.shape[0], np.uint8)
+    alive[[0, 4]] = 0
+    got, _ = find_clique(a, colour, 4, alive)
+    assert got.tolist() == [1, 3, 5, 8]
+    alive[3] = 0                                                 # class 1 emptied
+    assert find_clique(a, colour, 4, alive)[0] is None
+    assert find_clique(a, colour, 1)[0].tolist() == [0]

@@ -63,6 +63,14 @@ EXT_MUTANTS = {
         "    if (adj[(int64_t)a * n + x] && adj[(int64_t)u * n + x] && !adj[(int64_t)b * n + x]) return 0;",
         "    if (adj[(int64_t)a * n + x] && !adj[(int64_t)b * n + x]) return 0;"),
     "dom_edge_one_direction": ("            adj[(int64_t)u * n + a] = 0;\n", ""),
+    "clique_last_pick_unchecked": (
+        "    for (int32_t j = 0; j < c && ok; ++j) ok = adj[(int64_t)pick[j] * n + v] != 0;",
+        "    for (int32_t j = 0; j + 1 < c && ok; ++j) ok = adj[(int64_t)pick[j] * n + v] != 0;"),
+    "clique_ignores_live_mask": (
+        "    if (colour[v] != c || (alive && !alive[v])) continue;", "    if (colour[v] != c) continue;"),
+    "clique_descending_order": (
+        "  for (int32_t v = 0; v < n; ++v) {\n    if (colour[v] != c",
+        "  for (int32_t v = n - 1; v >= 0; --v) {\n    if (colour[v] != c"),
     "dom_edge_single_sweep": ("    if (!any) break;\n    ++sweeps;\n  }\n  stats[0] = sweeps;\n  stats[1] = de;",
                               "    break;\n  }\n  stats[0] = sweeps;\n  stats[1] = de;"),
 }
