@@ -409,6 +409,36 @@ int kz_dom_workspace_bytes(int32_t n, size_t *bytes);
 int kz_dominance(kz_ctx *ctx, int32_t mode, int32_t n, const uint64_t *rows, int32_t row_words, void *ws,
                  size_t ws_bytes, uint8_t *vmask, uint64_t *emask, void *stream, kz_dom_result *res);
 
+/* ------------------------------------------------------------ clique search
+ * The search the kernel is handed to (the thesis's problem: is there a
+ * k-clique?).  On a legally k-coloured graph a k-clique holds one vertex of
+ * every class.  kz_find_clique returns the lexicographically smallest
+ * k-clique among the live vertices -- ordered by its class-0 vertex, then
+ * its class-1 vertex, ... (vertex ids are the slot ids of the bit rows) --
+ * or reports that there is none.  Run it on kz_kernelize's output (rows =
+ * its emask, vmask = its vmask): every k-clique survives the kernel, so the
+ * answer is the same as on the input, found in less work.
+ *   g: KZ_BITSET_U64 (class-major slots; the rows are not re-validated, they
+ *      must be a valid kz_kernelize input or output);
+ *   colour: device int32[n], sorted, in [0, k) (KZ_ECOLOUR / KZ_EINVAL);
+ *   k: 1..64 (KZ_ETOOLARGE beyond);
+ *   vmask: device uint8[n] (0 = deleted), or NULL for all vertices;
+ *   ws, ws_bytes: device workspace of kz_clique_workspace_bytes() bytes,
+ *      256-byte aligned;
+ *   clique: device int32[k], the clique's vertex of each class, or all -1.
+ * Blocking: returns after the search with res->found. */
+typedef struct kz_clique_result {
+  int32_t status;
+  int32_t found;             /* 1 iff a k-clique exists                     */
+  int64_t nodes;             /* partial cliques the search extended (a
+                                measure; it depends on the schedule)        */
+  int64_t roots;             /* (class 0, class 1) pairs handed out         */
+} kz_clique_result;
+
+int kz_clique_workspace_bytes(const kz_graph *g, int32_t k, size_t *bytes);
+int kz_find_clique(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, const uint8_t *vmask,
+                   void *ws, size_t ws_bytes, int32_t *clique, void *stream, kz_clique_result *res);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,8 @@ EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_
             "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
             "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_set_edge_path",
-            "kz_kernelize_noalloc", "kz_dom_workspace_bytes", "kz_dominance")
+            "kz_kernelize_noalloc", "kz_dom_workspace_bytes", "kz_dominance", "kz_clique_workspace_bytes",
+            "kz_find_clique")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # KZ_NOALLOC_SCRATCH_BYTES
 KZ_EDGE_BITSET, KZ_EDGE_MFMA_I8 = 0, 1
 KZ_EAGAIN = -9
@@ -56,6 +57,13 @@ class kz_dom_result(C.Structure):
 
 
 KZ_DOM_VERTEX, KZ_DOM_EDGE = 0, 1
+
+
+class kz_clique_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("found", C.c_int32), ("nodes", C.c_int64), ("roots", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class kz_request(C.Structure):
@@ -134,6 +142,10 @@ def _load() -> C.CDLL:
     lib.kz_gen_bitset.argtypes = [vp, C.c_int32, vp, C.c_double, C.c_uint32, C.c_uint32, vp, vp, C.c_int32, vp, vp]
     lib.kz_dom_workspace_bytes.restype = C.c_int
     lib.kz_dom_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.kz_clique_workspace_bytes.restype = C.c_int
+    lib.kz_clique_workspace_bytes.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.kz_find_clique.restype = C.c_int
+    lib.kz_find_clique.argtypes = [vp, vp, vp, C.c_int32, vp, vp, C.c_size_t, vp, vp, vp]
     lib.kz_dominance.restype = C.c_int
     lib.kz_dominance.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int32, vp, C.c_size_t, vp, vp, vp,
                                  C.POINTER(kz_dom_result)]
@@ -273,6 +285,22 @@ def kz_dominance(ctx: int, mode: int, n: int, rows: int | None, row_words: int, 
     res = kz_dom_result()
     LIB.kz_dominance(ctx, int(mode), int(n), rows, int(row_words), ws, int(ws_bytes), vmask, emask, stream,
                      C.byref(res))
+    return res
+
+
+def kz_clique_workspace_bytes(graph: "kz_graph", k: int) -> int:
+    need = C.c_size_t(0)
+    st = LIB.kz_clique_workspace_bytes(C.byref(graph), int(k), C.byref(need))
+    if st != KZ_OK:
+        raise KzError(st, "kz_clique_workspace_bytes")
+    return int(need.value)
+
+
+def kz_find_clique(ctx: int, graph: "kz_graph", colour: int | None, k: int, vmask: int | None, ws: int,
+                   ws_bytes: int, clique: int | None, stream: int | None) -> kz_clique_result:
+    """k-clique search (see kz.h); the result's status is the return value."""
+    res = kz_clique_result()
+    LIB.kz_find_clique(ctx, C.byref(graph), colour, int(k), vmask, ws, int(ws_bytes), clique, stream, C.byref(res))
     return res
 
 
@@ -455,6 +483,21 @@ class Kernelizer:
         if check and res.status != KZ_OK:
             raise KzError(res.status, "kz_dominance")
         return vmask[:n], emask[:n], res.as_dict()
+
+
+    def find_clique(self, rows: torch.Tensor, colour: torch.Tensor, k: int, vmask: torch.Tensor | None = None,
+                    stream: torch.cuda.Stream | None = None, check: bool = True):
+        """The lexicographically smallest k-clique of class-major bit rows
+        int64 [n, R] among the live vertices (vmask, or all): (clique int32[k]
+        tensor, all -1 when none, result dict)."""
+        g = graph_bitset(rows)
+        ws = torch.empty(kz_clique_workspace_bytes(g, k), dtype=torch.uint8, device=self.device)
+        clique = torch.empty(max(int(k), 1), dtype=torch.int32, device=self.device)
+        res = kz_find_clique(self.ctx, g, _dev_ptr(colour), k, _dev_ptr(vmask), ws.data_ptr(), ws.numel(),
+                             clique.data_ptr(), _stream_handle(stream, self.device))
+        if check and res.status != KZ_OK:
+            raise KzError(res.status, "kz_find_clique")
+        return clique[:k], res.as_dict()
 
 
 LINE_WORDS, LINE_VERTICES = 16, 128   # a graph's arena ranges start on a 128-byte line

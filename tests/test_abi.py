@@ -26,8 +26,9 @@ def lib():
 
 def test_header_declares_the_entry_points():
     assert declared() == ["kz_batch_autotune", "kz_batch_get_config", "kz_batch_set_config",
-                          "kz_batch_workspace_bytes", "kz_create", "kz_destroy", "kz_dom_workspace_bytes",
-                          "kz_dominance", "kz_gen_bitset",
+                          "kz_batch_workspace_bytes", "kz_clique_workspace_bytes", "kz_create", "kz_destroy",
+                          "kz_dom_workspace_bytes",
+                          "kz_dominance", "kz_find_clique", "kz_gen_bitset",
                           "kz_kernelize", "kz_kernelize_batch", "kz_kernelize_noalloc", "kz_profile_enable",
                           "kz_profile_read",
                           "kz_server_create", "kz_server_destroy", "kz_server_fixed_bytes", "kz_server_poll",
