@@ -23,6 +23,7 @@ namespace {
 constexpr int kClqWaves = 4;        // waves per workgroup
 constexpr int kClqMaxWaves = 2048;  // waves of one launch (stack slots)
 constexpr long long kClqNone = 0x7fffffffffffffffLL;
+constexpr int kClqLdsWords = 1024;  // per-wave LDS stack (k * R words) when it fits
 
 struct ClqHdr {
   long long best;    // smallest root with a clique
@@ -98,11 +99,43 @@ __device__ __forceinline__ long long best_now(const ClqHdr *h) {
 
 // The search.  stack: kClqMaxWaves slots of k * R words; found: per slot the
 // root (int64) and the k picks.
+// Writes the next depth's common neighbourhood over the words [lo, hi) of
+// the classes after the pick (x(w) gives a word) and tells whether every one
+// of those classes keeps a candidate.  The words load together, lanes over
+// words; lane l then watches class c0 + l: whether the ballot of non-zero
+// words has a bit in its word range.
+template <typename F>
+__device__ __forceinline__ bool extend_all(const int *soff, int c0, int k, int lane, uint64_t *out, F x) {
+  const int lo = soff[c0], hi = soff[k];
+  const int c = c0 + lane;
+  const bool mine = c < k;
+  const int cl = mine ? soff[c] : 0, ch = mine ? soff[c + 1] : 0;
+  bool seen = false;
+  for (int w0 = lo; w0 < hi; w0 += kWave) {
+    const int w = w0 + lane;
+    uint64_t v = 0;
+    if (w < hi) {
+      v = x(w);
+      out[w] = v;
+    }
+    const unsigned long long nz = __ballot(v != 0ull);
+    if (mine && !seen && cl < w0 + kWave && ch > w0) {
+      const int a = max(cl, w0) - w0, b = min(ch, w0 + kWave) - w0;
+      const unsigned long long m = (b - a == 64 ? ~0ull : ((1ull << (b - a)) - 1)) << a;
+      seen = (nz & m) != 0ull;
+    }
+  }
+  return __ballot(mine && !seen) == 0ull;
+}
+
+// LDS: the stack lives in LDS when it fits (k * R <= kClqLdsWords per wave).
+template <bool LDS>
 __global__ void __launch_bounds__(kClqWaves * 64) k_clique_search(const uint64_t *__restrict__ rows, int k, int R,
                                                                   const uint64_t *__restrict__ am, ClqHdr *h,
                                                                   uint64_t *__restrict__ stack,
                                                                   long long *__restrict__ found_root,
                                                                   int *__restrict__ found_pick) {
+  __shared__ uint64_t lstack[LDS ? kClqWaves * kClqLdsWords : 1];
   __shared__ int pos[kClqWaves][kBatchK];
   __shared__ int coff_s[kBatchK + 1], soff_s[kBatchK + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -115,7 +148,7 @@ __global__ void __launch_bounds__(kClqWaves * 64) k_clique_search(const uint64_t
   __syncthreads();
   const int *coff = coff_s, *soff = soff_s;
   int *P = pos[wid];
-  uint64_t *cn = stack + (long long)slot * k * R;
+  uint64_t *cn = LDS ? lstack + wid * kClqLdsWords : stack + (long long)slot * k * R;
   const int s0 = coff[1] - coff[0];
   const int s1 = k > 1 ? coff[2] - coff[1] : 1;
   const long long nroots = (long long)s0 * s1;
@@ -152,22 +185,8 @@ __global__ void __launch_bounds__(kClqWaves * 64) k_clique_search(const uint64_t
     const uint64_t *r1 = rows + (long long)v1 * R;
     // depth 2: the common neighbourhood of v0, v1 over classes 2..k-1, each
     // of them non-empty
-    bool ok = true;
     uint64_t *c2 = cn + 2 * (long long)R;
-    for (int c = 2; c < k && ok; ++c) {
-      bool any = false;
-      for (int w0 = soff[c]; w0 < soff[c + 1]; w0 += kWave) {
-        const int w = w0 + lane;
-        uint64_t x = 0;
-        if (w < soff[c + 1]) {
-          x = r0[w] & r1[w] & am[w];
-          c2[w] = x;
-        }
-        any |= __ballot(x != 0ull) != 0ull;
-      }
-      ok = any;
-    }
-    if (!ok) continue;
+    if (k > 2 && !extend_all(soff, 2, k, lane, c2, [&](int w) { return r0[w] & r1[w] & am[w]; })) continue;
     if (k == 2) {
       if (lane == 0) {
         found_root[slot] = r;
@@ -180,8 +199,11 @@ __global__ void __launch_bounds__(kClqWaves * 64) k_clique_search(const uint64_t
     int d = 2;
     if (lane == 0) P[2] = -1;
     bool done = false;
+    int steps = 0;
     while (d >= 2 && !done) {
-      if (best_now(h) < r) break;  // a smaller root already has a clique
+      // a smaller root already has a clique (looked up every 32 steps: the
+      // load goes to memory)
+      if ((++steps & 31) == 0 && best_now(h) < r) break;
       // next candidate of class d after P[d] in the common neighbourhood
       const uint64_t *cd = cn + (long long)d * R;
       const int cs = coff[d], ws0 = soff[d], ws1 = soff[d + 1];
@@ -217,21 +239,7 @@ __global__ void __launch_bounds__(kClqWaves * 64) k_clique_search(const uint64_t
       // extend: the common neighbourhood of the pick over classes d+1..k-1
       const uint64_t *rv = rows + (long long)v * R;
       uint64_t *cnext = cn + (long long)(d + 1) * R;
-      bool ok2 = true;
-      for (int c = d + 1; c < k && ok2; ++c) {
-        bool any = false;
-        for (int w0 = soff[c]; w0 < soff[c + 1]; w0 += kWave) {
-          const int w = w0 + lane;
-          uint64_t x = 0;
-          if (w < soff[c + 1]) {
-            x = cd[w] & rv[w];
-            cnext[w] = x;
-          }
-          any |= __ballot(x != 0ull) != 0ull;
-        }
-        ok2 = any;
-      }
-      if (ok2) {
+      if (extend_all(soff, d + 1, k, lane, cnext, [&](int w) { return cd[w] & rv[w]; })) {
         ++d;
         if (lane == 0) P[d] = -1;
       }
@@ -319,8 +327,12 @@ int kz_find_clique(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_
   hipLaunchKernelGGL(k_clique_setup, dim3(1), dim3(256), 0, s, colour, n, k, R, h);
   hipLaunchKernelGGL(k_clique_alive, dim3((R + 255) / 256 > 0 ? (R + 255) / 256 : 1), dim3(256), 0, s, vmask, k, R,
                      h, am);
-  hipLaunchKernelGGL(k_clique_search, dim3(kClqMaxWaves / kClqWaves), dim3(kClqWaves * 64), 0, s, g->rows, k, R,
-                     am, h, stack, froot, fpick);
+  if ((long long)k * R <= kClqLdsWords)
+    hipLaunchKernelGGL(k_clique_search<true>, dim3(kClqMaxWaves / kClqWaves), dim3(kClqWaves * 64), 0, s, g->rows,
+                       k, R, am, h, stack, froot, fpick);
+  else
+    hipLaunchKernelGGL(k_clique_search<false>, dim3(kClqMaxWaves / kClqWaves), dim3(kClqWaves * 64), 0, s,
+                       g->rows, k, R, am, h, stack, froot, fpick);
   hipLaunchKernelGGL(k_clique_final, dim3((kClqMaxWaves + 255) / 256), dim3(256), 0, s, k, h, froot, fpick,
                      kClqMaxWaves, clique);
   ClqHdr *hh = (ClqHdr *)ctx->pinned;
