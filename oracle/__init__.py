@@ -93,6 +93,8 @@ def _load():
     lib.kzo_dom_vertex.argtypes = [i32, vp, vp, vp]
     lib.kzo_dom_edge.restype = C.c_int
     lib.kzo_dom_edge.argtypes = [i32, vp, vp]
+    lib.kzo_struction.restype = i64
+    lib.kzo_struction.argtypes = [i32, vp, i32, vp, i64, vp]
     lib.kzo_find_clique.restype = C.c_int
     lib.kzo_find_clique.argtypes = [i32, vp, vp, i32, vp, vp, vp]
     _lib = lib
@@ -313,4 +315,22 @@ def find_clique(adj, colour, k, alive=None):
     if f < 0:
         raise MemoryError("oracle: allocation failed")
     return (out[:k].copy() if f else None), int(nodes[0])
+
+
+# ---- struction (section 4.1), kz_oracle_ext.c
+def struction(adj, pivot=0):
+    """G' of Definition 4.1.1 around `pivot` (readings in kz_oracle_ext.c):
+    (adjacency uint8 [n', n'], map int32 [n', 2]: (vertex, -1) for the
+    pivot's neighbours A, (x, y) for the nodes c(x, y) of C)."""
+    a = np.ascontiguousarray(adj, dtype=np.uint8)
+    n = a.shape[0]
+    lib = _load()
+    npr = int(lib.kzo_struction(n, _ptr(a), int(pivot), None, 0, None))
+    if npr < 0:
+        raise ValueError("pivot outside the graph")
+    out = np.zeros((max(npr, 1), max(npr, 1)), np.uint8)
+    mp = np.zeros((max(npr, 1), 2), np.int32)
+    got = int(lib.kzo_struction(n, _ptr(a), int(pivot), _ptr(out), npr, _ptr(mp)))
+    assert got == npr
+    return out[:npr, :npr].copy(), mp[:npr].copy()
 

@@ -179,3 +179,72 @@ int kzo_find_clique(int32_t n, const uint8_t *adj, const int32_t *colour, int32_
   free(pick);
   return found;
 }
+
+/*
+ * Struction (thesis section 4.1, Definition 4.1.1, Lemmas 1-2, Theorem 1).
+ * Pivot p; A = the neighbours of p, B = the other vertices except p, both
+ * in increasing order.  C holds a node c(x, y) for every edge {x, y} of G
+ * inside B with x < y.  G' has the nodes A (in order) followed by C (ordered
+ * by x, then y):
+ *   a, a' in A are adjacent iff {a, a'} is an edge of G;
+ *   c(x, y), c(x', y') in C are adjacent iff x = x' and {y, y'} is an edge
+ *     of G (the thesis's "ordered pair {bY, bM}" is read as this edge);
+ *   a in A and c(x, y) in C are adjacent iff a is adjacent to both x and y
+ *     (the thesis gives no rule for these pairs; this one makes both lemmas
+ *     hold: the C nodes of a clique of G' share their first vertex x, and
+ *     x with their second vertices and the clique's A nodes is a clique of G
+ *     one larger; a clique of G that avoids p maps back through its smallest
+ *     B vertex).
+ * So omega(G') = omega(G) - 1 (Theorem 1).
+ *   adj: n*n bytes; out: n'*n' bytes (capacity cap nodes; call with out =
+ *   NULL to get n' only); map: int32[n'][2] = (vertex, -1) for A nodes and
+ *   (x, y) for C nodes.  Returns n', or -1 when cap is too small.
+ */
+int64_t kzo_struction(int32_t n, const uint8_t *adj, int32_t pivot, uint8_t *out, int64_t cap, int32_t *map) {
+  if (pivot < 0 || pivot >= n) return -1;
+  int64_t na = 0, nc = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    if (v == pivot) continue;
+    if (adj[(int64_t)pivot * n + v]) ++na;
+  }
+  for (int32_t x = 0; x < n; ++x) {
+    if (x == pivot || adj[(int64_t)pivot * n + x]) continue;
+    for (int32_t y = x + 1; y < n; ++y)
+      if (y != pivot && !adj[(int64_t)pivot * n + y] && adj[(int64_t)x * n + y]) ++nc;
+  }
+  const int64_t np = na + nc;
+  if (!out) return np;
+  if (np > cap) return -1;
+  int64_t i = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    if (v != pivot && adj[(int64_t)pivot * n + v]) {
+      map[2 * i] = v;
+      map[2 * i + 1] = -1;
+      ++i;
+    }
+  }
+  for (int32_t x = 0; x < n; ++x) {
+    if (x == pivot || adj[(int64_t)pivot * n + x]) continue;
+    for (int32_t y = x + 1; y < n; ++y) {
+      if (y != pivot && !adj[(int64_t)pivot * n + y] && adj[(int64_t)x * n + y]) {
+        map[2 * i] = x;
+        map[2 * i + 1] = y;
+        ++i;
+      }
+    }
+  }
+  for (int64_t s = 0; s < np; ++s) {
+    for (int64_t t = 0; t < np; ++t) {
+      uint8_t e = 0;
+      if (s != t) {
+        const int32_t xs = map[2 * s], ys = map[2 * s + 1], xt = map[2 * t], yt = map[2 * t + 1];
+        if (ys < 0 && yt < 0) e = adj[(int64_t)xs * n + xt];
+        else if (ys >= 0 && yt >= 0) e = xs == xt && adj[(int64_t)ys * n + yt];
+        else if (ys < 0) e = adj[(int64_t)xs * n + xt] && adj[(int64_t)xs * n + yt];
+        else e = adj[(int64_t)xt * n + xs] && adj[(int64_t)xt * n + ys];
+      }
+      out[s * np + t] = e;
+    }
+  }
+  return np;
+}

@@ -265,3 +265,34 @@ def test_clique_search_complete_multipartite_and_live_mask():
     alive[3] = 0                                                 # class 1 emptied
     assert find_clique(a, colour, 4, alive)[0] is None
     assert find_clique(a, colour, 1)[0].tolist() == [0]
+
+
+# ---------------------------------------------------------------- struction
+from oracle import struction  # noqa: E402
+
+
+def test_struction_hand_example():
+    # pivot 0: A = {1}; B = {2, 3, 4} with edges 23, 24, 34 -> C = c(2,3),
+    # c(2,4), c(3,4); 1 ~ c(2,3) (1 ~ 2 and 1 ~ 3); c(2,3) ~ c(2,4) (same
+    # first vertex, 3 ~ 4); omega: 3 in G ({1,2,3}, {2,3,4}), 2 in G'
+    g = graph(5, [(0, 1), (1, 2), (2, 3), (3, 4), (2, 4), (1, 3)])
+    out, mp = struction(g, 0)
+    assert mp.tolist() == [[1, -1], [2, 3], [2, 4], [3, 4]]
+    assert edges_of(out) == {(0, 1), (1, 2)}
+    assert omega(g) == 3 and omega(out) == 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_struction_lowers_the_clique_number_by_one(seed):
+    rng = np.random.default_rng(500 + seed)
+    for _ in range(40):
+        n = int(rng.integers(1, 9))
+        g = random_graph(rng, n, float(rng.uniform(0.1, 0.95)))
+        p = int(rng.integers(0, n))
+        out, mp = struction(g, p)
+        A = [v for v in range(n) if g[p, v]]
+        B = [v for v in range(n) if v != p and not g[p, v]]
+        inner = [(x, y) for x in B for y in B if x < y and g[x, y]]
+        assert mp.tolist() == [[a, -1] for a in A] + [list(e) for e in inner]
+        assert (out == out.T).all() and not out.diagonal().any()
+        assert omega(out) == omega(g) - 1          # Theorem 1

@@ -71,6 +71,15 @@ EXT_MUTANTS = {
     "clique_descending_order": (
         "  for (int32_t v = 0; v < n; ++v) {\n    if (colour[v] != c",
         "  for (int32_t v = n - 1; v >= 0; --v) {\n    if (colour[v] != c"),
+    "struction_ac_rule_one_endpoint": (
+        "        else if (ys < 0) e = adj[(int64_t)xs * n + xt] && adj[(int64_t)xs * n + yt];",
+        "        else if (ys < 0) e = adj[(int64_t)xs * n + xt];"),
+    "struction_cc_rule_any_first_vertex": (
+        "        else if (ys >= 0 && yt >= 0) e = xs == xt && adj[(int64_t)ys * n + yt];",
+        "        else if (ys >= 0 && yt >= 0) e = adj[(int64_t)ys * n + yt];"),
+    "struction_counts_pairs_reaching_into_a": (
+        "      if (y != pivot && !adj[(int64_t)pivot * n + y] && adj[(int64_t)x * n + y]) ++nc;",
+        "      if (y != pivot && adj[(int64_t)x * n + y]) ++nc;"),
     "dom_edge_single_sweep": ("    if (!any) break;\n    ++sweeps;\n  }\n  stats[0] = sweeps;\n  stats[1] = de;",
                               "    break;\n  }\n  stats[0] = sweeps;\n  stats[1] = de;"),
 }
