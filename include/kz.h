@@ -439,6 +439,43 @@ int kz_clique_workspace_bytes(const kz_graph *g, int32_t k, size_t *bytes);
 int kz_find_clique(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, const uint8_t *vmask,
                    void *ws, size_t ws_bytes, int32_t *clique, void *stream, kz_clique_result *res);
 
+/* ------------------------------------------------------------ struction
+ * Struction (thesis section 4.1, Definition 4.1.1, Theorem 1): a graph G'
+ * whose clique number is one less than G's.  Around the pivot p: A = the
+ * neighbours of p, B = the other vertices except p, and a node c(x, y) for
+ * every edge {x, y} of G inside B with x < y.  G' has the nodes A (in vertex
+ * order) followed by the nodes c(x, y) (ordered by x, then y):
+ *   a ~ a'           iff {a, a'} is an edge of G;
+ *   c(x,y) ~ c(x',y') iff x = x' and {y, y'} is an edge of G;
+ *   a ~ c(x, y)      iff a ~ x and a ~ y (the thesis states no rule for
+ *                    these pairs; this one makes its Lemmas 1 and 2 hold).
+ *   rows: device uint64[n * row_words], plain bit rows (bit w % 64 of word
+ *         w / 64 of row v: {v, w} is an edge), row_words >= ceil(n / 64),
+ *         symmetric, no self-loop, no bit at or beyond n (else KZ_EASYM /
+ *         KZ_ESELFLOOP / KZ_EINVAL); n >= 1, 0 <= pivot < n;
+ *   ws, ws_bytes: device workspace of kz_struction_workspace_bytes() bytes,
+ *         256-byte aligned;
+ *   out == NULL: plan only -- res gets the node counts and the row words
+ *         G' needs (ceil(n' / 64));
+ *   out: device uint64[out_nodes * out_row_words], G' in the same bit-row
+ *         layout; map: device int32[out_nodes * 2], per node (v, -1) for
+ *         A nodes and (x, y) for C nodes; KZ_EWORKSPACE when out_nodes or
+ *         out_row_words is too small for G'.
+ * Blocking (two small readbacks). */
+typedef struct kz_struction_result {
+  int32_t status;
+  int32_t row_words;         /* ceil(nodes / 64)                            */
+  int64_t nodes;             /* n' = a_nodes + c_nodes                      */
+  int64_t a_nodes;           /* the pivot's degree                          */
+  int64_t c_nodes;           /* edges inside B                              */
+  int64_t input_edges;       /* undirected                                  */
+} kz_struction_result;
+
+int kz_struction_workspace_bytes(int32_t n, int32_t row_words, size_t *bytes);
+int kz_struction(kz_ctx *ctx, int32_t n, const uint64_t *rows, int32_t row_words, int32_t pivot, void *ws,
+                 size_t ws_bytes, uint64_t *out, int32_t out_row_words, int64_t out_nodes, int32_t *map,
+                 void *stream, kz_struction_result *res);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
             "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_set_edge_path",
             "kz_kernelize_noalloc", "kz_dom_workspace_bytes", "kz_dominance", "kz_clique_workspace_bytes",
-            "kz_find_clique")
+            "kz_find_clique", "kz_struction_workspace_bytes", "kz_struction")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # KZ_NOALLOC_SCRATCH_BYTES
 KZ_EDGE_BITSET, KZ_EDGE_MFMA_I8 = 0, 1
 KZ_EAGAIN = -9
@@ -57,6 +57,14 @@ class kz_dom_result(C.Structure):
 
 
 KZ_DOM_VERTEX, KZ_DOM_EDGE = 0, 1
+
+
+class kz_struction_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("row_words", C.c_int32), ("nodes", C.c_int64), ("a_nodes", C.c_int64),
+                ("c_nodes", C.c_int64), ("input_edges", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class kz_clique_result(C.Structure):
@@ -142,6 +150,11 @@ def _load() -> C.CDLL:
     lib.kz_gen_bitset.argtypes = [vp, C.c_int32, vp, C.c_double, C.c_uint32, C.c_uint32, vp, vp, C.c_int32, vp, vp]
     lib.kz_dom_workspace_bytes.restype = C.c_int
     lib.kz_dom_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.kz_struction_workspace_bytes.restype = C.c_int
+    lib.kz_struction_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.kz_struction.restype = C.c_int
+    lib.kz_struction.argtypes = [vp, C.c_int32, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp, C.c_int32, C.c_int64,
+                                 vp, vp, C.POINTER(kz_struction_result)]
     lib.kz_clique_workspace_bytes.restype = C.c_int
     lib.kz_clique_workspace_bytes.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
     lib.kz_find_clique.restype = C.c_int
@@ -301,6 +314,24 @@ def kz_find_clique(ctx: int, graph: "kz_graph", colour: int | None, k: int, vmas
     """k-clique search (see kz.h); the result's status is the return value."""
     res = kz_clique_result()
     LIB.kz_find_clique(ctx, C.byref(graph), colour, int(k), vmask, ws, int(ws_bytes), clique, stream, C.byref(res))
+    return res
+
+
+def kz_struction_workspace_bytes(n: int, row_words: int) -> int:
+    need = C.c_size_t(0)
+    st = LIB.kz_struction_workspace_bytes(int(n), int(row_words), C.byref(need))
+    if st != KZ_OK:
+        raise KzError(st, "kz_struction_workspace_bytes")
+    return int(need.value)
+
+
+def kz_struction(ctx: int, n: int, rows: int | None, row_words: int, pivot: int, ws: int, ws_bytes: int,
+                 out: int | None, out_row_words: int, out_nodes: int, map_: int | None,
+                 stream: int | None) -> kz_struction_result:
+    """Struction (see kz.h); out = None plans only.  The result's status is the return value."""
+    res = kz_struction_result()
+    LIB.kz_struction(ctx, int(n), rows, int(row_words), int(pivot), ws, int(ws_bytes), out, int(out_row_words),
+                     int(out_nodes), map_, stream, C.byref(res))
     return res
 
 
@@ -498,6 +529,28 @@ class Kernelizer:
         if check and res.status != KZ_OK:
             raise KzError(res.status, "kz_find_clique")
         return clique[:k], res.as_dict()
+
+
+    def struction(self, rows: torch.Tensor, pivot: int = 0, stream: torch.cuda.Stream | None = None,
+                  check: bool = True):
+        """G' of Definition 4.1.1 around `pivot` for plain bit rows int64 [n, R]:
+        (rows int64 [n', ceil(n'/64)], map int32 [n', 2], result dict)."""
+        n, R = int(rows.shape[0]), int(rows.shape[1])
+        ws = torch.empty(kz_struction_workspace_bytes(n, R), dtype=torch.uint8, device=self.device)
+        sh = _stream_handle(stream, self.device)
+        res = kz_struction(self.ctx, n, _dev_ptr(rows), R, pivot, ws.data_ptr(), ws.numel(), None, 0, 0, None, sh)
+        if res.status != KZ_OK:
+            if check:
+                raise KzError(res.status, "kz_struction")
+            return None, None, res.as_dict()
+        npr, rp = int(res.nodes), max(int(res.row_words), 1)
+        out = torch.empty((max(npr, 1), rp), dtype=torch.int64, device=self.device)
+        mp = torch.empty((max(npr, 1), 2), dtype=torch.int32, device=self.device)
+        res = kz_struction(self.ctx, n, _dev_ptr(rows), R, pivot, ws.data_ptr(), ws.numel(), out.data_ptr(), rp, npr,
+                           mp.data_ptr(), sh)
+        if check and res.status != KZ_OK:
+            raise KzError(res.status, "kz_struction")
+        return out[:npr], mp[:npr], res.as_dict()
 
 
 LINE_WORDS, LINE_VERTICES = 16, 128   # a graph's arena ranges start on a 128-byte line

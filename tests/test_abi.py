@@ -33,7 +33,8 @@ def test_header_declares_the_entry_points():
                           "kz_profile_read",
                           "kz_server_create", "kz_server_destroy", "kz_server_fixed_bytes", "kz_server_poll",
                           "kz_server_progress", "kz_server_request_bytes", "kz_server_submit",
-                          "kz_set_edge_path", "kz_strerror", "kz_workspace_bytes"]
+                          "kz_set_edge_path", "kz_strerror", "kz_struction", "kz_struction_workspace_bytes",
+                          "kz_workspace_bytes"]
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -79,3 +80,21 @@ def test_struct_layouts_match_the_header():
     assert C.sizeof(b.kz_graph) == 56
     assert C.sizeof(b.kz_batch_config) == 20
     assert C.sizeof(b.kz_request) == 48
+
+
+def test_binding_argument_counts_match_header():
+    """Every binding declares as many ctypes arguments as kz.h gives the C
+    function parameters (a mismatch would only show at call time)."""
+    import re as _re
+
+    from paper_2212_00574_amd import binding
+    text = open(os.path.join(ROOT, "include", "kz.h")).read()
+    text = _re.sub(r"/\*.*?\*/", " ", text, flags=_re.S)
+    for name in declared():
+        m = _re.search(r"\b%s\s*\(([^)]*)\)\s*;" % name, text)
+        assert m, name
+        params = [p for p in m.group(1).split(",") if p.strip() and p.strip() != "void"]
+        fn = getattr(binding.LIB, name)
+        if fn.argtypes is None:
+            continue
+        assert len(fn.argtypes) == len(params), (name, len(fn.argtypes), len(params))
