@@ -58,6 +58,8 @@ WORKLOADS = {
     "dom": "dominance reductions (section 4.3), vertex and edge mode, on the thesis's ten evaluation sizes "
            "n = 100, 300, ..., 1900 with n(n-5)/2 edges (path plus skewed edges), plain bit rows",
     "clique": "k-clique search on the 4096 batching graphs (config 4), on each input graph and on its kernel",
+    "struction": "struction (section 4.1) of a random graph of 1000 vertices at p = 0.1 around vertex 0 "
+                 "(G' about 40 000 nodes), plain bit rows",
 }
 DOM_SIZES = list(range(100, 2000, 200))
 DOM_CPU_EDGE_SIZES = (100, 300, 500, 700, 900)   # edge-mode oracle sample: about 14 s on one core
@@ -847,6 +849,56 @@ def run_clique(args):
     return out
 
 
+# --------------------------------------------------------------- struction
+def run_struction(args):
+    """Struction (section 4.1) of one random graph: plan + build time (median
+    of three after a warm-up), the output's bytes over that time against the
+    HBM peak, parity with the oracle's G' (every word), and the oracle's time."""
+    import torch
+
+    from oracle import struction
+    from paper_2212_00574_amd import inputs
+    from paper_2212_00574_amd.binding import Kernelizer
+    kz = Kernelizer(0)
+    rng = np.random.default_rng(np.random.SeedSequence([args.seed, 0x5354]))
+    n, p = 1000, 0.1
+    a = (rng.random((n, n)) < p).astype(np.uint8)
+    a = np.triu(a, 1)
+    adj = a + a.T
+    rows = torch.from_numpy(inputs.dense_to_rows(adj).view(np.int64)).to(kz.device)
+    kz.struction(rows, 0)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        out, mp, res = kz.struction(rows, 0)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms = float(np.median(times))
+    out_bytes = float(out.numel() * 8 + mp.numel() * 4)
+    t0 = time.perf_counter()
+    ref, rmap = struction(adj, 0)
+    cpu_s = time.perf_counter() - t0
+    equal = (np.array_equal(mp.cpu().numpy(), rmap)
+             and np.array_equal(out.cpu().numpy().view(np.uint64), inputs.dense_to_rows(ref)))
+    gbps = out_bytes / (ms / 1e3) / 1e9
+    result = {"metric": "struction build time", "value": round(ms, 4), "unit": "ms", "higher_is_better": False,
+              "config": {"workload": "struction: " + WORKLOADS["struction"], "n": n, "p": p, "pivot": 0,
+                         "nodes": res["nodes"], "a_nodes": res["a_nodes"], "c_nodes": res["c_nodes"],
+                         "seed": args.seed},
+              "roofline": {"kernel": "k_st_rows (with plan, map and compression)", "bound": "hbm",
+                           "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                           "bytes": "G' rows and node map written (n' * ceil(n'/64) * 8 + 8 n')",
+                           "note": "whole blocking call (two readbacks) over the output bytes"},
+              "oracle_equal": bool(equal),
+              "cpu_baseline": {"value": round(cpu_s * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": "the whole graph (dense n' x n' bytes), one core", "host": host_info()}}
+    say("struction: n' = %d, %.3f ms (%.1f GB/s), oracle %.2f s, equal %s" % (res["nodes"], ms, gbps, cpu_s, equal))
+    kz.close()
+    return result
+
+
 # --------------------------------------------------------------- dominance
 def run_dom(args, cpu_proc=None):
     """Dominance reductions (section 4.3) on the ten evaluation graphs, both
@@ -957,6 +1009,8 @@ def main():
         out = run_dom(args, dom_proc)
     elif w == "clique":
         out = run_clique(args)
+    elif w == "struction":
+        out = run_struction(args)
     else:
         out = run_single(args, w, cpu_proc)
         if args.workload == "headline":
@@ -964,6 +1018,7 @@ def main():
             out["serve"] = run_serve(args)
             out["dominance"] = run_dom(args, dom_proc)
             out["clique"] = run_clique(args)
+            out["struction"] = run_struction(args)
     out.setdefault("n_gpus", 1)
     print(json.dumps(out), flush=True)
 
