@@ -27,7 +27,12 @@ something other than itself):
   (masks, rounds, survivors, exact-worklist counts, validation statuses) on
   seeded graphs of every shape the tests use, and by the same closed forms:
   Figure 8's hand-derived fixpoint, the k=3 kernel = union of triangles,
-  complete multipartite graphs and the index-inequality family.
+  complete multipartite graphs and the index-inequality family.  With a
+  clique size below the number of classes (``clique``): the clique-3 kernel
+  of an m-coloured graph is the union of its triangles, the clique-2 kernel
+  drops only isolated vertices, complete m-partite graphs keep everything,
+  every vertex and edge of every clique-sized clique survives (brute force),
+  kernels shrink as the clique size grows, and a hand case.
 * ``witness_words`` (a measurement, not a result: the words a first-witness
   search reads over every (edge, third class) pair of the input) -- pinned
   by a pure-Python count on small graphs and by closed forms (complete
@@ -87,6 +92,8 @@ def _load():
     lib.kzo_failing.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp]
     lib.kzo_fixpoint_rows.restype = C.c_int
     lib.kzo_fixpoint_rows.argtypes = [i32, i32, vp, vp, i32, vp, vp, vp]
+    lib.kzo_fixpoint_rows_mk.restype = C.c_int
+    lib.kzo_fixpoint_rows_mk.argtypes = [i32, i32, i32, vp, vp, i32, vp, vp, vp]
     lib.kzo_witness_words.restype = i64
     lib.kzo_witness_words.argtypes = [i32, i32, vp, vp, i32, C.POINTER(i64), C.POINTER(i64)]
     lib.kzo_dom_vertex.restype = C.c_int
@@ -236,10 +243,11 @@ def kernelize_csr(row_ptr, col_idx, colour, k) -> dict:
     return _guard(lambda: OracleGraph(FMT_CSR, n, k, colour, row_ptr=row_ptr, col_idx=col_idx))
 
 
-def fixpoint_rows(rows, colour, k) -> dict:
+def fixpoint_rows(rows, colour, k, clique=None) -> dict:
     """O3 on class-major bit rows (the BITSET format): same result and
     counts as O1.  Returns the dict of ``kernelize_bitset`` (emask as uint64
-    rows)."""
+    rows).  ``clique`` (default k) is the clique size when the k colour
+    classes outnumber it: thresholds clique-1 and clique-2."""
     rows = np.ascontiguousarray(rows, dtype=np.uint64)
     colour = np.ascontiguousarray(colour, dtype=np.int32)
     n = int(colour.size)
@@ -249,8 +257,9 @@ def fixpoint_rows(rows, colour, k) -> dict:
     vmask = np.zeros(n, np.uint8)
     emask = np.zeros((n, R), np.uint64)
     stats = np.zeros(5, np.int64)
-    st = _load().kzo_fixpoint_rows(n, int(k), _ptr(colour), _ptr(rows) if rows.size else None, R,
-                                   _ptr(vmask), _ptr(emask) if emask.size else None, _ptr(stats))
+    kk = int(k) if clique is None else int(clique)
+    st = _load().kzo_fixpoint_rows_mk(n, int(k), kk, _ptr(colour), _ptr(rows) if rows.size else None, R,
+                                      _ptr(vmask), _ptr(emask) if emask.size else None, _ptr(stats))
     if st:
         return dict(status=int(st))
     return dict(status=0, rounds=int(stats[0]), equals_input=int(stats[1]), surv_vertices=int(stats[2]),

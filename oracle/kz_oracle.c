@@ -661,9 +661,16 @@ void kzo_failing(void *h, const int32_t *vs, int64_t nv, uint8_t *vfail,
  * every edge of a failed vertex are cleared (both directions). */
 #define O3_BIT(row, w) (((row)[(w) >> 6] >> ((w) & 63)) & 1ull)
 
-int kzo_fixpoint_rows(int32_t n, int32_t k, const int32_t *col, const uint64_t *rows, int32_t row_words,
-                      uint8_t *vmask, uint64_t *emask, int64_t *stats) {
-  if (n < 0 || k < 1 || row_words < 0 || (n > 0 && (!col || !rows || !vmask || !emask))) return ST_EINVAL;
+/* More colours than the clique size (kk <= k classes): a k-clique still
+ * uses kk distinct classes, so the same argument gives thresholds kk-1 and
+ * kk-2: a vertex fails when more than k - kk other classes hold no
+ * neighbour, an edge when more than k - kk third classes hold no common
+ * neighbour.  kk = k is the rule above. */
+static int o3_run(int32_t n, int32_t k, int32_t kk, const int32_t *col, const uint64_t *rows, int32_t row_words,
+                  uint8_t *vmask, uint64_t *emask, int64_t *stats) {
+  if (n < 0 || k < 1 || kk < 1 || kk > k || row_words < 0 || (n > 0 && (!col || !rows || !vmask || !emask)))
+    return ST_EINVAL;
+  const int32_t slack = k - kk;  /* classes a test may find without a witness */
   for (int32_t v = 0; v < n; ++v)
     if (col[v] < 0 || col[v] >= k) return ST_ECOLOUR;
   for (int32_t v = 1; v < n; ++v)
@@ -726,12 +733,14 @@ int kzo_fixpoint_rows(int32_t n, int32_t k, const int32_t *col, const uint64_t *
       fv[v] = 0;
       if (!vmask[v]) continue;
       const uint64_t *rv = A + (int64_t)v * R;
-      for (int32_t c = 0; c < k && !fv[v]; ++c) {
+      int32_t miss = 0;
+      for (int32_t c = 0; c < k && miss <= slack; ++c) {
         if (c == col[v]) continue;
         int has = 0;
         for (int64_t w = seg[c]; w < seg[c + 1] && !has; ++w) has = rv[w] != 0;
-        if (!has) fv[v] = 1;
+        if (!has) ++miss;
       }
+      fv[v] = miss > slack;
       any |= fv[v];
     }
     /* edge tests on the snapshot: every alive edge u < v */
@@ -746,16 +755,16 @@ int kzo_fixpoint_rows(int32_t n, int32_t k, const int32_t *col, const uint64_t *
           x &= x - 1;
           int32_t cv = wcls[w];
           int64_t v = first[cv] + 64 * (w - seg[cv]) + j;
-          if (v <= u || k < 3) continue;
+          if (v <= u || kk < 3) continue;
           const uint64_t *rv = A + v * R;
-          int fails = 0;
-          for (int32_t c = 0; c < k && !fails; ++c) {
+          int32_t miss = 0;
+          for (int32_t c = 0; c < k && miss <= slack; ++c) {
             if (c == col[u] || c == cv) continue;
             int common = 0;
             for (int64_t t = seg[c]; t < seg[c + 1] && !common; ++t) common = (ru[t] & rv[t]) != 0;
-            if (!common) fails = 1;
+            if (!common) ++miss;
           }
-          if (fails) { fu[w] |= 1ull << j; any = 1; }
+          if (miss > slack) { fu[w] |= 1ull << j; any = 1; }
         }
       }
     }
@@ -819,6 +828,18 @@ int kzo_fixpoint_rows(int32_t n, int32_t k, const int32_t *col, const uint64_t *
   memcpy(stats, out, sizeof out);
   free(first); free(seg); free(wcls); free(Fe); free(fv); free(touched);
   return ST_OK;
+}
+
+int kzo_fixpoint_rows(int32_t n, int32_t k, const int32_t *col, const uint64_t *rows, int32_t row_words,
+                      uint8_t *vmask, uint64_t *emask, int64_t *stats) {
+  return o3_run(n, k, k, col, rows, row_words, vmask, emask, stats);
+}
+
+/* k classes, cliques of size kk <= k (section 4.2's indices with thresholds
+ * kk-1 and kk-2 on a graph coloured with more colours than the clique size). */
+int kzo_fixpoint_rows_mk(int32_t n, int32_t k, int32_t kk, const int32_t *col, const uint64_t *rows,
+                         int32_t row_words, uint8_t *vmask, uint64_t *emask, int64_t *stats) {
+  return o3_run(n, k, kk, col, rows, row_words, vmask, emask, stats);
 }
 
 /* ------------------------------------------------- witness-search work */

@@ -642,3 +642,88 @@ def test_witness_words_closed_forms():
     outer = len(edges_of(adj2)) - inner    # edges with an endpoint in class 3
     assert r["pairs"] == inner * 2 + outer * 2
     assert r["words"] == inner * (1 + 2) + outer * 2 and r["no_witness"] == 0
+
+
+# ------------------------------------ more colours than the clique size (O3)
+def test_o3_more_colours_hand_case():
+    # classes 0..3; a triangle on classes 0, 1, 2 and a class-3 vertex joined
+    # to two triangle vertices: with clique size 3 the triangle survives and
+    # the class-3 vertex (two neighbour classes, no common neighbour for its
+    # edges) goes with its edges; with clique size 4 (= classes) nothing has
+    # a neighbour in every other class
+    adj = dense_from_edges(4, [(0, 1), (1, 2), (0, 2), (3, 0), (3, 1)])
+    colour = np.array([0, 1, 2, 3], np.int32)
+    rows, col, order, lay = to_rows(adj, colour, 4)
+    r3 = fixpoint_rows(rows, col, 4, clique=3)
+    got = inputs.unpack_rows(r3["emask"], lay).astype(np.uint8)
+    # the edges {3,0} and {3,1} have the common neighbour 1 / 0 in a third
+    # class, so they pass too: the whole graph is made of triangles
+    assert edges_of(got) == edges_of(adj) and r3["vmask"].all() and r3["rounds"] == 0
+    r4 = fixpoint_rows(rows, col, 4, clique=4)
+    assert r4["surv_edges"] == 0 and r4["surv_vertices"] == 0
+    adj2 = dense_from_edges(4, [(0, 1), (1, 2), (0, 2), (3, 0)])
+    rows2, col2, _, lay2 = to_rows(adj2, colour, 4)
+    r = fixpoint_rows(rows2, col2, 4, clique=3)
+    assert set(edges_of(inputs.unpack_rows(r["emask"], lay2).astype(np.uint8))) == {(0, 1), (1, 2), (0, 2)}
+    assert r["vmask"].tolist() == [1, 1, 1, 0] and r["rounds"] == 1
+
+
+def m_coloured(rng, m, s, p):
+    sizes = rng.integers(1, s + 1, size=m)
+    colour = np.repeat(np.arange(m), sizes).astype(np.int32)
+    n = colour.size
+    a = (rng.random((n, n)) < p).astype(np.uint8)
+    a = np.triu(a, 1)
+    a = a + a.T
+    a[colour[:, None] == colour[None, :]] = 0
+    return a, colour
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_o3_clique3_on_more_colours_is_union_of_triangles(seed):
+    rng = np.random.default_rng(40 + seed)
+    for _ in range(10):
+        m = int(rng.integers(3, 7))
+        adj, colour = m_coloured(rng, m, 4, float(rng.uniform(0.2, 0.7)))
+        rows, col, order, lay = to_rows(adj, colour, m)
+        r = fixpoint_rows(rows, col, m, clique=3)
+        slot = adj[np.ix_(order, order)]
+        n = slot.shape[0]
+        tri = np.zeros_like(slot)
+        for a, b, c in itertools.combinations(range(n), 3):
+            if slot[a, b] and slot[b, c] and slot[a, c]:
+                for x, y in ((a, b), (b, c), (a, c)):
+                    tri[x, y] = tri[y, x] = 1
+        assert np.array_equal(inputs.unpack_rows(r["emask"], lay).astype(np.uint8), tri)
+        assert np.array_equal(r["vmask"], tri.any(axis=1).astype(np.uint8))
+        # clique size 2: only isolated vertices go, every edge stays
+        r2 = fixpoint_rows(rows, col, m, clique=2)
+        assert np.array_equal(inputs.unpack_rows(r2["emask"], lay).astype(np.uint8), slot)
+        assert np.array_equal(r2["vmask"], slot.any(axis=1).astype(np.uint8))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_o3_more_colours_soundness_and_monotonicity(seed):
+    rng = np.random.default_rng(60 + seed)
+    for _ in range(8):
+        m = int(rng.integers(3, 7))
+        adj, colour = m_coloured(rng, m, 3, float(rng.uniform(0.4, 0.9)))
+        rows, col, order, lay = to_rows(adj, colour, m)
+        slot = adj[np.ix_(order, order)]
+        prev = None
+        for kk in range(1, m + 1):
+            r = fixpoint_rows(rows, col, m, clique=kk)
+            got = inputs.unpack_rows(r["emask"], lay)
+            # every vertex and edge of every kk-clique survives (brute force)
+            for cl in itertools.combinations(range(slot.shape[0]), kk):
+                if len({int(col[v]) for v in cl}) == kk and all(slot[x, y] for x, y in itertools.combinations(cl, 2)):
+                    assert all(r["vmask"][v] for v in cl)
+                    assert all(got[x, y] for x, y in itertools.combinations(cl, 2))
+            if prev is not None:        # a larger clique size prunes at least as much
+                assert not (r["vmask"] & ~prev[0]).any() and not (got & ~prev[1]).any()
+            prev = (r["vmask"], got)
+        # a complete m-partite graph keeps everything for every clique size
+        full = (colour[:, None] != colour[None, :]).astype(np.uint8)
+        rf, cf, _, _ = to_rows(full, colour, m)
+        for kk in range(1, m + 1):
+            assert fixpoint_rows(rf, cf, m, clique=kk)["rounds"] == 0

@@ -31,10 +31,15 @@ MUTANTS = {
     "o3_edge_test_skips_only_one_endpoint_class": (
         "            if (c == col[u] || c == cv) continue;", "            if (c == col[u]) continue;"),
     "o3_failed_edge_cleared_during_the_scan": (
-        "          if (fails) { fu[w] |= 1ull << j; any = 1; }",
-        "          if (fails) { fu[w] |= 1ull << j; any = 1; ((uint64_t *)ru)[w] &= ~(1ull << j); }"),
+        "          if (miss > slack) { fu[w] |= 1ull << j; any = 1; }",
+        "          if (miss > slack) { fu[w] |= 1ull << j; any = 1; ((uint64_t *)ru)[w] &= ~(1ull << j); }"),
     "o3_vertex_test_skips_the_last_class": (
-        "      for (int32_t c = 0; c < k && !fv[v]; ++c) {", "      for (int32_t c = 0; c < k - 1 && !fv[v]; ++c) {"),
+        "      for (int32_t c = 0; c < k && miss <= slack; ++c) {\n        if (c == col[v]) continue;",
+        "      for (int32_t c = 0; c < k - 1 && miss <= slack; ++c) {\n        if (c == col[v]) continue;"),
+    "o3_vertex_slack_ignored": ("      fv[v] = miss > slack;", "      fv[v] = miss > 0;"),
+    "o3_edge_slack_off_by_one": (
+        "          if (miss > slack) { fu[w] |= 1ull << j; any = 1; }",
+        "          if (miss >= slack && miss) { fu[w] |= 1ull << j; any = 1; }"),
     "o3_rounds_count_the_confirming_pass": ("{rounds, rounds == 0,", "{rounds + 1, rounds == 0,"),
     "set_masks_accepts_one_way_edges": (
         "    if (g->ea[e] != g->ea[g->mate[e]]) return -1;\n", ""),
