@@ -206,8 +206,15 @@ int kz_set_edge_path(kz_ctx *ctx, int32_t path);
  * asynchronous: it enqueues the work on the stream and returns; results[g]
  * (device memory) is valid in stream order.  It performs no host
  * synchronisation, so a caller may capture it in a hipGraph and replay it. */
+/* clique: the clique size when it is below the number of colour classes k
+ * (1 <= clique < k; 0 or k: the clique size is k).  A k'-clique of a graph
+ * legally coloured with k colours uses k' distinct classes, so section
+ * 4.2's argument gives thresholds k'-1 and k'-2: a vertex fails when more
+ * than k - k' other classes hold no neighbour, an edge when more than k - k'
+ * third classes hold no common neighbour.  Outside [0, k]: KZ_EINVAL in the
+ * graph's result. */
 typedef struct kz_batch_graph {
-  int32_t n, k, row_words, reserved;
+  int32_t n, k, row_words, clique;
   int64_t row_offset;     /* in uint64 words */
   int64_t vertex_offset;  /* in vertices */
 } kz_batch_graph;
@@ -273,7 +280,11 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
 typedef struct kz_server kz_server;
 
 typedef struct kz_request {
-  int32_t n, k, row_words, reserved;
+  int32_t n, k, row_words, clique;  /* clique: as in kz_batch_graph (0 = k);
+                                       a request with clique in [1, k) is
+                                       served by the batched lane, so it must
+                                       fit that lane's limits (KZ_EINVAL
+                                       otherwise) */
   const uint64_t *rows;   /* device, n*row_words words (layout of KZ_BITSET_U64) */
   const int32_t *colour;  /* device, n colours sorted class by class            */
   uint8_t *vmask;         /* device output, n bytes                             */

@@ -75,7 +75,7 @@ class kz_clique_result(C.Structure):
 
 
 class kz_request(C.Structure):
-    _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("row_words", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("row_words", C.c_int32), ("clique", C.c_int32),
                 ("rows", C.c_void_p), ("colour", C.c_void_p), ("vmask", C.c_void_p), ("emask", C.c_void_p)]
 
 
@@ -90,7 +90,7 @@ class kz_batch_config(C.Structure):
 # numpy layouts of kz_batch_graph and kz_result (device arrays are filled from / read into these)
 import numpy as np  # noqa: E402
 
-BATCH_GRAPH_DTYPE = np.dtype([("n", "<i4"), ("k", "<i4"), ("row_words", "<i4"), ("reserved", "<i4"),
+BATCH_GRAPH_DTYPE = np.dtype([("n", "<i4"), ("k", "<i4"), ("row_words", "<i4"), ("clique", "<i4"),
                               ("row_offset", "<i8"), ("vertex_offset", "<i8")])
 RESULT_DTYPE = np.dtype([("status", "<i4"), ("rounds", "<i4"), ("equals_input", "<i4"), ("passes", "<i4"),
                          ("surviving_vertices", "<i8"), ("surviving_edges", "<i8"), ("input_edges", "<i8"),
@@ -563,8 +563,10 @@ def _line_up(x: int, q: int) -> int:
 class Batch:
     """Arenas, descriptors and results of one batch of bit-row graphs on a device.
 
-    ``graphs`` is a list of (rows uint64 [n, R], colour int32 [n], k).  Each
-    graph's ranges start on a 128-byte line (kz_kernelize_batch requires it).
+    ``graphs`` is a list of (rows uint64 [n, R], colour int32 [n], k) or
+    (rows, colour, k, clique) -- clique: the clique size when it is below the
+    number of colour classes k (0 = k).  Each graph's ranges start on a
+    128-byte line (kz_kernelize_batch requires it).
     """
 
     def __init__(self, graphs, device):
@@ -572,16 +574,19 @@ class Batch:
         G = len(graphs)
         desc = np.zeros(G, BATCH_GRAPH_DTYPE)
         ro, vo = 0, 0
-        for i, (rows, colour, k) in enumerate(graphs):
+        for i, gr in enumerate(graphs):
+            rows, colour, k = gr[:3]
+            clique = int(gr[3]) if len(gr) > 3 else 0
             n, R = (rows.shape[0], rows.shape[1]) if rows.ndim == 2 else (len(colour), 0)
-            desc[i] = (n, k, R, 0, ro, vo)
+            desc[i] = (n, k, R, clique, ro, vo)
             ro = _line_up(ro + n * R, LINE_WORDS)
             vo = _line_up(vo + n, LINE_VERTICES)
         self.G = G
         self.desc = desc
         rows_all = np.zeros(max(ro, 1), np.uint64)
         col_all = np.zeros(max(vo, 1), np.int32)
-        for i, (rows, colour, k) in enumerate(graphs):
+        for i, gr in enumerate(graphs):
+            rows, colour = gr[0], gr[1]
             n, R = int(desc[i]["n"]), int(desc[i]["row_words"])
             a, b = int(desc[i]["row_offset"]), int(desc[i]["vertex_offset"])
             rows_all[a:a + n * R] = np.asarray(rows, np.uint64).reshape(-1)
@@ -679,13 +684,14 @@ class Server:
 
     @staticmethod
     def request(rows: torch.Tensor, colour: torch.Tensor, k: int, vmask: torch.Tensor,
-                emask: torch.Tensor) -> kz_request:
+                emask: torch.Tensor, clique: int = 0) -> kz_request:
         n = int(colour.numel())
         R = int(rows.shape[1]) if rows.dim() == 2 else (int(rows.numel()) // n if n else 0)
-        return kz_request(n, int(k), R, 0, _dev_ptr(rows), _dev_ptr(colour), _dev_ptr(vmask), _dev_ptr(emask))
+        return kz_request(n, int(k), R, int(clique), _dev_ptr(rows), _dev_ptr(colour), _dev_ptr(vmask),
+                          _dev_ptr(emask))
 
-    def submit(self, rows, colour, k, vmask, emask) -> int | None:
-        t = kz_server_submit(self.srv, self.request(rows, colour, k, vmask, emask))
+    def submit(self, rows, colour, k, vmask, emask, clique: int = 0) -> int | None:
+        t = kz_server_submit(self.srv, self.request(rows, colour, k, vmask, emask, clique))
         if t is not None:
             self.keep[t] = (rows, colour, vmask, emask)
         return t

@@ -131,6 +131,7 @@ struct BatchLds {
 
 struct GView {
   int g, n, k, R;
+  int slack;  // classes a test may find without a witness: k - clique size
   const uint64_t *rows;
   uint64_t *cur, *nxt;
   const int *colour;
@@ -146,6 +147,7 @@ __device__ __forceinline__ GView gview(const BatchArgs &a, int g) {
   v.n = G.n;
   v.k = G.k;
   v.R = G.row_words;
+  v.slack = G.clique > 0 && G.clique < G.k ? G.k - G.clique : 0;
   const long long T = (long long)v.R * (v.R - 1) / 2;
   if (a.ptrs) {
     const BatchPtrs P = a.ptrs[g];
@@ -180,14 +182,14 @@ __device__ void vertex_chunk(const GView &V, BatchLds &S, int v0, bool first, in
   if (!__ballot(act)) return;
   const uint64_t *row = src + (long long)(act ? v : v0) * R;
   const int cv = act ? V.colour[v] : -1;
-  bool fail = false;
+  int miss = 0;  // other classes without a neighbour
   int pr = 0;
   for (int c = 0; c < k; ++c) {
     const int w0 = S.soff[c], w1 = S.soff[c + 1];
     const int s = S.coff[c + 1] - S.coff[c];
     if (!act) continue;
     if (w1 == w0) {
-      fail |= c != cv;
+      miss += c != cv;
       continue;
     }
     if (first && (s & 63) && (row[w1 - 1] >> (s & 63))) pr = max(pr, P_EINVAL);
@@ -211,10 +213,10 @@ __device__ void vertex_chunk(const GView &V, BatchLds &S, int v0, bool first, in
     }
     bool nz = false;
     for (int w = w0; w < w1 && !nz; ++w) nz = row[w] != 0;
-    fail |= !nz;
+    miss += !nz;
   }
   if (pr) atomicMax(&S.prio, pr);
-  fail = fail && act;
+  const bool fail = act && miss > V.slack;
   if (act) {
     if (first) V.valive[v] = fail ? 0 : 1;
     else if (fail) V.valive[v] = 0;
@@ -242,7 +244,33 @@ __device__ void tile(const GView &V, BatchLds &S, int X, int Y, bool first, int 
   const unsigned long long TU = first ? ~0ull : __ballot(lane < xl && tbit(S.tc, xs + lane));
   const unsigned long long TV = first ? ~0ull : __ballot(lane < yl && tbit(S.tc, ys + lane));
   unsigned long long myP = Eu;  // P of the row this lane stands for
-  const int nthird = V.k - 2;
+  const int nthird = V.slack > 0 ? 0 : V.k - 2;
+  if (V.slack > 0) {
+    // more classes than the clique size: an edge fails when more than slack
+    // third classes hold no common neighbour; lane v counts its misses
+    for (int u = 0; u < xl; ++u) {
+      unsigned long long P = bcast64(myP, u);
+      const unsigned long long Pt = P & (((TU >> u) & 1ull) ? ~0ull : TV);
+      if (!Pt) continue;
+      const uint64_t *rowu = src + (long long)(xs + u) * R;
+      const bool tested = (Pt >> lane) & 1ull;
+      int miss = 0;
+      for (int c = 0; c < V.k; ++c) {
+        if (c == cx || c == cy) continue;
+        bool wit = false;
+        for (int w = S.soff[c]; w < S.soff[c + 1]; ++w) {
+          const uint64_t xu = rowu[w];
+          if (!xu) continue;
+          const uint64_t yv = tested && !wit ? rowv[w] : 0ull;
+          wit |= (xu & yv) != 0ull;
+          if (!(Pt & ~__ballot(wit))) break;  // every tested lane has its witness
+        }
+        miss += !wit;
+      }
+      P &= ~(Pt & __ballot(tested && miss > V.slack));
+      if (lane == u) myP = P;
+    }
+  }
   for (int q = 0; q < nthird; q += CH) {
     // stage the first two words of each third-class segment: row u's in LDS
     // (read as broadcasts), row v's in registers
@@ -501,7 +529,9 @@ __device__ bool start_job(const BatchArgs &a, BatchLds &S, int g) {
   const kz_batch_graph G = a.graphs[g];
   const int n = G.n, k = G.k, R = G.row_words;
   int st = 0;
-  if (n < 0 || k < 1 || R < 0 || (!a.ptrs && (G.row_offset < 0 || G.vertex_offset < 0))) st = KZ_EINVAL;
+  if (n < 0 || k < 1 || R < 0 || G.clique < 0 || G.clique > k ||
+      (!a.ptrs && (G.row_offset < 0 || G.vertex_offset < 0)))
+    st = KZ_EINVAL;
   else if (k > kBatchK || R > kBatchR || n > kBatchN) st = kBatchTooLarge;
   if (st != 0 || n == 0) {
     if (tid == 0) {

@@ -228,7 +228,7 @@ int launch(kz_server *s, Record &rec) {
     g.n = q.r.n;
     g.k = q.r.k;
     g.row_words = q.r.row_words;
-    g.reserved = 0;
+    g.clique = q.r.clique;
     g.row_offset = 0;
     g.vertex_offset = 0;
     kzi::BatchPtrs &p = rec.ptrs_host[i];
@@ -376,7 +376,11 @@ int kz_server_submit(kz_server *s, const kz_request *req, uint64_t *ticket) {
     return KZ_EINVAL;
   // the batch lane's outputs must not share a 128-byte line with other data
   if ((uintptr_t)r.vmask % 128 || (uintptr_t)r.emask % 128) return KZ_EINVAL;
-  const bool big = r.n >= kSplitN || r.k > kzi::kBatchK || r.row_words > kzi::kBatchR;
+  if (r.clique < 0 || r.clique > r.k) return KZ_EINVAL;
+  const bool fits_batch = r.k <= kzi::kBatchK && r.row_words <= kzi::kBatchR && r.n <= kzi::kBatchN;
+  const bool below = r.clique > 0 && r.clique < r.k;  // only the batched lane takes a smaller clique size
+  if (below && !fits_batch) return KZ_EINVAL;
+  const bool big = !below && (r.n >= kSplitN || !fits_batch);
   size_t bytes = batch_bytes(r);
   if (big && single_bytes(s->wctx[0], r, &bytes) != KZ_OK) return KZ_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
