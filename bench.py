@@ -37,6 +37,11 @@ import time
 
 import numpy as np
 
+# The serving workload runs the session lane, six single-graph workers and
+# the caller's stream at once: give each stream a hardware queue of its own
+# (HIP reads this when it starts, before any GPU call).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -63,6 +68,10 @@ WORKLOADS = {
     "struction": "struction (section 4.1) of a random graph of 1000 vertices at p = 0.1 around vertex 0 "
                  "(G' about 40 000 nodes), plain bit rows",
 }
+SERVE_SPLIT_N = 2048       # c5 lane split (vertices)
+SERVE_IDLE_US = 20000
+SERVE_RESIDENT_GIB = 8.0
+SERVE_WORKERS = 6          # c5: single-graph lane workers
 DOM_SIZES = list(range(100, 2000, 200))
 DOM_CPU_EDGE_SIZES = (100, 300, 500, 700, 900)   # edge-mode oracle sample: about 14 s on one core
 
@@ -82,6 +91,15 @@ def parse(argv=None):
     ap.add_argument("--edge-path", default="bitset", choices=("bitset", "mfma"),
                     help="edge test of the single-graph path: witness search on bit rows, or int8 MFMA counts")
     ap.add_argument("--requests", type=int, default=50000, help="c5: requests of the stream (a prefix)")
+    ap.add_argument("--split-n", type=int, default=SERVE_SPLIT_N,
+                    help="c5: requests of at least this many vertices take the single-graph lane")
+    ap.add_argument("--idle-us", type=int, default=SERVE_IDLE_US, help="c5: a session launch ends after this idle time")
+    ap.add_argument("--session-cus", type=int, default=0, help="c5: compute units of a session launch (0: 3/16)")
+    ap.add_argument("--lease-us", type=int, default=0, help="c5: session workgroup lease (0: the server's 50 ms)")
+    ap.add_argument("--workers", type=int, default=SERVE_WORKERS,
+                    help="c5: single-graph lane workers (requests of that lane in flight at once)")
+    ap.add_argument("--resident-gib", type=float, default=SERVE_RESIDENT_GIB,
+                    help="c5: admission limit on the admitted requests' rows, colours and masks")
     ap.add_argument("--copy-calibration", type=int, default=None, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (memory-counter calibration)")
     return ap.parse_args(argv)
@@ -659,7 +677,12 @@ def run_serve(args):
     N = args.requests
     specs = inputs.config5_specs(args.seed, requests=N)
     kz = Kernelizer(0)
-    srv = Server(kz, arena_bytes=16 << 30, max_slots=512)
+    # inputs are generated and fenced on a stream of the server's own, not
+    # on the legacy null stream
+    srv = Server(kz, arena_bytes=16 << 30, max_slots=512, stream=torch.cuda.Stream(kz.device))
+    resident = int(args.resident_gib * (1 << 30))
+    srv.configure(split_n=args.split_n, idle_us=args.idle_us, resident_limit=resident,
+                  session_cus=args.session_cus, lease_us=args.lease_us, workers=args.workers)
     fx = golden("c5_seed%d.json" % args.seed)
     check_ids = set(fx["buckets"][0]["ids"]) if fx is not None and N == 50000 else set()
     digests = {}
@@ -683,26 +706,27 @@ def run_serve(args):
                     break
                 tickets[t] = i
                 waiting.pop(0)
-            srv.progress()
-            for t in list(tickets):
-                r = srv.poll(t)
-                if r is None:
-                    continue
+            for t, r in srv.done(1024):
                 i = tickets.pop(t)
                 res[i] = r
                 lat[i] = time.perf_counter() - t0 - (arrivals[i] if arrivals is not None else 0.0)
                 if arrivals is None and i in check_ids:
+                    # complete once reported done; no device-wide wait (it
+                    # would also wait for the running session launch to end)
                     _, _, vm, em = st.live[i]
-                    torch.cuda.synchronize()
                     digests[i] = digest(vm.cpu().numpy(), em.cpu().numpy(), r)
                 st.live.pop(i, None)
                 done += 1
+                if done % 5000 == 0:
+                    say("c5: %d of %d requests done, %.1f s" % (done, N, time.perf_counter() - t0))
             if time.perf_counter() - t0 > 400:
                 raise RuntimeError("serving run did not finish")
         return res, lat, time.perf_counter() - t0
 
     N_all = N
     N = min(64, N_all)
+    say("c5: warm-up on %d requests (split_n %d, idle %d us, resident limit %.1f GiB, %d workers)"
+        % (N, args.split_n, args.idle_us, args.resident_gib, args.workers))
     run(None)                                   # warm-up on the first requests
     N = N_all
     res, _, closed_s = run(None)
@@ -749,6 +773,11 @@ def run_serve(args):
     return {"metric": "served requests/s (closed loop)", "value": S, "unit": "requests/s", "requests": N,
             "ms_per_request": closed_s * 1e3 / N,
             "config": {"workload": "c5: " + WORKLOADS["c5"], "requests": N, "seed": args.seed,
+                       "split_n": args.split_n, "idle_us": args.idle_us, "resident_limit_bytes": resident,
+                       "session_cus": args.session_cus or "3/16 of the device", "lease_us": args.lease_us or 50000,
+                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
+                       "workers": args.workers,
+                       "max_slots": 512,
                        "edge_tests": float(tests.sum()), "max_rounds": int(max(r["rounds"] for r in res))},
             "latency": phases, "edge_tests_per_s": float(tests.sum()) / closed_s,
             "one_by_one": one, "served_over_one_by_one": None if one is None else S / one["value"],

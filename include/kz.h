@@ -260,23 +260,39 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
 
 /* ------------------------------------------------------------ serving
  * A server admits requests one at a time and runs them with continuous
- * batching: each launch of the batched path (the job runtime above) takes
- * every admitted request that is waiting, and at most two launches are in
- * flight on the server's stream (one running, one queued behind it).
- * Requests of 4096 vertices or more (or beyond the batched path's k and
- * row-word limits) take a second lane instead: two worker threads, each
- * with a stream of its own, run them through the single-graph path, one
- * request each at a time, overlapping the batch launches.  A request is a
- * KZ_BITSET_U64 graph in caller-owned device buffers (vmask and emask
- * 128-byte aligned, else KZ_EINVAL); results are the same as kz_kernelize on
- * the graph alone.  The server takes a fixed part of a
- * caller-provided device arena for its launch records and carves each
- * admitted request's scratch from the rest (first fit); it admits a request
- * only when a slot and its scratch are free, else KZ_EAGAIN.  It allocates
- * no device memory of its own; when it is created it allocates pinned host
- * memory for descriptors and results, and per worker a context, a stream
- * and a thread.  A server belongs to one host thread (the worker is
- * internal). */
+ * batching in two lanes that share the device.
+ *
+ * Session lane: requests go, once the inputs written on the server's stream
+ * before their submission are complete, into a ring in pinned host memory
+ * that a running launch of the batched path's job runtime (the persistent
+ * workgroups above) reads while it runs: a workgroup that frees up takes the
+ * next request, so a new request never waits for a whole batch to end.  A
+ * launch has session_cus workgroups of 16 waves (each fills a compute unit's
+ * registers, so the other units stay free for the other lane); a workgroup
+ * takes no new request once lease_us has passed since it started, and
+ * leaves once idle, so under load a launch ends about every lease_us and
+ * the server starts the next when requests wait.
+ *
+ * Single-graph lane: requests of split_n vertices or more (default 2048),
+ * or beyond the batched path's k and row-word limits, go to worker threads
+ * (six by default), each with a stream of its own, that run them through
+ * the single-graph path one request each at a time, beside the session
+ * lane.  The process then has workers + 2 streams of its own besides the
+ * caller's; with fewer hardware queues than streams (HIP's
+ * GPU_MAX_HW_QUEUES, 4 by default) streams share queues, and a short
+ * kernel can wait behind a long one of another lane.
+ *
+ * A request is a KZ_BITSET_U64 graph in caller-owned device buffers (vmask
+ * and emask 128-byte aligned, else KZ_EINVAL); results are the same as
+ * kz_kernelize on the graph alone.  The server takes a fixed part of a
+ * caller-provided device arena for the runtime's state and carves each
+ * admitted request's scratch from the rest (first fit).  It admits a request
+ * only when a slot, its scratch and (when a limit is set) its resident bytes
+ * fit, else KZ_EAGAIN.  It allocates no device memory of its own; when it is
+ * created it allocates pinned host memory for the ring and the per-slot
+ * descriptors and results, a stream for session launches, and per worker a
+ * context, a stream and a thread.  A server belongs to one host thread (the
+ * workers are internal). */
 typedef struct kz_server kz_server;
 
 typedef struct kz_request {
@@ -293,8 +309,9 @@ typedef struct kz_request {
                              unchanged until the request is done               */
 } kz_request;
 
-/* Fixed arena bytes of a server with max_slots slots (1..4096); the arena
- * must be larger by the scratch of the requests it is to hold at once. */
+/* Fixed arena bytes of a server with max_slots slots (1..4096): the
+ * session runtime's counters, board and per-slot job states; the arena must
+ * be larger by the scratch of the requests it is to hold at once. */
 size_t kz_server_fixed_bytes(int32_t max_slots);
 
 /* Arena bytes an admitted request holds until it is done: in the batch
@@ -306,20 +323,54 @@ size_t kz_server_request_bytes(const kz_server *srv, const kz_request *req);
 /* Creates a server on ctx's device.  arena: device memory, 256-byte aligned,
  * arena_bytes > kz_server_fixed_bytes(max_slots), owned by the caller and
  * not touched by it until kz_server_destroy returns.  stream: the stream all
- * work is ordered on (NULL = the null stream); inputs a caller writes on this
- * stream before kz_server_submit are ordered before the request's launch. */
+ * inputs are written on (NULL = the null stream): what a caller writes on
+ * it before kz_server_submit is complete before the request runs. */
 int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_slots, void *stream,
                      kz_server **out);
 
-/* Admits a request: KZ_OK and *ticket, KZ_EAGAIN (no slot or scratch now:
- * retry after kz_server_poll has retired finished requests), or KZ_EINVAL
- * (bad arguments). */
+typedef struct kz_server_config {
+  int32_t split_n;        /* requests with at least this many vertices take the
+                             single-graph lane (0 = 2048); a value above 32768
+                             keeps every request the batched path takes in
+                             the session lane                                */
+  int32_t idle_us;        /* a session launch ends after this long without
+                             work, in microseconds (0 = 20000; at most 1e6)  */
+  int32_t lease_us;       /* a session workgroup takes no new request this
+                             long after it started (0 = 50000; at most 1e6)  */
+  int32_t session_cus;    /* compute units a session launch fills, up to the
+                             device's (0 = 3/16 of them)                     */
+  int32_t workers;        /* single-graph lane: requests in flight at once,
+                             each with a worker thread, context and stream
+                             of its own (0 = 6; at most 8)                   */
+  int32_t partition;      /* 1: the session lane's stream is masked to
+                             session_cus compute units and the other lane's
+                             streams to the rest, so neither lane waits for
+                             the other's workgroups to leave a unit (masked
+                             streams are blocking streams: pass the server a
+                             stream other than the legacy null stream);
+                             0: both lanes may use every unit               */
+  size_t resident_limit;  /* admit while the admitted, unfinished requests'
+                             rows, colours and masks (2*8*n*row_words + 5*n
+                             bytes each) total at most this; 0 = no limit    */
+} kz_server_config;
+
+/* Sets the configuration; only while no request is admitted (KZ_EAGAIN
+ * otherwise).  KZ_EINVAL for negative fields, times above 1e6 or more
+ * compute units than the device has. */
+int kz_server_configure(kz_server *srv, const kz_server_config *cfg);
+
+/* Admits a request: KZ_OK and *ticket, KZ_EAGAIN (no slot, scratch or
+ * resident budget now: retry after kz_server_poll has retired finished
+ * requests), or KZ_EINVAL (bad arguments, or a request whose resident bytes
+ * alone exceed the limit). */
 int kz_server_submit(kz_server *srv, const kz_request *req, uint64_t *ticket);
 
-/* Retires finished launches (freeing their scratch) and launches waiting
- * requests when a launch slot is free.  Returns the number of admitted
- * requests not yet retired by kz_server_poll (a request holds its slot
- * until then), or a negative status. */
+/* Collects finished requests (freeing their scratch, slot and resident
+ * bytes), publishes requests whose inputs are complete and starts a session
+ * launch when published requests wait.  Returns the number of admitted
+ * requests not yet retired by kz_server_poll, or a negative status.  Call
+ * it (or kz_server_poll) while requests are outstanding: the server has no
+ * thread of its own for this. */
 int kz_server_progress(kz_server *srv);
 
 /* 1: the request is done; *res (if not NULL) receives its result and the
@@ -327,7 +378,16 @@ int kz_server_progress(kz_server *srv);
  * kz_server_progress first. */
 int kz_server_poll(kz_server *srv, uint64_t ticket, kz_result *res);
 
-/* Waits for the launches in flight and releases the server. */
+/* Retires up to max finished requests, oldest completion first: their
+ * tickets go to tickets[0..), their results (if res is not NULL) to
+ * res[0..).  Calls kz_server_progress first.  Returns the number retired
+ * (0 when none has finished), or a negative status.  One call replaces a
+ * kz_server_poll per outstanding ticket. */
+int kz_server_done(kz_server *srv, uint64_t *tickets, kz_result *res, int32_t max);
+
+/* Waits for the requests in flight (a session launch ends once idle) and
+ * releases the server; requests whose inputs were not yet complete are
+ * dropped. */
 void kz_server_destroy(kz_server *srv);
 
 /* ------------------------------------------------------------ measurement

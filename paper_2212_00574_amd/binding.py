@@ -22,7 +22,7 @@ EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_
             "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
             "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
-            "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_set_edge_path",
+            "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_server_configure", "kz_server_done", "kz_set_edge_path",
             "kz_kernelize_noalloc", "kz_dom_workspace_bytes", "kz_dominance", "kz_clique_workspace_bytes",
             "kz_find_clique", "kz_struction_workspace_bytes", "kz_struction")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # KZ_NOALLOC_SCRATCH_BYTES
@@ -77,6 +77,11 @@ class kz_clique_result(C.Structure):
 class kz_request(C.Structure):
     _fields_ = [("n", C.c_int32), ("k", C.c_int32), ("row_words", C.c_int32), ("clique", C.c_int32),
                 ("rows", C.c_void_p), ("colour", C.c_void_p), ("vmask", C.c_void_p), ("emask", C.c_void_p)]
+
+
+class kz_server_config(C.Structure):
+    _fields_ = [("split_n", C.c_int32), ("idle_us", C.c_int32), ("lease_us", C.c_int32), ("session_cus", C.c_int32),
+                ("workers", C.c_int32), ("partition", C.c_int32), ("resident_limit", C.c_size_t)]
 
 
 class kz_batch_config(C.Structure):
@@ -144,6 +149,10 @@ def _load() -> C.CDLL:
     lib.kz_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(kz_result)]
     lib.kz_server_destroy.restype = None
     lib.kz_server_destroy.argtypes = [vp]
+    lib.kz_server_done.restype = C.c_int
+    lib.kz_server_done.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(kz_result), C.c_int32]
+    lib.kz_server_configure.restype = C.c_int
+    lib.kz_server_configure.argtypes = [vp, C.POINTER(kz_server_config)]
     lib.kz_set_edge_path.restype = C.c_int
     lib.kz_set_edge_path.argtypes = [vp, C.c_int32]
     lib.kz_gen_bitset.restype = C.c_int
@@ -380,6 +389,26 @@ def kz_server_poll(srv: int, ticket: int) -> dict | None:
 
 def kz_server_destroy(srv: int) -> None:
     LIB.kz_server_destroy(srv)
+
+
+def kz_server_done(srv: int, max_count: int = 256) -> list[tuple[int, dict]]:
+    """Finished requests, oldest completion first: (ticket, result) pairs
+    (retired)."""
+    tickets = (C.c_uint64 * max_count)()
+    res = (kz_result * max_count)()
+    st = LIB.kz_server_done(srv, tickets, res, int(max_count))
+    if st < 0:
+        raise KzError(st, "kz_server_done")
+    return [(int(tickets[i]), res[i].as_dict()) for i in range(st)]
+
+
+def kz_server_configure(srv: int, split_n: int = 0, idle_us: int = 0, resident_limit: int = 0, lease_us: int = 0,
+                        session_cus: int = 0, workers: int = 0, partition: int = 0) -> None:
+    cfg = kz_server_config(int(split_n), int(idle_us), int(lease_us), int(session_cus), int(workers),
+                           int(partition), int(resident_limit))
+    st = LIB.kz_server_configure(srv, C.byref(cfg))
+    if st != 0:
+        raise KzError(st, "kz_server_configure")
 
 
 # ----------------------------------------------------------- tensor helpers
@@ -696,8 +725,22 @@ class Server:
             self.keep[t] = (rows, colour, vmask, emask)
         return t
 
+    def configure(self, split_n: int = 0, idle_us: int = 0, resident_limit: int = 0, lease_us: int = 0,
+                  session_cus: int = 0, workers: int = 0, partition: int = 0) -> None:
+        """Lane split, session idle time and lease, session compute units,
+        single-graph workers, compute-unit partition and resident-byte limit
+        (0: defaults / no limit); only while no request is admitted."""
+        kz_server_configure(self.srv, split_n, idle_us, resident_limit, lease_us, session_cus, workers, partition)
+
     def progress(self) -> int:
         return kz_server_progress(self.srv)
+
+    def done(self, max_count: int = 256) -> list[tuple[int, dict]]:
+        """Finished requests since the last call (retired), oldest first."""
+        out = kz_server_done(self.srv, max_count)
+        for t, _ in out:
+            self.keep.pop(t, None)
+        return out
 
     def poll(self, ticket: int) -> dict | None:
         r = kz_server_poll(self.srv, ticket)

@@ -55,6 +55,7 @@ constexpr int kVertexItem = 1 << 30;                 // item = kVertexItem | chu
 constexpr int kVChunk = 128;                         // vertices of a vertex item: one line of the vertex mask
 constexpr int kYShift = 9, kXMask = (1 << kYShift) - 1;
 constexpr unsigned long long kIdleTicks = 2000000;   // 20 ms of the 100 MHz wall clock
+constexpr unsigned long long kHostPoll = 200;        // 2 us: session mode's look at the host's count
 // Claim word: pass (24 bits) | items (20 bits) | next unclaimed item (20 bits).
 constexpr int kItemBits = 20;
 constexpr unsigned kItemMask = (1u << kItemBits) - 1;
@@ -106,6 +107,16 @@ __device__ __forceinline__ void release_agent() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __builtin_amdgcn_s_waitcnt(0);
 }
+// Release to the host (system scope), with its wait, for results that the
+// host reads from pinned memory.
+__device__ __forceinline__ void release_system() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  __builtin_amdgcn_s_waitcnt(0);
+}
+__device__ __forceinline__ void acquire_system() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+  __builtin_amdgcn_s_waitcnt(0);
+}
 __device__ __forceinline__ void acquire_agent() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __builtin_amdgcn_s_waitcnt(0);
@@ -122,11 +133,13 @@ struct BatchLds {
   unsigned tc[kBatchN / 32], tn[kBatchN / 32];    // vertices touched in the previous / this pass
   unsigned btc[kBatchR / 32], btn[kBatchR / 32];  // blocks touched in the previous / this pass
   int job, pass;       // the job and pass the copies above belong to
+  int pass0;           // the job's first pass
   int shared;          // the pass is shared
   int got, base, cnt, nitems, next_item, last, reload;
   int prio, nchanged;  // this run (solo: this pass)
   unsigned long long removed_v, removed_e, tests;
   int gi, queue_empty, bad_colour, bad_layout, pick, quit, end, status;
+  unsigned long long ticket;  // session mode: the ticket of the job being started
 };
 
 struct GView {
@@ -140,8 +153,14 @@ struct GView {
   BatchJob *J;
 };
 
+// A job's descriptor: the batch's, or in session mode the copy its starter
+// made of the host slot.
+__device__ __forceinline__ kz_batch_graph job_desc(const BatchArgs &a, int g) {
+  return a.session ? a.jobs[g].sdesc : a.graphs[g];
+}
+
 __device__ __forceinline__ GView gview(const BatchArgs &a, int g) {
-  const kz_batch_graph G = a.graphs[g];
+  const kz_batch_graph G = job_desc(a, g);
   GView v;
   v.g = g;
   v.n = G.n;
@@ -149,8 +168,8 @@ __device__ __forceinline__ GView gview(const BatchArgs &a, int g) {
   v.R = G.row_words;
   v.slack = G.clique > 0 && G.clique < G.k ? G.k - G.clique : 0;
   const long long T = (long long)v.R * (v.R - 1) / 2;
-  if (a.ptrs) {
-    const BatchPtrs P = a.ptrs[g];
+  if (a.ptrs || a.session) {
+    const BatchPtrs P = a.session ? a.jobs[g].sptrs : a.ptrs[g];
     v.rows = P.rows;
     v.cur = P.emask;
     v.nxt = P.next;
@@ -380,7 +399,7 @@ template <int NW, int CH>
 __device__ void run_items(const GView &V, BatchLds &S, unsigned long long (*sU)[CH][kBlk],
                           unsigned long long (*sU2)[CH][kBlk]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const bool first = S.pass == 1;
+  const bool first = S.pass == S.pass0;
   const int cnt = S.cnt, base = S.base;
   for (;;) {
     int i = 0;
@@ -400,6 +419,13 @@ __device__ void run_items(const GView &V, BatchLds &S, unsigned long long (*sU)[
 }
 
 __device__ void write_result(const BatchArgs &a, int g, const kz_result &r) {
+  if (a.session) {
+    // the outputs and the result reach memory before the done flag
+    a.hres[g] = r;
+    release_system();
+    __hip_atomic_store(&a.hdone[g], a.jobs[g].ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
   a.results[g] = r;
   atomicAdd(a.finished, 1);
 }
@@ -437,7 +463,13 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int n = V.n, R = V.R, p = S.pass;
   const int nw = (n + 31) >> 5, nbw = (R + 31) >> 5;
-  if (tid == 0) S.nitems = 0;
+  if (tid == 0) {
+    S.nitems = 0;
+    // every pass number this job uses, the final empty one included: the
+    // workgroup that ends the job keeps it in S.pass, and the slot's next
+    // job must number its passes above it
+    ast(&V.J->lastpass, p);
+  }
   __syncthreads();
   // vertex chunks (128 vertices, four touched words) holding a touched vertex
   const int nvc = (n + kVChunk - 1) / kVChunk;
@@ -473,14 +505,15 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
   __syncthreads();
   const int ni = S.nitems;
   if (ni == 0) {
-    if (tid == 0) end_job(a, V, p);
+    if (tid == 0) end_job(a, V, p - S.pass0 + 1);
     __syncthreads();
     return false;
   }
   if (tid == 0) {
     bool shared = a.share == 1;
     if (a.share == 0 && ni > NW)
-      shared = ni >= kShareBig || __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.G;
+      shared = ni >= kShareBig ||
+               (a.session ? ald(a.squeue) >= ald(a.dhead) : ald(a.queue) >= a.G);
     S.shared = shared;
     S.base = 0;
     S.cnt = shared ? min(ni, NW) : ni;
@@ -515,7 +548,7 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
                                     ((unsigned long long)ni << kItemBits) | (unsigned long long)S.cnt;
       release_agent();
       __hip_atomic_exchange(&J->claim, cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.board[V.g & (kBatchBoard - 1)], V.g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.board[V.g & a.board_mask], V.g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   return true;
@@ -526,11 +559,20 @@ __device__ bool open_pass(const BatchArgs &a, const GView &V, BatchLds &S) {
 template <int NW>
 __device__ bool start_job(const BatchArgs &a, BatchLds &S, int g) {
   const int tid = threadIdx.x;
-  const kz_batch_graph G = a.graphs[g];
+  if (a.session) {
+    if (tid == 0) {
+      BatchJob *J = a.jobs + g;
+      J->sdesc = a.hgraphs[g];
+      J->sptrs = a.hptrs[g];
+      J->ticket = S.ticket;
+    }
+    __syncthreads();
+  }
+  const kz_batch_graph G = job_desc(a, g);
   const int n = G.n, k = G.k, R = G.row_words;
   int st = 0;
   if (n < 0 || k < 1 || R < 0 || G.clique < 0 || G.clique > k ||
-      (!a.ptrs && (G.row_offset < 0 || G.vertex_offset < 0)))
+      (!a.ptrs && !a.session && (G.row_offset < 0 || G.vertex_offset < 0)))
     st = KZ_EINVAL;
   else if (k > kBatchK || R > kBatchR || n > kBatchN) st = kBatchTooLarge;
   if (st != 0 || n == 0) {
@@ -625,8 +667,19 @@ __device__ bool start_job(const BatchArgs &a, BatchLds &S, int g) {
     ast(&J->tot_removed_e, 0ll);
     ast(&J->tot_tests, 0ll);
     ast(&J->m, 0ll);
+    int p0 = 1;
+    if (a.session) {
+      // above every pass number a workgroup may still hold for this slot
+      // (after the wrap, numbers from over 2^23 passes ago: a launch ends
+      // within its lease, and with it every copy in LDS, long before that)
+      p0 = ald(&J->lastpass) + 1;
+      if (p0 >= (1 << 23)) p0 = 1;
+    }
+    ast(&J->pass0, p0);
+    ast(&J->lastpass, p0);
     S.job = g;
-    S.pass = 1;
+    S.pass = p0;
+    S.pass0 = p0;
     S.prio = 0;
     S.removed_v = 0;
     S.removed_e = 0;
@@ -671,7 +724,10 @@ __device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
     if (got) {
       if (!(S.job == g && S.pass == cp)) {
         acquire_agent();  // the pass was listed by another workgroup
-        S.reload = S.job != g ? 2 : 1;
+        // a new job in the slot has another first pass: its layout differs
+        const int p0 = ald(&J->pass0);
+        S.reload = S.job != g || S.pass0 != p0 ? 2 : 1;
+        S.pass0 = p0;
         S.job = g;
         S.pass = cp;
         S.shared = 1;
@@ -682,7 +738,7 @@ __device__ void claim(const BatchArgs &a, BatchLds &S, int g) {
   }
   __syncthreads();
   if (S.got && S.reload) {
-    const kz_batch_graph G = a.graphs[g];
+    const kz_batch_graph G = job_desc(a, g);
     const int p = S.pass, nw = (G.n + 31) >> 5, nbw = (G.row_words + 31) >> 5;
     if (S.reload == 2) {
       for (int c = tid; c <= G.k; c += NW * kWave) {
@@ -805,7 +861,7 @@ __device__ bool carry(const BatchArgs &a, const GView &V, BatchLds &S) {
                  : S.prio == P_ESELFLOOP ? KZ_ESELFLOOP
                  : S.prio == P_EASYM     ? KZ_EASYM
                                          : KZ_EILLEGAL;
-    if (p == 1) ast(&J->m, (long long)S.tests);
+    if (p == S.pass0) ast(&J->m, (long long)S.tests);
     ast(&J->tot_tests, ald(&J->tot_tests) + (long long)S.tests);
     ast(&J->tot_removed_v, ald(&J->tot_removed_v) + rv);
     ast(&J->tot_removed_e, ald(&J->tot_removed_e) + re);
@@ -816,7 +872,7 @@ __device__ bool carry(const BatchArgs &a, const GView &V, BatchLds &S) {
   if (S.end) {
     if (tid == 0) {
       if (S.status) fail_job(a, V.g, S.status);
-      else end_job(a, V, p);
+      else end_job(a, V, p - S.pass0 + 1);
     }
     __syncthreads();
     return false;
@@ -846,18 +902,22 @@ __device__ bool carry(const BatchArgs &a, const GView &V, BatchLds &S) {
 __device__ int find_job(const BatchArgs &a, BatchLds &S, unsigned least) {
   const int tid = threadIdx.x;
   if (tid < kWave) {
-    int gs[kBatchBoard / kWave];
-#pragma unroll
-    for (int j = 0; j < kBatchBoard / kWave; ++j)
-      gs[j] = __hip_atomic_load(&a.board[j * kWave + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long key = 0;
+    // kBatchBoard entries per step: their loads, then their claim words', in flight together
+    for (int base = 0; base <= a.board_mask; base += kBatchBoard) {
+      int gs[kBatchBoard / kWave];
 #pragma unroll
-    for (int j = 0; j < kBatchBoard / kWave; ++j) {
-      if (gs[j] < 0) continue;
-      const unsigned long long cw =
-          __hip_atomic_load(&a.jobs[gs[j]].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned ni = (unsigned)(cw >> kItemBits) & kItemMask, nx = (unsigned)cw & kItemMask;
-      if (nx < ni && ni - nx >= least) key = max(key, ((unsigned long long)(ni - nx) << 32) | (unsigned)(gs[j] + 1));
+      for (int j = 0; j < kBatchBoard / kWave; ++j)
+        gs[j] = __hip_atomic_load(&a.board[base + j * kWave + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int j = 0; j < kBatchBoard / kWave; ++j) {
+        if (gs[j] < 0) continue;
+        const unsigned long long cw =
+            __hip_atomic_load(&a.jobs[gs[j]].claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned ni = (unsigned)(cw >> kItemBits) & kItemMask, nx = (unsigned)cw & kItemMask;
+        if (nx < ni && ni - nx >= least)
+          key = max(key, ((unsigned long long)(ni - nx) << 32) | (unsigned)(gs[j] + 1));
+      }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -870,6 +930,49 @@ __device__ int find_job(const BatchArgs &a, BatchLds &S, unsigned least) {
   return S.pick;
 }
 
+// Session mode (thread 0): refreshes the device's copy of the host's
+// request count.  The count lives in pinned host memory; one workgroup at a
+// time reads it, at most every kHostPoll ticks.
+__device__ void poll_host(const BatchArgs &a) {
+  const unsigned long long now = wall_clock64();
+  unsigned long long last = ald(a.hpoll);
+  if (now - last < kHostPoll || !__hip_atomic_compare_exchange_strong(a.hpoll, &last, now, __ATOMIC_RELAXED,
+                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    return;
+  const unsigned long long hh = __hip_atomic_load(a.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  // the copy is written after the count's load has returned (it is the
+  // operand); a taker's own acquire orders its reads of the host tables
+  if (hh > ald(a.dhead)) __hip_atomic_fetch_max(a.dhead, hh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Session mode (thread 0): takes the next published request, if any, and
+// returns its slot (S.ticket: its ticket), else -1.
+__device__ int take_request(const BatchArgs &a, BatchLds &S) {
+  poll_host(a);
+  unsigned long long h = ald(a.dhead), q = ald(a.squeue);
+  while (q < h) {
+    if (__hip_atomic_compare_exchange_strong(a.squeue, &q, q + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) {
+      acquire_system();
+      unsigned *e = a.ring + q % (unsigned long long)a.cap;
+      unsigned slot = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      // the host wrote the entry before the count; should the entry still
+      // read as free, look again for a while rather than take a bad slot
+      for (int i = 0; i < 4096 && slot >= (unsigned)a.G; ++i) {
+        __builtin_amdgcn_s_sleep(8);
+        acquire_system();
+        slot = __hip_atomic_load(e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      if (slot >= (unsigned)a.G) return -1;  // never observed: the request stays untaken for good
+      S.ticket = __hip_atomic_load(a.htickets + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      // the host may write the entry again once it sees it read
+      __hip_atomic_store(e, kRingFree, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      return (int)slot;
+    }
+  }
+  return -1;
+}
+
 template <int NW, int CH>
 __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
   __shared__ BatchLds S;
@@ -879,11 +982,13 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
   if (tid == 0) {
     S.job = -1;
     S.pass = 0;
+    S.pass0 = 0;
     S.got = 0;
     S.queue_empty = 0;
   }
   __syncthreads();
   int job = -1;
+  const unsigned long long born = wall_clock64();  // session mode: the lease runs from here
   unsigned long long idle0 = 0;  // thread 0: when this workgroup ran out of work
   int backoff = 1;                // idle polls sleep 1, 2, 4 or 8 times between looks
   for (;;) {
@@ -903,9 +1008,16 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
       if (job >= 0) continue;
       __syncthreads();
       if (tid == 0) {
-        const int t = atomicAdd(a.queue, 1);
-        S.gi = t < a.G ? a.order[t] : -1;
-        if (t >= a.G) S.queue_empty = 1;
+        if (a.session) {
+          // past its lease a workgroup takes no new request, so the launch
+          // ends and kernels queued behind it on the same hardware queue run
+          const bool leased = a.lease_ticks && wall_clock64() - born > a.lease_ticks;
+          S.gi = leased ? -1 : take_request(a, S);
+        } else {
+          const int t = atomicAdd(a.queue, 1);
+          S.gi = t < a.G ? a.order[t] : -1;
+          if (t >= a.G) S.queue_empty = 1;
+        }
       }
       __syncthreads();
       const int g = S.gi;
@@ -925,8 +1037,10 @@ __global__ void __launch_bounds__(NW * 64) k_batch(BatchArgs a) {
     if (tid == 0) {
       const unsigned long long now = wall_clock64();
       if (!idle0) idle0 = now;
-      S.quit = __hip_atomic_load(a.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.G ||
-               now - idle0 > kIdleTicks;
+      // a session's workgroups stay for new requests until idle for idle_ticks
+      S.quit = a.session ? now - idle0 > a.idle_ticks || (a.lease_ticks && now - born > a.lease_ticks)
+                         : __hip_atomic_load(a.finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.G ||
+                               now - idle0 > kIdleTicks;
     }
     __syncthreads();
     if (S.quit) break;
@@ -949,7 +1063,7 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a, int lpt) {
     *a.queue = 0;
     *a.finished = 0;
   }
-  for (int i = t; i < kBatchBoard; i += 1024) a.board[i] = -1;
+  for (int i = t; i <= a.board_mask; i += 1024) a.board[i] = -1;
   if (!lpt || G > kBatchSortMax) {
     for (int i = t; i < G; i += 1024) a.order[i] = i;
     return;
@@ -990,8 +1104,11 @@ __global__ void __launch_bounds__(1024) k_batch_order(BatchArgs a, int lpt) {
 
 }  // namespace
 
-void launch_batch(const BatchArgs &a, const BatchConfig &cfg, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, a, cfg.lpt);
+void launch_batch(const BatchArgs &args, const BatchConfig &cfg, hipStream_t s) {
+  BatchArgs a = args;
+  if (a.board_mask <= 0) a.board_mask = kBatchBoard - 1;
+  // a session's queue and board are set up once, when its server is made
+  if (!a.session) hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, a, cfg.lpt);
   const dim3 grid(cfg.workgroups);
 #define KZ_B(NW, CH) hipLaunchKernelGGL((k_batch<NW, CH>), grid, dim3(NW * 64), 0, s, a)
   if (cfg.waves == 4) {

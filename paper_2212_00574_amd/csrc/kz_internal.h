@@ -165,8 +165,20 @@ constexpr int kBatchK = 64;          // classes
 constexpr int kBatchR = 512;         // words per row (blocks)
 constexpr int kBatchN = 32768;       // vertices
 constexpr int kBatchSortMax = 8192;  // graphs ordered by work on the device up to this count
-constexpr int kBatchBoard = 256;     // board of shared passes (job g posts at g mod kBatchBoard)
+constexpr int kBatchBoard = 256;     // board of shared passes (job g posts at g mod its size): default
+                                     // size, and the part one scan step of a wave reads
 constexpr int kBatchTooLarge = KZ_ETOOLARGE;
+
+// Per-graph buffers when graphs do not sit in shared arenas (served requests).
+struct BatchPtrs {
+  const uint64_t *rows;
+  const int *colour;
+  uint8_t *vmask;
+  uint64_t *emask;
+  uint64_t *next;  // n*row_words words
+  int *lists;      // changed tiles: 2*n*row_words ints
+  int *items;      // pass items: 2*n*row_words ints
+};                 // every buffer starts on a 128-byte line
 
 // One graph's job state in device memory.  Every word other workgroups
 // update with atomics is only ever accessed with (agent-scope) atomics, and
@@ -184,6 +196,16 @@ struct alignas(128) BatchJob {
   // totals, kept by the carriers (atomic loads and stores)
   alignas(128) long long tot_removed_v, tot_removed_e, tot_tests, m;
   int rounds;
+  // the number of the job's first pass, and the last pass opened in this
+  // slot: a slot that takes a new job while the launch runs numbers its
+  // passes on from the previous job's, so a workgroup holding a copy of an
+  // earlier job's pass never mistakes it for one of the new job's
+  int pass0, lastpass;
+  // session mode: the request's descriptor, buffers and ticket, copied from
+  // the host slot when the job starts (plain; read after the job's fences)
+  alignas(128) kz_batch_graph sdesc;
+  BatchPtrs sptrs;
+  unsigned long long ticket;
   // layout, written when the job starts, read by helpers (plain)
   alignas(128) int coff[kBatchK + 1], soff[kBatchK + 1];
   short bcls[kBatchR];
@@ -191,26 +213,17 @@ struct alignas(128) BatchJob {
   unsigned char blen[kBatchR];
 };
 
-// Per-graph buffers when graphs do not sit in shared arenas (served requests).
-struct BatchPtrs {
-  const uint64_t *rows;
-  const int *colour;
-  uint8_t *vmask;
-  uint64_t *emask;
-  uint64_t *next;  // n*row_words words
-  int *lists;      // changed tiles: 2*n*row_words ints
-  int *items;      // pass items: 2*n*row_words ints
-};                 // every buffer starts on a 128-byte line
 
 struct BatchArgs {
   const kz_batch_graph *graphs;
   const BatchPtrs *ptrs;  // [G] or null: then the arenas below and the descriptors' offsets
-  int G;
+  int G;          // graphs (session mode: slots)
   int share;      // 0: share passes once the queue is empty; 1: share every pass; 2: never
   int *order;     // [G]
   int *queue;     // next graph to take
   int *finished;  // graphs finished
-  int *board;     // [kBatchBoard] jobs with a shared pass
+  int *board;     // [board_mask + 1] jobs with a shared pass (job g posts at g & board_mask)
+  int board_mask; // a power of two of at least kBatchBoard, less one (0: kBatchBoard - 1)
   BatchJob *jobs; // [G]
   const uint64_t *rows;
   const int *colour;
@@ -220,7 +233,27 @@ struct BatchArgs {
   uint64_t *next;  // next-state words, same layout as rows
   int *lists;      // changed tiles: graph g's at int offset 2*row_offset
   int *items;      // pass items: graph g's at int offset 2*row_offset
+  // session mode (a server's continuous feed): jobs are slots of pinned host
+  // memory that the host publishes through a ring, and workgroups take them
+  // while the launch runs
+  int session;                        // 1: the fields below feed the queue
+  unsigned long long *squeue;         // next sequence number to take (device, atomics only)
+  unsigned long long *dhead;          // the host's count as last seen (device, atomics only)
+  unsigned long long *hpoll;          // when a workgroup last read the host's words (device)
+  int cap;                            // ring length (>= slots)
+  unsigned *ring;                     // [cap] slot of the request at each sequence number;
+                                      // the device marks an entry it has read kRingFree
+  const unsigned long long *head;     // requests published (host-written)
+  const kz_batch_graph *hgraphs;      // [slots] descriptors (row/vertex offsets unused)
+  const BatchPtrs *hptrs;             // [slots] buffers
+  const unsigned long long *htickets; // [slots] the request's ticket
+  kz_result *hres;                    // [slots] results
+  unsigned long long *hdone;          // [slots] ticket of the request whose result is in the slot
+  unsigned long long idle_ticks;      // leave after this long without work (wall_clock64 ticks)
+  unsigned long long lease_ticks;     // take no new request after this long (0: no limit)
 };
+
+constexpr unsigned kRingFree = 0xffffffffu;  // a ring entry the device has read
 
 struct BatchConfig {
   int waves, chunk, lpt, workgroups, share;

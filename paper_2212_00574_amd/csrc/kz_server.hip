@@ -1,25 +1,40 @@
-// Serving (host code): admission by slot and arena scratch, continuous
-// batching at launch granularity on top of the batched path's job runtime,
-// and a second lane for large requests.
+// Serving (host code): admission by slot, arena scratch and resident bytes;
+// continuous batching inside a running launch of the batched path's job
+// runtime (its session mode); and a second lane for requests that do not
+// suit the batched path.
 //
-// The arena starts with two launch records (descriptors, pointer tables,
-// job states, results, queue counters), each able to carry max_slots
-// requests; the rest is a first-fit heap of request scratch.  A launch takes
-// the waiting requests in arrival order, fills a free record's pinned host
-// tables, copies them to the device, runs the batched kernels and copies
-// the results back, all on the server's stream, and records an event;
-// kz_server_progress retires launches whose event has fired.
+// Session lane.  The arena starts with the runtime's device state (queue
+// counters, the board of shared passes, one job state per slot); the rest is
+// a first-fit heap of request scratch.  Pinned host memory holds, per slot,
+// the request's descriptor, buffer table, ticket, result and done flag, and
+// a ring of slot numbers with a published count.  A request is published
+// (its slot written, then the ring entry, then the count) once an event
+// recorded on the caller's stream after its submission has fired, so inputs
+// written there before kz_server_submit are complete.  Workgroups of a
+// running launch take published requests as they free up; a launch ends by
+// itself once it has had nothing to do for idle_us, and the host starts one
+// whenever published requests stay untaken with no launch running (or,
+// behind a running one, once they have waited kRelaunchUs).  Completion is
+// the slot's done flag reaching the request's ticket.
 //
-// Requests with at least kSplitN vertices (or beyond the batched path's
-// class and row-word limits) go to kWorkers worker threads instead: each
-// runs them one at a time through the single-graph path (kz_kernelize,
-// whose multi-workgroup passes suit large graphs) on a stream of its own,
-// after waiting for an event recorded on the server's stream when the
-// request was admitted (so inputs written there first are complete).  Both
-// lanes overlap on the device.  The two threads share the request table and
-// the arena heap under one mutex.
+// Single-graph lane.  Requests with at least split_n vertices, or beyond
+// the batched path's class and row-word limits, go to `workers` worker
+// threads (at most kMaxWorkers): each runs them one at a time through
+// kz_kernelize on a stream of its own, after waiting for an event recorded on the caller's stream at
+// admission.  The runtime's tiles restage rows for every pair of blocks, a
+// cost that grows with the cube of the row words, so large graphs go here.
+//
+// Sharing the device.  A session workgroup of 16 waves takes all of a
+// compute unit's registers, so a launch of session_cus workgroups leaves
+// the other units to this lane's kernels.  Each workgroup also takes no new
+// request once lease_us has passed since it started, so a launch ends
+// within about lease_us under load and whatever waits behind it on a shared
+// hardware queue runs; the host then starts the next.  Both lanes share the
+// request table and the arena heap under one mutex.
 #include <string.h>
 
+#include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -37,31 +52,71 @@ namespace {
 constexpr size_t kSrvAlign = 256;
 constexpr int kSrvMaxSlots = 4096;
 constexpr int kSrvMaxWorkgroups = 1024;
-constexpr int kSplitN = 4096;  // vertices from which a request takes the single-graph lane
-constexpr int kWorkers = 2;    // large requests in flight at once (each its own context and stream)
+constexpr int kMaxWorkers = 8;     // single-graph lane: requests in flight at once (each its own context and stream)
+constexpr int kDefaultWorkers = 6;
+constexpr int kMaxFences = 16;     // input-ready events in flight
+constexpr double kRelaunchUs = 500;  // untaken requests behind a running launch: queue another
+constexpr int kDefaultSplitN = 2048;
+constexpr int kDefaultIdleUs = 20000;
+constexpr int kDefaultLeaseUs = 50000;
+
+// Session lane's share of the compute units by default: the batched
+// runtime is the better path only for the smallest requests, which are a
+// small part of a mixed stream's work.
+int default_session_cus(int cus) { return std::max(1, cus * 3 / 16); }
 
 size_t up(size_t x) { return (x + kSrvAlign - 1) / kSrvAlign * kSrvAlign; }
 
-// Byte layout of one launch record in the arena.
-struct RecLayout {
-  size_t graphs, ptrs, order, counters, board, jobs, results, total;
+// Byte layout of the runtime's device state at the start of the arena.
+struct FixedLayout {
+  size_t ctl, board, jobs, total;
 };
+constexpr size_t kLine = 128;  // each control word on a cache line of its own
 
-RecLayout rec_layout(int slots) {
-  RecLayout L{};
+// The session's board has an entry per slot (a power of two, at least
+// kBatchBoard): shared passes of jobs in different slots never hide one
+// another.
+int board_size(int slots) {
+  int b = kzi::kBatchBoard;
+  while (b < slots) b *= 2;
+  return b;
+}
+
+FixedLayout fixed_layout(int slots) {
+  FixedLayout L{};
   size_t o = 0;
   auto take = [&o](size_t b) {
     const size_t at = o;
     o += up(b);
     return at;
   };
+  L.ctl = take(3 * kLine);  // queue, count copy, poll time
+  L.board = take(sizeof(int) * (size_t)board_size(slots));
+  L.jobs = take(sizeof(kzi::BatchJob) * (size_t)slots);
+  L.total = o;
+  return L;
+}
+
+// Byte layout of the pinned host tables.
+struct HostLayout {
+  size_t ring, head, graphs, ptrs, tickets, res, done, total;
+};
+
+HostLayout host_layout(int slots, int cap) {
+  HostLayout L{};
+  size_t o = 0;
+  auto take = [&o](size_t b) {
+    const size_t at = o;
+    o += up(b);
+    return at;
+  };
+  L.ring = take(sizeof(unsigned) * (size_t)cap);
+  L.head = take(sizeof(unsigned long long));
   L.graphs = take(sizeof(kz_batch_graph) * (size_t)slots);
   L.ptrs = take(sizeof(kzi::BatchPtrs) * (size_t)slots);
-  L.order = take(sizeof(int) * (size_t)slots);
-  L.counters = take(2 * sizeof(int));
-  L.board = take(sizeof(int) * kzi::kBatchBoard);
-  L.jobs = take(sizeof(kzi::BatchJob) * (size_t)slots);
-  L.results = take(sizeof(kz_result) * (size_t)slots);
+  L.tickets = take(sizeof(unsigned long long) * (size_t)slots);
+  L.res = take(sizeof(kz_result) * (size_t)slots);
+  L.done = take(sizeof(unsigned long long) * (size_t)slots);
   L.total = o;
   return L;
 }
@@ -107,48 +162,85 @@ class Heap {
 struct Req {
   kz_request r;
   size_t at, bytes;  // scratch in the arena
-  int state;         // 0 waiting, 1 launched, 2 done
+  size_t resident;   // the caller's buffers: rows, colours, masks
+  int state;         // 0 admitted, 1 published / taken by a worker, 2 done
   bool big;          // single-graph lane
-  hipEvent_t ready;  // big: inputs complete on the server's stream
+  int slot;          // session lane
+  hipEvent_t ready;  // single-graph lane: inputs complete on the caller's stream
   kz_result res;
 };
 
-struct Record {
-  char *dev;                    // in the arena
-  kz_batch_graph *graphs_host;  // pinned
-  kzi::BatchPtrs *ptrs_host;    // pinned
-  kz_result *results_host;      // pinned
-  hipEvent_t done;
-  bool busy;
-  std::vector<uint64_t> tickets;
+struct Fence {
+  hipEvent_t ev;
+  size_t count;  // pending requests it covers
 };
+
+using Clock = std::chrono::steady_clock;
 
 }  // namespace
 
 struct kz_server {
   kz_ctx *ctx;
-  hipStream_t stream;
+  hipStream_t stream;   // the caller's
+  hipStream_t sstream;  // session launches
   char *arena;
   size_t arena_bytes;
-  int slots;
-  RecLayout L;
-  Record rec[2];
+  int slots, cap;
+  FixedLayout F;
+  HostLayout H;
+  char *host;      // pinned tables (host address)
+  char *host_dev;  // the same, as the device sees them
+  unsigned *ring;
+  unsigned long long *head;
+  kz_batch_graph *hgraphs;
+  kzi::BatchPtrs *hptrs;
+  unsigned long long *htickets;
+  kz_result *hres;
+  unsigned long long *hdone;
+  std::vector<int> free_slots;
+  std::vector<uint64_t> slot_ticket;  // published request in each slot (0: none)
+  std::vector<int> running;           // slots published and not yet seen done
   Heap heap;
-  std::deque<uint64_t> waiting;
+  std::deque<uint64_t> pending;  // session lane, admitted, not yet published (in order)
+  size_t covered, ready;         // of pending (from the front): under a fence / fence fired
+  std::deque<Fence> fences;
+  std::vector<hipEvent_t> evpool;
+  uint64_t published;
+  std::deque<hipEvent_t> launches;  // session launches in flight on sstream
+  bool untaken_seen;
+  Clock::time_point untaken_since;
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next_ticket;
   int admitted;  // requests admitted and not yet retired by a poll
+  // configuration
+  int split_n, idle_us, lease_us, session_cus;
+  int partition;  // 1: the lanes' streams carry complementary compute-unit masks
+  int clock_khz;  // the device's constant-rate clock (wall_clock64)
+  size_t resident_limit, resident;
   // single-graph lane
-  kz_ctx *wctx[kWorkers];  // each worker's context (its own readback buffer)
-  hipStream_t wstream[kWorkers];
-  std::thread worker[kWorkers];
-  std::mutex mu;  // reqs, heap, big, stop, admitted
+  int workers;                // running
+  kz_ctx *wctx[kMaxWorkers];  // each worker's context (its own readback buffer)
+  hipStream_t wstream[kMaxWorkers];
+  std::thread worker[kMaxWorkers];
+  std::mutex mu;  // everything above that both lanes touch
   std::condition_variable cv;
   std::deque<uint64_t> big;
+  std::deque<uint64_t> finished;  // done, in completion order, not yet retired
   bool stop;
 };
 
 namespace {
+
+hipEvent_t take_event(kz_server *s) {
+  hipEvent_t e = nullptr;
+  if (!s->evpool.empty()) {
+    e = s->evpool.back();
+    s->evpool.pop_back();
+  } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
 
 void release(kz_server *s) {
   {
@@ -160,16 +252,15 @@ void release(kz_server *s) {
     if (w.joinable()) w.join();
   for (auto &kv : s->reqs)
     if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
-  for (int i = 0; i < kWorkers; ++i) {
+  for (Fence &f : s->fences) (void)hipEventDestroy(f.ev);
+  for (hipEvent_t e : s->launches) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
+  for (int i = 0; i < kMaxWorkers; ++i) {
     if (s->wstream[i]) (void)hipStreamDestroy(s->wstream[i]);
     if (s->wctx[i]) kz_destroy(s->wctx[i]);
   }
-  for (Record &r : s->rec) {
-    if (r.done) (void)hipEventDestroy(r.done);
-    if (r.graphs_host) (void)hipHostFree(r.graphs_host);
-    if (r.ptrs_host) (void)hipHostFree(r.ptrs_host);
-    if (r.results_host) (void)hipHostFree(r.results_host);
-  }
+  if (s->sstream) (void)hipStreamDestroy(s->sstream);
+  if (s->host) (void)hipHostFree(s->host);
   delete s;
 }
 
@@ -183,8 +274,8 @@ void work(kz_server *s, int id) {
     Req q{};
     {
       std::unique_lock<std::mutex> g(s->mu);
-      s->cv.wait(g, [s] { return s->stop || !s->big.empty(); });
-      if (s->stop) return;
+      s->cv.wait(g, [s, id] { return s->stop || id >= s->workers || !s->big.empty(); });
+      if (s->stop || id >= s->workers) return;
       t = s->big.front();
       s->big.pop_front();
       Req &r = s->reqs[t];
@@ -207,84 +298,217 @@ void work(kz_server *s, int id) {
     Req &r = s->reqs[t];
     r.res = res;
     r.state = 2;
+    s->finished.push_back(t);
     (void)hipEventDestroy(r.ready);
     r.ready = nullptr;
     if (r.bytes) s->heap.give(r.at, r.bytes);
     r.bytes = 0;
+    s->resident -= r.resident;
   }
 }
 
-int launch(kz_server *s, Record &rec) {
-  const int G = (int)std::min<size_t>(s->waiting.size(), (size_t)s->slots);
-  if (G == 0) return KZ_OK;
-  rec.tickets.clear();
-  for (int i = 0; i < G; ++i) {
-    const uint64_t t = s->waiting.front();
-    s->waiting.pop_front();
-    Req &q = s->reqs[t];
-    q.state = 1;
-    rec.tickets.push_back(t);
-    kz_batch_graph &g = rec.graphs_host[i];
-    g.n = q.r.n;
-    g.k = q.r.k;
-    g.row_words = q.r.row_words;
-    g.clique = q.r.clique;
-    g.row_offset = 0;
-    g.vertex_offset = 0;
-    kzi::BatchPtrs &p = rec.ptrs_host[i];
-    const size_t words = (size_t)q.r.n * (size_t)q.r.row_words;
-    p.rows = q.r.rows;
-    p.colour = q.r.colour;
-    p.vmask = q.r.vmask;
-    p.emask = q.r.emask;
-    p.next = (uint64_t *)(s->arena + q.at);
-    p.lists = (int *)(s->arena + q.at + up(words * sizeof(uint64_t)));
-    p.items = (int *)(s->arena + q.at + up(words * sizeof(uint64_t)) + up(2 * words * sizeof(int)));
+// A lane's stream: with partition on, the session lane's on the first
+// session_cus compute units (in the mask's bit order) and the other lane's
+// on the rest; else a plain stream.  Masked streams are blocking streams
+// (work on the legacy null stream waits for theirs), so a caller that
+// partitions passes the server a stream of its own.
+hipError_t make_stream(kz_server *s, bool session, hipStream_t *out) {
+  const int cus = s->ctx->cus;
+  if (!s->partition || s->session_cus >= cus) return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
+  std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+  for (int c = 0; c < cus; ++c)
+    if ((c < s->session_cus) == session) mask[(size_t)c / 32] |= 1u << (c % 32);
+  return hipExtStreamCreateWithCUMask(out, (uint32_t)mask.size(), mask.data());
+}
+
+// Runs n workers (caller does not hold mu; no request is admitted): stops
+// those beyond n, and makes contexts, streams and threads up to n.
+int set_workers(kz_server *s, int n) {
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->workers = std::min(s->workers, n);
   }
-  kzi::BatchArgs a{};
-  a.graphs = (const kz_batch_graph *)(rec.dev + s->L.graphs);
-  a.ptrs = (const kzi::BatchPtrs *)(rec.dev + s->L.ptrs);
-  a.G = G;
-  a.share = s->ctx->batch_cfg.share;
-  a.order = (int *)(rec.dev + s->L.order);
-  a.queue = (int *)(rec.dev + s->L.counters);
-  a.finished = a.queue + 1;
-  a.board = (int *)(rec.dev + s->L.board);
-  a.jobs = (kzi::BatchJob *)(rec.dev + s->L.jobs);
-  a.results = (kz_result *)(rec.dev + s->L.results);
-  kzi::BatchConfig c = s->ctx->batch_cfg;
-  c.workgroups = c.workgroups > 0 ? c.workgroups : s->ctx->cus * (16 / c.waves);
-  if (c.workgroups > kSrvMaxWorkgroups) c.workgroups = kSrvMaxWorkgroups;
-  if (hipMemcpyAsync((void *)a.graphs, rec.graphs_host, sizeof(kz_batch_graph) * G, hipMemcpyHostToDevice,
-                     s->stream) != hipSuccess ||
-      hipMemcpyAsync((void *)a.ptrs, rec.ptrs_host, sizeof(kzi::BatchPtrs) * G, hipMemcpyHostToDevice,
-                     s->stream) != hipSuccess)
-    return KZ_EHIP;
-  kzi::launch_batch(a, c, s->stream);
-  if (hipGetLastError() != hipSuccess) return KZ_EHIP;
-  if (hipMemcpyAsync(rec.results_host, a.results, sizeof(kz_result) * G, hipMemcpyDeviceToHost, s->stream) !=
-          hipSuccess ||
-      hipEventRecord(rec.done, s->stream) != hipSuccess)
-    return KZ_EHIP;
-  rec.busy = true;
+  s->cv.notify_all();
+  for (int i = n; i < kMaxWorkers; ++i)
+    if (s->worker[i].joinable()) s->worker[i].join();
+  for (int i = 0; i < n; ++i) {
+    if (!s->wctx[i]) {
+      if (kz_create(&s->wctx[i], s->ctx->device) != KZ_OK) return KZ_EHIP;
+      s->wctx[i]->edge_path = s->ctx->edge_path;
+    }
+    if (!s->wstream[i] && make_stream(s, false, &s->wstream[i]) != hipSuccess) return KZ_EHIP;
+  }
+  std::lock_guard<std::mutex> g(s->mu);
+  s->workers = n;
+  for (int i = 0; i < n; ++i)
+    if (!s->worker[i].joinable()) s->worker[i] = std::thread(work, s, i);
   return KZ_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t kz_server_fixed_bytes(int32_t max_slots) {
-  if (max_slots < 1 || max_slots > kSrvMaxSlots) return 0;
-  return 2 * rec_layout(max_slots).total;
+// Covers the pending requests no fence covers yet with an event on the
+// caller's stream (caller holds mu).
+int cover(kz_server *s) {
+  if (s->pending.size() <= s->covered || (int)s->fences.size() >= kMaxFences) return KZ_OK;
+  Fence f{take_event(s), s->pending.size() - s->covered};
+  if (!f.ev) return KZ_EHIP;
+  if (hipEventRecord(f.ev, s->stream) != hipSuccess) {
+    s->evpool.push_back(f.ev);
+    return KZ_EHIP;
+  }
+  s->fences.push_back(f);
+  s->covered = s->pending.size();
+  return KZ_OK;
 }
 
-namespace {
+// Writes request t into its slot and the ring, then bumps the count.
+void publish(kz_server *s, uint64_t t) {
+  Req &q = s->reqs[t];
+  const int slot = q.slot;
+  kz_batch_graph &g = s->hgraphs[slot];
+  g.n = q.r.n;
+  g.k = q.r.k;
+  g.row_words = q.r.row_words;
+  g.clique = q.r.clique;
+  g.row_offset = 0;
+  g.vertex_offset = 0;
+  kzi::BatchPtrs &p = s->hptrs[slot];
+  const size_t words = (size_t)q.r.n * (size_t)q.r.row_words;
+  p.rows = q.r.rows;
+  p.colour = q.r.colour;
+  p.vmask = q.r.vmask;
+  p.emask = q.r.emask;
+  p.next = (uint64_t *)(s->arena + q.at);
+  p.lists = (int *)(s->arena + q.at + up(words * sizeof(uint64_t)));
+  p.items = (int *)(s->arena + q.at + up(words * sizeof(uint64_t)) + up(2 * words * sizeof(int)));
+  s->htickets[slot] = t;
+  s->hdone[slot] = 0;
+  s->slot_ticket[slot] = t;
+  __atomic_store_n(&s->ring[s->published % (uint64_t)s->cap], (unsigned)slot, __ATOMIC_RELEASE);
+  ++s->published;
+  __atomic_store_n(s->head, (unsigned long long)s->published, __ATOMIC_RELEASE);
+  q.state = 1;
+  s->running.push_back(slot);
+}
 
-// Scratch of the batch lane: next-state words, changed-tile and item lists.
+int launch_session(kz_server *s) {
+  hipEvent_t e = take_event(s);
+  if (!e) return KZ_EHIP;
+  kzi::BatchArgs a{};
+  char *ctl = s->arena + s->F.ctl;
+  a.session = 1;
+  a.G = s->slots;
+  a.share = s->ctx->batch_cfg.share;
+  a.board = (int *)(s->arena + s->F.board);
+  a.board_mask = board_size(s->slots) - 1;
+  a.jobs = (kzi::BatchJob *)(s->arena + s->F.jobs);
+  a.squeue = (unsigned long long *)ctl;
+  a.dhead = (unsigned long long *)(ctl + kLine);
+  a.hpoll = (unsigned long long *)(ctl + 2 * kLine);
+  a.cap = s->cap;
+  a.ring = (unsigned *)(s->host_dev + s->H.ring);
+  a.head = (const unsigned long long *)(s->host_dev + s->H.head);
+  a.hgraphs = (const kz_batch_graph *)(s->host_dev + s->H.graphs);
+  a.hptrs = (const kzi::BatchPtrs *)(s->host_dev + s->H.ptrs);
+  a.htickets = (const unsigned long long *)(s->host_dev + s->H.tickets);
+  a.hres = (kz_result *)(s->host_dev + s->H.res);
+  a.hdone = (unsigned long long *)(s->host_dev + s->H.done);
+  a.idle_ticks = (unsigned long long)s->idle_us * (unsigned long long)s->clock_khz / 1000ull;
+  a.lease_ticks = (unsigned long long)s->lease_us * (unsigned long long)s->clock_khz / 1000ull;
+  kzi::BatchConfig c = s->ctx->batch_cfg;
+  c.workgroups = s->session_cus * (16 / c.waves);
+  if (c.workgroups > kSrvMaxWorkgroups) c.workgroups = kSrvMaxWorkgroups;
+  kzi::launch_batch(a, c, s->sstream);
+  if (hipGetLastError() != hipSuccess || hipEventRecord(e, s->sstream) != hipSuccess) {
+    s->evpool.push_back(e);
+    return KZ_EHIP;
+  }
+  s->launches.push_back(e);
+  return KZ_OK;
+}
+
+// One step of the session lane (caller holds mu).
+int step(kz_server *s) {
+  // completions
+  for (size_t i = 0; i < s->running.size();) {
+    const int slot = s->running[i];
+    const uint64_t t = s->slot_ticket[slot];
+    if (__atomic_load_n(&s->hdone[slot], __ATOMIC_ACQUIRE) != t) {
+      ++i;
+      continue;
+    }
+    Req &q = s->reqs[t];
+    q.res = s->hres[slot];
+    q.state = 2;
+    s->finished.push_back(t);
+    if (q.bytes) s->heap.give(q.at, q.bytes);
+    q.bytes = 0;
+    s->resident -= q.resident;
+    s->slot_ticket[slot] = 0;
+    s->free_slots.push_back(slot);
+    s->running[i] = s->running.back();
+    s->running.pop_back();
+  }
+  // inputs ready: publish in order while the ring has room
+  while (!s->fences.empty()) {
+    const hipError_t e = hipEventQuery(s->fences.front().ev);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return KZ_EHIP;
+    s->ready += s->fences.front().count;
+    s->evpool.push_back(s->fences.front().ev);
+    s->fences.pop_front();
+  }
+  while (s->ready > 0 &&
+         __atomic_load_n(&s->ring[s->published % (uint64_t)s->cap], __ATOMIC_ACQUIRE) == kzi::kRingFree) {
+    const uint64_t t = s->pending.front();
+    s->pending.pop_front();
+    --s->ready;
+    --s->covered;
+    publish(s, t);
+  }
+  int st = cover(s);
+  if (st != KZ_OK) return st;
+  // launches
+  while (!s->launches.empty()) {
+    const hipError_t e = hipEventQuery(s->launches.front());
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return KZ_EHIP;
+    s->evpool.push_back(s->launches.front());
+    s->launches.pop_front();
+  }
+  const bool untaken =
+      s->published > 0 &&
+      __atomic_load_n(&s->ring[(s->published - 1) % (uint64_t)s->cap], __ATOMIC_ACQUIRE) != kzi::kRingFree;
+  if (!untaken) {
+    s->untaken_seen = false;
+    return KZ_OK;
+  }
+  if (s->launches.empty()) {
+    s->untaken_seen = false;
+    return launch_session(s);
+  }
+  const Clock::time_point now = Clock::now();
+  if (!s->untaken_seen) {
+    s->untaken_seen = true;
+    s->untaken_since = now;
+  } else if (s->launches.size() < 2 &&
+             std::chrono::duration<double, std::micro>(now - s->untaken_since).count() > kRelaunchUs) {
+    // the running launch may be ending, or busy: queue one behind it
+    s->untaken_seen = false;
+    return launch_session(s);
+  }
+  return KZ_OK;
+}
+
+// Scratch of the session lane: next-state words, changed-tile and item lists.
 size_t batch_bytes(const kz_request &r) {
   const size_t words = (size_t)r.n * (size_t)r.row_words;
   return up(words * sizeof(uint64_t)) + 2 * up(2 * words * sizeof(int));
+}
+
+// The caller's buffers of a request: rows, colours, vmask, emask.
+size_t resident_bytes(const kz_request &r) {
+  const size_t words = (size_t)r.n * (size_t)r.row_words;
+  return 2 * words * sizeof(uint64_t) + (size_t)r.n * (sizeof(int32_t) + 1);
 }
 
 // Scratch of the single-graph lane: kz_kernelize's workspace.
@@ -299,11 +523,28 @@ int single_bytes(kz_ctx *ctx, const kz_request &r, size_t *bytes) {
   return st;
 }
 
+bool fits_batch(const kz_request &r) {
+  return r.k <= kzi::kBatchK && r.row_words <= kzi::kBatchR && r.n <= kzi::kBatchN;
+}
+
+// Lane of a valid request: true = single-graph.
+bool takes_big(const kz_server *s, const kz_request &r) {
+  const bool below = r.clique > 0 && r.clique < r.k;  // only the session lane takes a smaller clique size
+  return !below && (r.n >= s->split_n || !fits_batch(r));
+}
+
 }  // namespace
+
+extern "C" {
+
+size_t kz_server_fixed_bytes(int32_t max_slots) {
+  if (max_slots < 1 || max_slots > kSrvMaxSlots) return 0;
+  return fixed_layout(max_slots).total;
+}
 
 size_t kz_server_request_bytes(const kz_server *s, const kz_request *req) {
   if (!s || !req || req->n < 0 || req->k < 1 || req->row_words < 0) return 0;
-  if (req->n < kSplitN && req->k <= kzi::kBatchK && req->row_words <= kzi::kBatchR) return batch_bytes(*req);
+  if (!takes_big(s, *req)) return batch_bytes(*req);
   size_t b = 0;
   return single_bytes(s->wctx[0], *req, &b) == KZ_OK ? b : 0;
 }
@@ -314,58 +555,120 @@ int kz_server_create(kz_ctx *ctx, void *arena, size_t arena_bytes, int32_t max_s
   *out = nullptr;
   if (!ctx || !arena || (uintptr_t)arena % kSrvAlign || max_slots < 1 || max_slots > kSrvMaxSlots)
     return KZ_EINVAL;
-  const RecLayout L = rec_layout(max_slots);
-  if (arena_bytes <= 2 * L.total) return KZ_EWORKSPACE;
+  const FixedLayout F = fixed_layout(max_slots);
+  if (arena_bytes <= F.total) return KZ_EWORKSPACE;
   kz_server *s = new (std::nothrow) kz_server();
   if (!s) return KZ_ENOMEM;
   s->ctx = ctx;
   s->stream = (hipStream_t)stream;
+  s->sstream = nullptr;
   s->arena = (char *)arena;
   s->arena_bytes = arena_bytes;
   s->slots = max_slots;
-  s->L = L;
+  s->cap = 2 * max_slots;
+  s->F = F;
+  s->H = host_layout(max_slots, s->cap);
+  s->host = nullptr;
+  s->covered = s->ready = 0;
+  s->published = 0;
+  s->untaken_seen = false;
   s->next_ticket = 1;
   s->admitted = 0;
-  s->heap.init(2 * L.total, arena_bytes - 2 * L.total);
-  for (int i = 0; i < kWorkers; ++i) {
+  s->split_n = kDefaultSplitN;
+  s->idle_us = kDefaultIdleUs;
+  s->lease_us = kDefaultLeaseUs;
+  s->session_cus = default_session_cus(ctx->cus);
+  s->partition = 0;
+  s->resident_limit = 0;
+  s->resident = 0;
+  s->stop = false;
+  s->heap.init(F.total, arena_bytes - F.total);
+  s->workers = 0;
+  for (int i = 0; i < kMaxWorkers; ++i) {
     s->wctx[i] = nullptr;
     s->wstream[i] = nullptr;
   }
-  s->stop = false;
-  for (int i = 0; i < 2; ++i) {
-    Record &r = s->rec[i];
-    r.dev = s->arena + i * L.total;
-    r.graphs_host = nullptr;
-    r.ptrs_host = nullptr;
-    r.results_host = nullptr;
-    r.done = nullptr;
-    r.busy = false;
-  }
-  if (hipSetDevice(ctx->device) != hipSuccess) {
+  if (hipSetDevice(ctx->device) != hipSuccess ||
+      hipDeviceGetAttribute(&s->clock_khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess ||
+      s->clock_khz <= 0) {
     release(s);
     return KZ_EHIP;
   }
-  for (Record &r : s->rec) {
-    if (hipHostMalloc((void **)&r.graphs_host, sizeof(kz_batch_graph) * max_slots, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void **)&r.ptrs_host, sizeof(kzi::BatchPtrs) * max_slots, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void **)&r.results_host, sizeof(kz_result) * max_slots, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipEventCreateWithFlags(&r.done, hipEventDisableTiming) != hipSuccess) {
-      release(s);
-      return KZ_EHIP;
-    }
+  // host tables the device reads and writes while a launch runs: fine-grained
+  if (hipHostMalloc((void **)&s->host, s->H.total, hipHostMallocCoherent) != hipSuccess) {
+    s->host = nullptr;
+    release(s);
+    return KZ_EHIP;
   }
-  for (int i = 0; i < kWorkers; ++i) {
-    if (kz_create(&s->wctx[i], ctx->device) != KZ_OK || hipStreamCreate(&s->wstream[i]) != hipSuccess) {
-      release(s);
-      return KZ_EHIP;
-    }
-    s->wctx[i]->edge_path = ctx->edge_path;
+  if (hipHostGetDevicePointer((void **)&s->host_dev, s->host, 0) != hipSuccess) {
+    release(s);
+    return KZ_EHIP;
   }
-  for (int i = 0; i < kWorkers; ++i) s->worker[i] = std::thread(work, s, i);
+  memset(s->host, 0, s->H.total);
+  s->ring = (unsigned *)(s->host + s->H.ring);
+  s->head = (unsigned long long *)(s->host + s->H.head);
+  s->hgraphs = (kz_batch_graph *)(s->host + s->H.graphs);
+  s->hptrs = (kzi::BatchPtrs *)(s->host + s->H.ptrs);
+  s->htickets = (unsigned long long *)(s->host + s->H.tickets);
+  s->hres = (kz_result *)(s->host + s->H.res);
+  s->hdone = (unsigned long long *)(s->host + s->H.done);
+  for (int i = 0; i < s->cap; ++i) s->ring[i] = kzi::kRingFree;
+  s->slot_ticket.assign((size_t)max_slots, 0);
+  for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
+  s->running.reserve((size_t)max_slots);
+  // device state: counters zero, job states zero (first pass numbers start
+  // at 1), board empty
+  if (make_stream(s, true, &s->sstream) != hipSuccess ||
+      hipMemsetAsync(s->arena, 0, F.total, s->sstream) != hipSuccess ||
+      hipMemsetAsync(s->arena + F.board, 0xff, sizeof(int) * (size_t)board_size(max_slots), s->sstream) !=
+          hipSuccess ||
+      hipStreamSynchronize(s->sstream) != hipSuccess) {
+    release(s);
+    return KZ_EHIP;
+  }
+  if (set_workers(s, kDefaultWorkers) != KZ_OK) {
+    release(s);
+    return KZ_EHIP;
+  }
   *out = s;
+  return KZ_OK;
+}
+
+int kz_server_configure(kz_server *s, const kz_server_config *cfg) {
+  if (!s || !cfg || cfg->split_n < 0 || cfg->idle_us < 0 || cfg->idle_us > 1000000 || cfg->lease_us < 0 ||
+      cfg->lease_us > 1000000 || cfg->session_cus < 0 || cfg->session_cus > s->ctx->cus || cfg->workers < 0 ||
+      cfg->workers > kMaxWorkers || cfg->partition < 0 || cfg->partition > 1 ||
+      (cfg->partition && cfg->session_cus >= s->ctx->cus))
+    return KZ_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->admitted > 0) return KZ_EAGAIN;
+  }
+  // nothing is admitted, so every worker waits idle
+  if (hipSetDevice(s->ctx->device) != hipSuccess) return KZ_EHIP;
+  const int cus = cfg->session_cus > 0 ? cfg->session_cus : default_session_cus(s->ctx->cus);
+  if (cfg->partition != s->partition || (cfg->partition && cus != s->session_cus)) {
+    // new streams: wait for what the old ones run, then replace them
+    for (hipEvent_t e : s->launches) (void)hipEventSynchronize(e);
+    if (set_workers(s, 0) != KZ_OK || hipStreamSynchronize(s->sstream) != hipSuccess) return KZ_EHIP;
+    s->partition = cfg->partition != 0;
+    s->session_cus = cus;
+    for (int i = 0; i < kMaxWorkers; ++i) {
+      if (s->wstream[i]) (void)hipStreamDestroy(s->wstream[i]);
+      s->wstream[i] = nullptr;
+    }
+    (void)hipStreamDestroy(s->sstream);
+    s->sstream = nullptr;
+    if (make_stream(s, true, &s->sstream) != hipSuccess) return KZ_EHIP;
+  }
+  const int st = set_workers(s, cfg->workers > 0 ? cfg->workers : kDefaultWorkers);
+  if (st != KZ_OK) return st;
+  std::lock_guard<std::mutex> g(s->mu);
+  s->split_n = cfg->split_n > 0 ? cfg->split_n : kDefaultSplitN;
+  s->idle_us = cfg->idle_us > 0 ? cfg->idle_us : kDefaultIdleUs;
+  s->lease_us = cfg->lease_us > 0 ? cfg->lease_us : kDefaultLeaseUs;
+  s->session_cus = cus;
+  s->resident_limit = cfg->resident_limit;
   return KZ_OK;
 }
 
@@ -374,25 +677,29 @@ int kz_server_submit(kz_server *s, const kz_request *req, uint64_t *ticket) {
   const kz_request &r = *req;
   if (r.n < 0 || r.k < 1 || r.row_words < 0 || (r.n > 0 && (!r.rows || !r.colour || !r.vmask || !r.emask)))
     return KZ_EINVAL;
-  // the batch lane's outputs must not share a 128-byte line with other data
+  // the session lane's outputs must not share a 128-byte line with other data
   if ((uintptr_t)r.vmask % 128 || (uintptr_t)r.emask % 128) return KZ_EINVAL;
   if (r.clique < 0 || r.clique > r.k) return KZ_EINVAL;
-  const bool fits_batch = r.k <= kzi::kBatchK && r.row_words <= kzi::kBatchR && r.n <= kzi::kBatchN;
-  const bool below = r.clique > 0 && r.clique < r.k;  // only the batched lane takes a smaller clique size
-  if (below && !fits_batch) return KZ_EINVAL;
-  const bool big = !below && (r.n >= kSplitN || !fits_batch);
+  const bool below = r.clique > 0 && r.clique < r.k;
+  if (below && !fits_batch(r)) return KZ_EINVAL;
+  const bool big = takes_big(s, r);
   size_t bytes = batch_bytes(r);
   if (big && single_bytes(s->wctx[0], r, &bytes) != KZ_OK) return KZ_EINVAL;
+  const size_t resident = resident_bytes(r);
   std::lock_guard<std::mutex> g(s->mu);
-  if (s->admitted >= s->slots) return KZ_EAGAIN;
+  if (s->resident_limit && resident > s->resident_limit) return KZ_EINVAL;  // could never be admitted
+  if (s->admitted >= s->slots || (!big && s->free_slots.empty())) return KZ_EAGAIN;
+  if (s->resident_limit && s->resident + resident > s->resident_limit) return KZ_EAGAIN;
   size_t at = 0;
   if (bytes && !s->heap.take(bytes, &at)) return KZ_EAGAIN;
   Req q{};
   q.r = r;
   q.at = at;
   q.bytes = bytes;
+  q.resident = resident;
   q.state = 0;
   q.big = big;
+  q.slot = -1;
   q.ready = nullptr;
   if (big && (hipEventCreateWithFlags(&q.ready, hipEventDisableTiming) != hipSuccess ||
               hipEventRecord(q.ready, s->stream) != hipSuccess)) {
@@ -401,12 +708,22 @@ int kz_server_submit(kz_server *s, const kz_request *req, uint64_t *ticket) {
     return KZ_EHIP;
   }
   const uint64_t t = s->next_ticket++;
+  if (!big) {
+    q.slot = s->free_slots.back();
+    s->free_slots.pop_back();
+  }
   s->reqs.emplace(t, q);
-  if (big) s->big.push_back(t);
-  else s->waiting.push_back(t);
+  s->resident += resident;
   ++s->admitted;
   *ticket = t;
-  if (big) s->cv.notify_one();
+  if (big) {
+    s->big.push_back(t);
+    s->cv.notify_one();
+    return KZ_OK;
+  }
+  s->pending.push_back(t);
+  // an input-ready event right away (kz_server_progress covers the rest)
+  (void)cover(s);
   return KZ_OK;
 }
 
@@ -414,30 +731,29 @@ int kz_server_progress(kz_server *s) {
   if (!s) return KZ_EINVAL;
   if (hipSetDevice(s->ctx->device) != hipSuccess) return KZ_EHIP;
   std::lock_guard<std::mutex> g(s->mu);
-  for (Record &rec : s->rec) {
-    if (!rec.busy) continue;
-    const hipError_t e = hipEventQuery(rec.done);
-    if (e == hipErrorNotReady) continue;
-    if (e != hipSuccess) return KZ_EHIP;
-    for (size_t i = 0; i < rec.tickets.size(); ++i) {
-      Req &q = s->reqs[rec.tickets[i]];
-      q.res = rec.results_host[i];
-      q.state = 2;
-      if (q.bytes) s->heap.give(q.at, q.bytes);
-      q.bytes = 0;
-    }
-    rec.tickets.clear();
-    rec.busy = false;
+  const int st = step(s);
+  return st != KZ_OK ? st : s->admitted;
+}
+
+int kz_server_done(kz_server *s, uint64_t *tickets, kz_result *res, int32_t max) {
+  if (!s || max < 0 || (max > 0 && !tickets)) return KZ_EINVAL;
+  if (hipSetDevice(s->ctx->device) != hipSuccess) return KZ_EHIP;
+  std::lock_guard<std::mutex> g(s->mu);
+  const int st = step(s);
+  if (st != KZ_OK) return st;
+  int got = 0;
+  while (got < max && !s->finished.empty()) {
+    const uint64_t t = s->finished.front();
+    s->finished.pop_front();
+    auto it = s->reqs.find(t);
+    if (it == s->reqs.end()) continue;  // retired by kz_server_poll meanwhile
+    tickets[got] = t;
+    if (res) res[got] = it->second.res;
+    s->reqs.erase(it);
+    --s->admitted;
+    ++got;
   }
-  // launch what waits, into a free record (the first in flight runs, a
-  // second queues behind it on the stream)
-  for (Record &rec : s->rec) {
-    if (s->waiting.empty()) break;
-    if (rec.busy) continue;
-    const int st = launch(s, rec);
-    if (st != KZ_OK) return st;
-  }
-  return s->admitted;
+  return got;
 }
 
 int kz_server_poll(kz_server *s, uint64_t ticket, kz_result *res) {
@@ -458,12 +774,13 @@ void kz_server_destroy(kz_server *s) {
   if (!s) return;
   (void)hipSetDevice(s->ctx->device);
   {
-    // let the worker finish what it holds; it takes nothing new once stopped
+    // workers finish what they hold and take nothing new; requests not yet
+    // published are dropped
     std::unique_lock<std::mutex> g(s->mu);
     s->big.clear();
   }
-  for (Record &rec : s->rec)
-    if (rec.busy) (void)hipEventSynchronize(rec.done);
+  // session launches end once idle (published requests they took first)
+  for (hipEvent_t e : s->launches) (void)hipEventSynchronize(e);
   release(s);
 }
 

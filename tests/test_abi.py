@@ -31,7 +31,8 @@ def test_header_declares_the_entry_points():
                           "kz_dominance", "kz_find_clique", "kz_gen_bitset",
                           "kz_kernelize", "kz_kernelize_batch", "kz_kernelize_noalloc", "kz_profile_enable",
                           "kz_profile_read",
-                          "kz_server_create", "kz_server_destroy", "kz_server_fixed_bytes", "kz_server_poll",
+                          "kz_server_configure", "kz_server_create", "kz_server_destroy", "kz_server_done", "kz_server_fixed_bytes",
+                          "kz_server_poll",
                           "kz_server_progress", "kz_server_request_bytes", "kz_server_submit",
                           "kz_set_edge_path", "kz_strerror", "kz_struction", "kz_struction_workspace_bytes",
                           "kz_workspace_bytes"]

@@ -295,3 +295,163 @@ def test_server_trickle_shared_passes(kz):
         assert np.array_equal(ref_m[i][0], o["vmask"]), i
         assert np.array_equal(ref_m[i][1].view(np.uint64).reshape(lay.n, lay.R), o["emask"]), i
     srv.close()
+
+
+def test_server_slot_reuse_in_running_launch(kz):
+    """Three slots for 150 requests submitted as fast as they are admitted:
+    each slot takes a new job while the launch that ran its previous one is
+    still running, with every pass shared across workgroups.  Results equal
+    those of the same requests with every pass kept by one workgroup, and a
+    sample equals the oracle."""
+    from paper_2212_00574_amd.binding import kz_batch_get_config, kz_batch_set_config
+    say("server: slot reuse inside a running launch")
+    rng = np.random.default_rng(41)
+    reqs = []
+    for i in range(150):
+        k = int(rng.integers(3, 12))
+        reqs.append(Req(rng.integers(10, 80, size=k), float(rng.uniform(0.2, 0.8)), 41, i,
+                        plant=bool(rng.random() < 0.3)))
+    cfg0 = kz_batch_get_config(kz.ctx)
+    try:
+        out = {}
+        for share in (2, 1):
+            kz_batch_set_config(kz.ctx, dict(cfg0, share=share))
+            srv = Server(kz, arena_bytes=64 << 20, max_slots=3)
+            for r in reqs:
+                r.vmask.fill_(9)
+                r.emask.fill_(-1)
+            res = run_all(srv, reqs)
+            out[share] = (res, [r.masks() for r in reqs])
+            srv.close()
+            say("  share mode %d: done" % share)
+    finally:
+        kz_batch_set_config(kz.ctx, cfg0)
+    for i in range(len(reqs)):
+        assert out[1][0][i] == out[2][0][i], i
+        assert np.array_equal(out[1][1][i][0], out[2][1][i][0]), i
+        assert np.array_equal(out[1][1][i][1], out[2][1][i][1]), i
+    check(reqs[::15], out[1][0][::15], "reuse")
+
+
+def test_server_resident_limit_and_configure(kz):
+    """Admission by the caller's resident bytes (rows, colours, masks)."""
+    from paper_2212_00574_amd.binding import kz_server_configure
+    say("server: resident-byte admission")
+    srv = Server(kz, arena_bytes=64 << 20, max_slots=8)
+    a = Req([40] * 5, 0.5, 43, 0)
+    b = Req([40] * 5, 0.5, 43, 1)
+    one = 2 * 8 * a.n * a.R + 5 * a.n
+    srv.configure(resident_limit=one + one // 2)        # room for one such request
+    huge = Req([200] * 4, 0.5, 43, 2)
+    with pytest.raises(KzError):
+        huge.submit(srv)                                 # alone beyond the limit
+    t1 = a.submit(srv)
+    assert t1 is not None
+    assert b.submit(srv) is None                         # the budget is held by the first
+    with pytest.raises(KzError):
+        kz_server_configure(srv.srv, resident_limit=0)   # only while nothing is admitted
+    r1 = wait(srv, t1)
+    t2 = b.submit(srv)                                   # the budget is back
+    assert t2 is not None
+    r2 = wait(srv, t2)
+    check([a, b], [r1, r2], "resident")
+    srv.configure()                                      # defaults again, no limit
+    t3 = huge.submit(srv)
+    assert t3 is not None
+    check([huge], [wait(srv, t3)], "huge")
+    with pytest.raises(KzError):
+        kz_server_configure(srv.srv, idle_us=-1)
+    srv.close()
+
+
+def test_server_large_requests_in_session_lane(kz):
+    """With the lane split above every request's size, graphs of 5600 and
+    8400 vertices run in the session lane (their passes shared by the
+    workgroups), beside small ones, and equal the oracle."""
+    say("server: large requests in the session lane")
+    srv = Server(kz, arena_bytes=2 << 30, max_slots=16)
+    srv.configure(split_n=40000, idle_us=200)
+    big = []
+    for sizes, p, gid in (([700] * 8, 0.06, 0), ([2100] * 4, 0.05, 3)):
+        g = inputs.make_graph(sizes, p, seed=12, gid=gid, plant=True, shuffle=False)
+        rows_np, col_np, lay = g.bitset()
+        rows = torch.from_numpy(rows_np.view(np.int64).reshape(-1).copy()).to(DEV)
+        colour = torch.from_numpy(col_np).to(DEV)
+        vmask = torch.empty(lay.n, dtype=torch.uint8, device=DEV)
+        emask = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+        t = srv.submit(rows, colour, len(sizes), vmask, emask)
+        assert t is not None
+        big.append((t, rows_np, col_np, len(sizes), vmask, emask, lay))
+    small = mixed_requests(10, seed=26)
+    res_small = run_all(srv, small)
+    for t, rows_np, col_np, k, vmask, emask, lay in big:
+        res = wait(srv, t)
+        ref = kernelize_bitset(rows_np, col_np, k)
+        assert res["rounds"] == ref["rounds"] and res["edge_tests"] == ref["edge_tests"]
+        assert res["surviving_edges"] == ref["surv_edges"]
+        assert np.array_equal(vmask.cpu().numpy(), ref["vmask"])
+        assert np.array_equal(emask.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R), ref["emask"])
+    check(small, res_small, "small")
+    srv.close()
+
+
+def test_server_one_slot_sequential_shared(kz):
+    """One slot, one request at a time, every pass shared, and a launch kept
+    alive across requests: each job starts in the slot the previous one just
+    left, while the workgroup that ended the previous job waits idle and
+    joins the new job's first pass.  Pass numbers continue across the jobs
+    of a slot, so it reloads the new job's layout; every result equals the
+    oracle."""
+    from paper_2212_00574_amd.binding import kz_batch_get_config, kz_batch_set_config
+    say("server: one slot, sequential requests, shared passes")
+    rng = np.random.default_rng(47)
+    reqs = []
+    for i in range(120):
+        k = int(rng.integers(3, 10))
+        reqs.append(Req(rng.integers(20, 120, size=k), float(rng.uniform(0.25, 0.75)), 47, i,
+                        plant=bool(rng.random() < 0.3)))
+    cfg0 = kz_batch_get_config(kz.ctx)
+    try:
+        kz_batch_set_config(kz.ctx, dict(cfg0, share=1))
+        srv = Server(kz, arena_bytes=16 << 20, max_slots=1)
+        srv.configure(idle_us=200000, lease_us=1000000)
+        res = []
+        for r in reqs:
+            t = r.submit(srv)
+            assert t is not None
+            res.append(wait(srv, t))
+        srv.close()
+    finally:
+        kz_batch_set_config(kz.ctx, cfg0)
+    check(reqs, res, "one slot")
+
+
+def test_server_done_queue(kz):
+    """kz_server_done hands back every finished request once, from both
+    lanes, and retires it."""
+    say("server: completion queue")
+    srv = Server(kz, arena_bytes=256 << 20, max_slots=16)
+    srv.configure(split_n=1000)                       # the larger ones take the single-graph lane
+    reqs = mixed_requests(30, seed=48) + [Req([300] * 4, 0.4, 48, 100 + i) for i in range(3)]
+    tickets = {}
+    for i, r in enumerate(reqs):
+        t = r.submit(srv)
+        while t is None:
+            for tk, res in srv.done(4):
+                tickets[tk] = (tickets[tk][0], res)
+            t = r.submit(srv)
+        tickets[t] = (i, None)
+    t0 = time.time()
+    while any(v[1] is None for v in tickets.values()):
+        for tk, res in srv.done(4):
+            assert tickets[tk][1] is None                 # once only
+            tickets[tk] = (tickets[tk][0], res)
+        assert time.time() - t0 < 60, "requests did not complete"
+    assert srv.done() == []
+    with pytest.raises(KzError):
+        srv.poll(next(iter(tickets)))                     # retired
+    res = [None] * len(reqs)
+    for i, r in tickets.values():
+        res[i] = r
+    check(reqs, res, "done queue")
+    srv.close()
