@@ -118,6 +118,19 @@ typedef struct kz_result {     /* host memory, filled on return            */
                                   edge in round r                           */
 } kz_result;
 
+/* The result of the asynchronous call, written by the device in stream
+ * order after every pass: device memory or pinned, device-mapped host
+ * memory. */
+typedef struct kz_out {
+  kz_result result;      /* as kz_kernelize reports it, for the passes run so
+                            far (status: input errors found in pass 1)      */
+  int32_t converged;     /* 1 once a pass removed nothing (the fixpoint) or
+                            pass 1 found an input error; later passes of
+                            the same run then do nothing                    */
+  int32_t pad;
+  int64_t last_removed;  /* vertices plus edges the latest pass removed     */
+} kz_out;
+
 typedef struct kz_ctx kz_ctx;
 
 /* Creates a context on HIP device `device`.  Returns KZ_OK or KZ_EHIP /
@@ -148,6 +161,32 @@ int kz_workspace_bytes(const kz_ctx *ctx, const kz_graph *g, int32_t k, size_t *
 int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k,
                  void *ws, size_t ws_bytes, uint8_t *vmask, void *emask,
                  void *stream, kz_result *res);
+
+/* The asynchronous form of kz_kernelize (section 4.2's pruning, repeated to
+ * the fixpoint): enqueues passes first_pass .. first_pass + npasses - 1 on
+ * `stream` and returns without waiting.  Every pass ends with a one-wave
+ * kernel that folds the pass's removals into the result and, at the first
+ * pass that removes nothing (or at pass 1 on an input error), marks the run
+ * converged; the kernels of later passes of the run then return at once.
+ * There is no host synchronisation inside, so the call can be captured in a
+ * HIP graph (it issues kernel launches only).
+ *   first_pass: 1 starts from the input (setup and validation included);
+ *               a larger value continues a run whose passes up to
+ *               first_pass - 1 were enqueued by earlier calls with the same
+ *               arguments and workspace;
+ *   npasses:    passes to enqueue (>= 1); a run needs rounds + 1 passes;
+ *   out:        NULL, or a kz_out in device memory or in pinned,
+ *               device-mapped host memory, written in stream order after
+ *               every pass (after the last call's work completes: the final
+ *               result when out->converged is 1, else the result so far).
+ * The masks hold the kernel once out->converged is 1 and status is KZ_OK
+ * (dense input: they are written only then).  Returns KZ_OK once enqueued,
+ * or a host-detectable error (KZ_EINVAL also for first_pass < 1 or
+ * npasses < 1) with nothing enqueued.  kz_kernelize is this call in chunks
+ * of passes, with one look at the result between chunks. */
+int kz_kernelize_async(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k,
+                       void *ws, size_t ws_bytes, uint8_t *vmask, void *emask,
+                       int32_t first_pass, int32_t npasses, void *stream, kz_out *out);
 
 /* The same as kz_kernelize, with the library's own workspace instead of a
  * caller's: for callers that cannot allocate device memory (code under HIP

@@ -18,7 +18,7 @@ KZ_OK, KZ_EINVAL, KZ_ECOLOUR, KZ_EILLEGAL, KZ_EASYM, KZ_ESELFLOOP = 0, -1, -2, -
 KZ_EWORKSPACE, KZ_ENOMEM, KZ_EHIP, KZ_EAGAIN = -6, -7, -8, -9
 KZ_DENSE_U8, KZ_BITSET_U64, KZ_CSR = 0, 1, 2
 
-EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_kernelize",
+EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_kernelize", "kz_kernelize_async",
             "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
             "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
@@ -79,6 +79,23 @@ class kz_request(C.Structure):
                 ("rows", C.c_void_p), ("colour", C.c_void_p), ("vmask", C.c_void_p), ("emask", C.c_void_p)]
 
 
+class kz_out(C.Structure):
+    _fields_ = [("result", kz_result), ("converged", C.c_int32), ("pad", C.c_int32), ("last_removed", C.c_int64)]
+
+
+KZ_OUT_BYTES = C.sizeof(kz_out)
+
+
+def kz_out_from_bytes(raw: bytes) -> dict:
+    """A kz_out read back from memory, as a dict (the result's fields plus
+    converged and last_removed)."""
+    o = kz_out.from_buffer_copy(raw)
+    d = o.result.as_dict()
+    d["converged"] = int(o.converged)
+    d["last_removed"] = int(o.last_removed)
+    return d
+
+
 class kz_server_config(C.Structure):
     _fields_ = [("split_n", C.c_int32), ("idle_us", C.c_int32), ("lease_us", C.c_int32), ("session_cus", C.c_int32),
                 ("workers", C.c_int32), ("partition", C.c_int32), ("resident_limit", C.c_size_t)]
@@ -118,6 +135,9 @@ def _load() -> C.CDLL:
     lib.kz_kernelize.restype = C.c_int
     lib.kz_kernelize.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, C.c_size_t, vp, vp, vp,
                                  C.POINTER(kz_result)]
+    lib.kz_kernelize_async.restype = C.c_int
+    lib.kz_kernelize_async.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, C.c_size_t, vp, vp, C.c_int32,
+                                       C.c_int32, vp, vp]
     lib.kz_kernelize_noalloc.restype = C.c_int
     lib.kz_kernelize_noalloc.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, vp, vp, C.POINTER(kz_result)]
     lib.kz_batch_workspace_bytes.restype = C.c_int
@@ -207,6 +227,17 @@ def kz_workspace_bytes(ctx: int, graph: kz_graph, k: int) -> int:
     if st != KZ_OK:
         raise KzError(st, "kz_workspace_bytes")
     return int(b.value)
+
+
+def kz_kernelize_async(ctx: int, graph: kz_graph, colour_ptr: int, k: int, ws_ptr: int, ws_bytes: int,
+                       vmask_ptr: int, emask_ptr: int, first_pass: int, npasses: int, stream: int,
+                       out_ptr: int | None) -> None:
+    """Enqueues passes [first_pass, first_pass + npasses); raises on a
+    host-detectable error (nothing enqueued then)."""
+    st = LIB.kz_kernelize_async(ctx, C.byref(graph), colour_ptr, int(k), ws_ptr, int(ws_bytes), vmask_ptr,
+                                emask_ptr, int(first_pass), int(npasses), stream, out_ptr)
+    if st != 0:
+        raise KzError(st, "kz_kernelize_async")
 
 
 def kz_kernelize(ctx: int, graph: kz_graph, colour_ptr: int, k: int, ws_ptr: int, ws_bytes: int,
@@ -504,6 +535,23 @@ class Kernelizer:
         if check and res.status != KZ_OK:
             raise KzError(res.status, "kz_kernelize")
         return res.as_dict()
+
+    def run_async(self, graph: kz_graph, colour: torch.Tensor, k: int, vmask: torch.Tensor,
+                  emask: torch.Tensor, out: torch.Tensor | None, first_pass: int = 1, npasses: int = 32,
+                  stream: torch.cuda.Stream | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+        """Enqueues passes [first_pass, first_pass + npasses) (no wait); `out`:
+        a uint8 device tensor of KZ_OUT_BYTES receiving the kz_out in stream
+        order.  Returns the workspace used (pass it again to continue)."""
+        if colour.dtype != torch.int32:
+            raise ValueError("colour must be int32")
+        if out is not None and out.numel() * out.element_size() < KZ_OUT_BYTES:
+            raise ValueError("out must hold a kz_out")
+        if ws is None:
+            ws = self.workspace(graph, k)
+        kz_kernelize_async(self.ctx, graph, _dev_ptr(colour), k, ws.data_ptr(), ws.numel(), _dev_ptr(vmask),
+                           _dev_ptr(emask), first_pass, npasses, _stream_handle(stream, self.device),
+                           None if out is None else out.data_ptr())
+        return ws
 
     def kernelize_dense(self, adj: torch.Tensor, colour: torch.Tensor, k: int, **kw):
         """(vmask u8[n], emask u8[n,n], result dict) for a dense uint8 adjacency."""

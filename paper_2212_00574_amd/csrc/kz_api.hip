@@ -6,6 +6,9 @@
 // read of the pass counters, until a pass removes nothing.
 #include <string.h>
 
+#include <algorithm>
+#include <climits>
+
 #include <mutex>
 #include <new>
 #include <vector>
@@ -163,18 +166,6 @@ kzi::WsSizes plan_sizes(const kz_graph *g, int32_t k, bool mfma) {
   return z;
 }
 
-int map_hdr_status(const kzi::Hdr &h) {
-  if (h.bad_colour) return KZ_ECOLOUR;
-  if (h.bad_layout) return KZ_EINVAL;
-  switch (h.prio) {
-    case kzi::P_EINVAL: return KZ_EINVAL;
-    case kzi::P_ESELFLOOP: return KZ_ESELFLOOP;
-    case kzi::P_EASYM: return KZ_EASYM;
-    case kzi::P_EILLEGAL: return KZ_EILLEGAL;
-    default: return KZ_OK;
-  }
-}
-
 int finish(kz_result *res, const kz_result &r) {
   if (res) *res = r;
   return r.status;
@@ -280,11 +271,12 @@ int batch_launch(kz_ctx *ctx, const kzi::BatchConfig &cfg, const kz_batch_graph 
 }
 
 // Sparse path: state in place in vmask / emask; every pass is vertex test,
-// edge test, apply, then the counter readback.
-int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, char *base,
-                  const kzi::WsSizes &z, uint8_t *vmask, uint8_t *emask, hipStream_t s, kz_result *res) {
-  kz_result r{};
-  r.status = KZ_EHIP;
+// edge test, apply, then the device-side pass end.  Enqueues setup and the
+// validating first sweep when first_pass is 1, then passes [first_pass,
+// first_pass + npasses); no host synchronisation.
+int enqueue_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, char *base,
+                const kzi::WsSizes &z, uint8_t *vmask, uint8_t *emask, int first_pass, int npasses,
+                hipStream_t s, kz_out *out) {
   kzi::Plan p{};
   p.hdr = (kzi::Hdr *)base;
   p.counts = (int *)(base + z.off_counts);
@@ -300,20 +292,16 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
   const int64_t *rp = g->row_ptr;
   const int32_t *ci = g->col_idx;
   const long long nnz = g->nnz;
-  {
-    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_setup(p, colour, 0, kzi::SETUP_CSR, s);
-  }
-  {
+  if (first_pass == 1) {
+    {
+      ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+      kzi::launch_setup(p, colour, 0, kzi::SETUP_CSR, s);
+    }
     // validation and pass 1's vertex test share one sweep over the rows
     ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
     kzi::launch_csr_first(p, rp, ci, nnz, colour, vmask, emask, s);
   }
-  if (hipGetLastError() != hipSuccess) return finish(res, r);
-  long long removed_v = 0, removed_e = 0, tests = 0, m = 0;
-  int rounds = 0, pass = 0;
-  for (;;) {
-    ++pass;
+  for (int pass = first_pass; pass < first_pass + npasses; ++pass) {
     const bool first = pass == 1;
     if (!first) {
       ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
@@ -327,45 +315,121 @@ int kernelize_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t
       ProfScope t(ctx, KZ_KERNEL_APPLY, s);
       kzi::launch_csr_apply(p, nnz, emask, s);
     }
-    if (hipGetLastError() != hipSuccess) return finish(res, r);
-    if (hipMemcpyAsync(ctx->pinned, p.hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return finish(res, r);
-    prof_collect(ctx);
-    const kzi::Hdr &h = *ctx->pinned;
-    if (first) {
-      // unequal counts of entries above and below the diagonal: some
-      // entry below it has no reverse
-      unsigned long long balance = 0;
-      for (int slot = 0; slot < kzi::kCtrSlots; ++slot) balance += h.ctr(1, slot, 3);
-      kzi::Hdr hs = h;
-      if (balance != 0 && hs.prio < kzi::P_EASYM) hs.prio = kzi::P_EASYM;
-      const int st = map_hdr_status(hs);
-      if (st != KZ_OK) {
-        r.status = st;
-        return finish(res, r);
-      }
-    }
-    unsigned long long c[3] = {0, 0, 0};
-    for (int slot = 0; slot < kzi::kCtrSlots; ++slot)
-      for (int j = 0; j < 3; ++j) c[j] += h.ctr(pass & 1, slot, j);
-    if (first) m = (long long)c[2];
-    tests += (long long)c[2];
-    removed_v += (long long)c[0];
-    removed_e += (long long)c[1];
-    if (c[0] + c[1] == 0) break;
-    ++rounds;
-    if (rounds > g->n + m + 1) return finish(res, r);  // cannot happen: every round removes something
+    kzi::launch_pass_end(p, pass, true, out, s);
   }
-  r.status = KZ_OK;
-  r.rounds = rounds;
-  r.equals_input = rounds == 0;
-  r.passes = pass;
-  r.surviving_vertices = g->n - removed_v;
-  r.surviving_edges = m - removed_e;
-  r.input_edges = m;
-  r.edge_tests = tests;
-  return finish(res, r);
+  return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
+}
+
+constexpr int kMaxChunk = 16;  // passes the blocking call enqueues between two looks at the result
+
+// Host-checkable errors of a single-graph call (nothing is enqueued when
+// one is found); the workspace plan and the edge path otherwise.
+int check_call(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, void *ws, size_t ws_bytes,
+               uint8_t *vmask, void *emask, kzi::WsSizes *z, bool *mfma) {
+  if (!ctx || !shape_ok(g, k)) return KZ_EINVAL;
+  const int n = g->n;
+  const bool dense = g->format == KZ_DENSE_U8;
+  const bool csr = g->format == KZ_CSR;
+  if (n == 0) return KZ_OK;
+  if (!colour || !vmask || !ws) return KZ_EINVAL;
+  if (!emask && !(csr && g->nnz == 0)) return KZ_EINVAL;
+  if (dense && !g->adj) return KZ_EINVAL;
+  if (g->format == KZ_BITSET_U64 && !g->rows) return KZ_EINVAL;
+  if (csr && (!g->row_ptr || (g->nnz > 0 && !g->col_idx))) return KZ_EINVAL;
+  if ((uintptr_t)ws % kAlign) return KZ_EINVAL;
+  *mfma = ctx->edge_path == KZ_EDGE_MFMA_I8 && !csr;
+  *z = plan_sizes(g, k, *mfma);
+  if (*mfma && z->Rmax > kzi::kMfMaxWords) return KZ_ETOOLARGE;
+  if (ws_bytes < z->total) return KZ_EWORKSPACE;
+  if (z->Tmax > 0x7fffffffLL) return KZ_EINVAL;
+  return KZ_OK;
+}
+
+// Enqueues setup (first_pass == 1) and passes [first_pass, first_pass +
+// npasses) of the single-graph path, each ended on the device by
+// k_pass_end, then (dense input) the output unpack, which writes only at
+// the fixpoint.  No host synchronisation: the whole call can be captured.
+int enqueue_passes(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, char *base,
+                   const kzi::WsSizes &z, bool mfma, uint8_t *vmask, void *emask, int first_pass, int npasses,
+                   hipStream_t s, kz_out *out) {
+  if (g->format == KZ_CSR)
+    return enqueue_csr(ctx, g, colour, k, base, z, vmask, (uint8_t *)emask, first_pass, npasses, s, out);
+  const int n = g->n;
+  const bool dense = g->format == KZ_DENSE_U8;
+  kzi::Plan p{};
+  p.hdr = (kzi::Hdr *)base;
+  p.counts = (int *)(base + z.off_counts);
+  p.coff = (int *)(base + z.off_coff);
+  p.soff = (int *)(base + z.off_soff);
+  p.bcls = (int *)(base + z.off_bcls);
+  p.bstart = (int *)(base + z.off_bstart);
+  p.blen = (int *)(base + z.off_blen);
+  p.hist = (int *)(base + z.off_hist);
+  p.perm = (int *)(base + z.off_perm);
+  p.inv = (int *)(base + z.off_inv);
+  p.scls = (int *)(base + z.off_scls);
+  p.valive = dense ? (uint8_t *)(base + z.off_valive) : vmask;
+  p.touched[0] = (uint8_t *)(base + z.off_touched0);
+  p.touched[1] = (uint8_t *)(base + z.off_touched1);
+  p.btouched[0] = (uint8_t *)(base + z.off_bt0);
+  p.btouched[1] = (uint8_t *)(base + z.off_bt1);
+  p.tiles = (int2 *)(base + z.off_tiles);
+  p.packed = (uint64_t *)(base + z.off_packed);
+  p.spare = (uint64_t *)(base + z.off_spare);
+  p.F = (uint64_t *)(base + z.off_F);
+  p.S = (uint64_t *)(base + z.off_S);
+  p.fb = (uint64_t *)(base + z.off_fb);
+  p.n = n;
+  p.k = k;
+  p.Rmax = z.Rmax;
+  p.nchunks = z.nchunks;
+  p.kF = kzi::f_stride(k);
+  p.Tmax = z.Tmax;
+
+  // Pass 1 reads the input rows (bitset: the caller's; dense: packed here)
+  // and writes the whole state after round 1 into `cur`; later passes work
+  // in place on `cur`, staging changed tiles in `scratch`.
+  const uint64_t *in_rows = dense ? p.packed : g->rows;
+  uint64_t *cur = dense ? p.spare : (uint64_t *)emask;
+  uint64_t *scratch = dense ? p.packed : p.spare;
+  if (first_pass == 1) {
+    {
+      ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+      kzi::launch_setup(p, colour, g->row_words, dense ? kzi::SETUP_DENSE : kzi::SETUP_BITSET, s);
+    }
+    if (dense) {
+      {
+        ProfScope t(ctx, KZ_KERNEL_SETUP, s);
+        kzi::launch_rank(p, colour, s);
+      }
+      ProfScope t(ctx, KZ_KERNEL_PACK, s);
+      kzi::launch_pack_dense(p, g->adj, colour, p.packed, s);
+    }
+  }
+  const int *scls = dense ? p.scls : colour;
+  for (int pass = first_pass; pass < first_pass + npasses; ++pass) {
+    const bool first = pass == 1;
+    const uint64_t *src = first ? in_rows : cur;
+    {
+      ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
+      kzi::launch_vertex_pass(p, scls, src, cur, pass, first, dense ? 0 : g->row_words, s);
+    }
+    {
+      ProfScope t(ctx, KZ_KERNEL_EDGE, s);
+      if (mfma) kzi::launch_edge_pass_mfma(p, src, first ? cur : scratch, p.fb, pass, first, s);
+      else kzi::launch_edge_pass(p, src, first ? cur : scratch, pass, first, s);
+    }
+    if (!first) {
+      ProfScope t(ctx, KZ_KERNEL_APPLY, s);
+      kzi::launch_apply(p, scratch, cur, s);
+    }
+    kzi::launch_pass_end(p, pass, false, out, s);
+  }
+  if (dense) {
+    ProfScope t(ctx, KZ_KERNEL_UNPACK, s);
+    kzi::launch_unpack_dense(p, colour, cur, vmask, (uint8_t *)emask, s);
+  }
+  return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
 }
 
 }  // namespace
@@ -595,155 +659,60 @@ int kz_workspace_bytes(const kz_ctx *ctx, const kz_graph *g, int32_t k, size_t *
 int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, void *ws,
                  size_t ws_bytes, uint8_t *vmask, void *emask, void *stream, kz_result *res) {
   kz_result r{};
-  r.status = KZ_EINVAL;
-  if (!ctx || !shape_ok(g, k)) return finish(res, r);
-  const int n = g->n;
-  const bool dense = g->format == KZ_DENSE_U8;
-  const bool csr = g->format == KZ_CSR;
-  if (n > 0) {
-    if (!colour || !vmask || !ws) return finish(res, r);
-    if (!emask && !(csr && g->nnz == 0)) return finish(res, r);
-    if (dense && !g->adj) return finish(res, r);
-    if (g->format == KZ_BITSET_U64 && !g->rows) return finish(res, r);
-    if (csr && (!g->row_ptr || (g->nnz > 0 && !g->col_idx))) return finish(res, r);
-    if ((uintptr_t)ws % kAlign) return finish(res, r);
-  }
-  if (n == 0) {
-    r.status = KZ_OK;
-    r.equals_input = 1;
+  kzi::WsSizes z{};
+  bool mfma = false;
+  r.status = check_call(ctx, g, colour, k, ws, ws_bytes, vmask, emask, &z, &mfma);
+  if (r.status != KZ_OK || g->n == 0) {
+    if (r.status == KZ_OK) r.equals_input = 1;
     return finish(res, r);
   }
-  const bool mfma = ctx->edge_path == KZ_EDGE_MFMA_I8 && !csr;
-  const kzi::WsSizes z = plan_sizes(g, k, mfma);
-  if (mfma && z.Rmax > kzi::kMfMaxWords) {
-    r.status = KZ_ETOOLARGE;
-    return finish(res, r);
-  }
-  if (ws_bytes < z.total) {
-    r.status = KZ_EWORKSPACE;
-    return finish(res, r);
-  }
-  if (z.Tmax > 0x7fffffffLL) return finish(res, r);
   r.status = KZ_EHIP;
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(res, r);
   hipStream_t s = (hipStream_t)stream;
-
-  if (csr) return kernelize_csr(ctx, g, colour, k, (char *)ws, z, vmask, (uint8_t *)emask, s, res);
-
-  char *base = (char *)ws;
-  kzi::Plan p{};
-  p.hdr = (kzi::Hdr *)base;
-  p.counts = (int *)(base + z.off_counts);
-  p.coff = (int *)(base + z.off_coff);
-  p.soff = (int *)(base + z.off_soff);
-  p.bcls = (int *)(base + z.off_bcls);
-  p.bstart = (int *)(base + z.off_bstart);
-  p.blen = (int *)(base + z.off_blen);
-  p.hist = (int *)(base + z.off_hist);
-  p.perm = (int *)(base + z.off_perm);
-  p.inv = (int *)(base + z.off_inv);
-  p.scls = (int *)(base + z.off_scls);
-  p.valive = dense ? (uint8_t *)(base + z.off_valive) : vmask;
-  p.touched[0] = (uint8_t *)(base + z.off_touched0);
-  p.touched[1] = (uint8_t *)(base + z.off_touched1);
-  p.btouched[0] = (uint8_t *)(base + z.off_bt0);
-  p.btouched[1] = (uint8_t *)(base + z.off_bt1);
-  p.tiles = (int2 *)(base + z.off_tiles);
-  p.packed = (uint64_t *)(base + z.off_packed);
-  p.spare = (uint64_t *)(base + z.off_spare);
-  p.F = (uint64_t *)(base + z.off_F);
-  p.S = (uint64_t *)(base + z.off_S);
-  p.fb = (uint64_t *)(base + z.off_fb);
-  p.n = n;
-  p.k = k;
-  p.Rmax = z.Rmax;
-  p.nchunks = z.nchunks;
-  p.kF = kzi::f_stride(k);
-  p.Tmax = z.Tmax;
-
-  // Pass 1 reads the input rows (bitset: the caller's; dense: packed here)
-  // and writes the whole state after round 1 into `cur`; later passes work
-  // in place on `cur`, staging changed tiles in `scratch`.
-  const uint64_t *in_rows = dense ? p.packed : g->rows;
-  uint64_t *cur = dense ? p.spare : (uint64_t *)emask;
-  uint64_t *scratch = dense ? p.packed : p.spare;
-  {
-    ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-    kzi::launch_setup(p, colour, g->row_words, dense ? kzi::SETUP_DENSE : kzi::SETUP_BITSET, s);
-  }
-  if (dense) {
-    {
-      ProfScope t(ctx, KZ_KERNEL_SETUP, s);
-      kzi::launch_rank(p, colour, s);
-    }
-    ProfScope t(ctx, KZ_KERNEL_PACK, s);
-    kzi::launch_pack_dense(p, g->adj, colour, p.packed, s);
-  }
-  if (hipGetLastError() != hipSuccess) return finish(res, r);
-
-  const int *scls = dense ? p.scls : colour;
-  long long removed_v = 0, removed_e = 0, tests = 0, m = 0;
-  int rounds = 0, pass = 0;
+  // The asynchronous passes in chunks, with one look at the device's result
+  // per chunk: one pass at a time while passes remove much, longer chunks
+  // (the surplus passes do nothing) through the tail of a cascade.
+  const kzi::Hdr *hdr = (const kzi::Hdr *)ws;
+  int next = 1, chunk = 1;
   for (;;) {
-    ++pass;
-    const bool first = pass == 1;
-    const uint64_t *src = first ? in_rows : cur;
-    {
-      ProfScope t(ctx, KZ_KERNEL_VERTEX, s);
-      kzi::launch_vertex_pass(p, scls, src, cur, pass, first, dense ? 0 : g->row_words, s);
-    }
-    {
-      ProfScope t(ctx, KZ_KERNEL_EDGE, s);
-      if (mfma) kzi::launch_edge_pass_mfma(p, src, first ? cur : scratch, p.fb, pass, first, s);
-      else kzi::launch_edge_pass(p, src, first ? cur : scratch, pass, first, s);
-    }
-    if (!first) {
-      ProfScope t(ctx, KZ_KERNEL_APPLY, s);
-      kzi::launch_apply(p, scratch, cur, s);
-    }
-    if (hipGetLastError() != hipSuccess) return finish(res, r);
-    if (hipMemcpyAsync(ctx->pinned, p.hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (enqueue_passes(ctx, g, colour, k, (char *)ws, z, mfma, vmask, emask, next, chunk, s, nullptr) != KZ_OK)
+      return finish(res, r);
+    if (hipMemcpyAsync(ctx->pinned, hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return finish(res, r);
     prof_collect(ctx);
-    const kzi::Hdr &h = *ctx->pinned;
-    if (first) {
-      const int st = map_hdr_status(h);
-      if (st != KZ_OK) {
-        r.status = st;
-        return finish(res, r);
-      }
+    const kz_out &o = ctx->pinned->out;
+    if (o.converged) {
+      r = o.result;
+      break;
     }
-    unsigned long long c[3] = {0, 0, 0};
-    for (int slot = 0; slot < kzi::kCtrSlots; ++slot)
-      for (int j = 0; j < 3; ++j) c[j] += h.ctr(pass & 1, slot, j);
-    if (first) m = (long long)c[2];
-    tests += (long long)c[2];
-    removed_v += (long long)c[0];
-    removed_e += (long long)c[1];
-    if (c[0] + c[1] == 0) break;
-    ++rounds;
-    if (rounds > n + m + 1) return finish(res, r);  // cannot happen: every round removes something
+    next += chunk;
+    // every productive pass removes something: a run cannot outlast n + m + 1 passes
+    if (next > (long long)g->n + o.result.input_edges + 2) return finish(res, r);
+    chunk = o.last_removed * 256 < o.result.input_edges + g->n ? std::min(2 * chunk, kMaxChunk) : 1;
   }
-  if (dense) {
-    ProfScope t(ctx, KZ_KERNEL_UNPACK, s);
-    kzi::launch_unpack_dense(p, colour, cur, vmask, (uint8_t *)emask, s);
-  }
-  if (hipGetLastError() != hipSuccess) return finish(res, r);
-  if (!ctx->pending.empty()) {
-    if (hipStreamSynchronize(s) != hipSuccess) return finish(res, r);
-    prof_collect(ctx);
-  }
-
-  r.status = KZ_OK;
-  r.rounds = rounds;
-  r.equals_input = rounds == 0;
-  r.passes = pass;
-  r.surviving_vertices = n - removed_v;
-  r.surviving_edges = m - removed_e;
-  r.input_edges = m;
-  r.edge_tests = tests;
   return finish(res, r);
+}
+
+int kz_kernelize_async(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, void *ws,
+                       size_t ws_bytes, uint8_t *vmask, void *emask, int32_t first_pass, int32_t npasses,
+                       void *stream, kz_out *out) {
+  kzi::WsSizes z{};
+  bool mfma = false;
+  const int st = check_call(ctx, g, colour, k, ws, ws_bytes, vmask, emask, &z, &mfma);
+  if (st != KZ_OK) return st;
+  if (first_pass < 1 || npasses < 1 || first_pass > INT32_MAX - npasses) return KZ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return KZ_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (g->n == 0) {
+    if (!out) return KZ_OK;
+    kz_out o{};
+    o.result.equals_input = 1;
+    o.converged = 1;
+    kzi::launch_write_out(out, o, s);
+    return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
+  }
+  return enqueue_passes(ctx, g, colour, k, (char *)ws, z, mfma, vmask, emask, first_pass, npasses, s, out);
 }
 
 }  // extern "C"

@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) k_csr_vertex(Plan p, const int64_t *rp, c
                                                     const int *colour, uint8_t *vmask,
                                                     const uint8_t *emask, int pass) {
   Hdr *h = p.hdr;
-  if (csr_bad(h) || h->prio) return;
+  if (csr_bad(h) || h->prio || h->done) return;
   const int n = p.n, k = p.k;
   const int cur = pass & 1, nxt = cur ^ 1;
   {
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) k_csr_edge(Plan p, const int64_t *rp, con
                                                   long long nnz, const int *colour, const uint8_t *emask,
                                                   int pass) {
   Hdr *h = p.hdr;
-  if (csr_bad(h) || h->prio) return;
+  if (csr_bad(h) || h->prio || h->done) return;
   const int k = p.k;
   const int cur = pass & 1, nxt = cur ^ 1;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(256) k_csr_edge(Plan p, const int64_t *rp, con
 // has read the old masks).  Four entries per thread.
 __global__ void __launch_bounds__(256) k_csr_apply(Plan p, long long nnz, uint8_t *emask) {
   const Hdr *h = p.hdr;
-  if (csr_bad(h) || h->prio) return;
+  if (csr_bad(h) || h->prio || h->done) return;
   const long long i0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {

@@ -69,6 +69,11 @@ struct Hdr {
   int bad_layout;        // stage 1: bitset colours unsorted / row stride mismatch
   int R;                 // words per row == number of 64-slot blocks
   int n, k, pad;
+  // the pass loop's state on the device (k_pass_end): set once a pass
+  // removed nothing or pass 1 found an input error; every later pass kernel
+  // of the run then returns at once
+  int done, pad2;
+  kz_out out;  // the result so far
 };
 
 // Device pointers of one kernelization (workspace carve-up + caller buffers).
@@ -145,6 +150,11 @@ void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pas
 void launch_edge_pass_mfma(const Plan &p, const uint64_t *src, uint64_t *dst, uint64_t *fb, int pass, bool first,
                            hipStream_t s);
 void launch_apply(const Plan &p, const uint64_t *scratch, uint64_t *cur, hipStream_t s);
+// Ends pass `pass` on the device (one wave): folds its counters into the
+// header's result, sets `done` at the fixpoint or on an input error, and
+// copies the result to `out` when it is not null.
+void launch_pass_end(const Plan &p, int pass, bool csr, kz_out *out, hipStream_t s);
+void launch_write_out(kz_out *out, const kz_out &v, hipStream_t s);
 void launch_unpack_dense(const Plan &p, const int *colour, const uint64_t *cur, uint8_t *vmask,
                          uint8_t *emask, hipStream_t s);
 

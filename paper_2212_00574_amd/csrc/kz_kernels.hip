@@ -88,6 +88,8 @@ __global__ void __launch_bounds__(kSetupThreads) k_setup(Plan p, const int *colo
     h->R = 0;
     h->n = n;
     h->k = k;
+    h->done = 0;
+    h->out = kz_out{};
     s_bad_colour = 0;
     s_bad_layout = 0;
     carry_a = 0;
@@ -321,7 +323,7 @@ __global__ void __launch_bounds__(256) k_pack_dense(Plan p, const uint8_t *adj, 
 __global__ void __launch_bounds__(256) k_vertex(Plan p, const int *scls, const uint64_t *__restrict__ src,
                                                 int pass) {
   Hdr *h = p.hdr;
-  if (stage1_bad(h)) return;
+  if (stage1_bad(h) || h->done) return;
   const int R = h->R, n = p.n, k = p.k;
   const int cur = pass & 1, nxt = cur ^ 1;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -629,7 +631,7 @@ __device__ __forceinline__ bool tile_begin(const Plan &p, const uint64_t *__rest
   tri_decode(t, p.Rmax, T.X, T.Y);
   // one round of independent loads (X, Y < Rmax: the block table is in
   // bounds even where this call's layout is shorter or invalid)
-  const int bad = h->bad_colour | h->bad_layout, R = h->R;
+  const int bad = h->bad_colour | h->bad_layout | h->done, R = h->R;
   T.cx = p.bcls[T.X];
   T.cy = p.bcls[T.Y];
   T.xs = p.bstart[T.X];
@@ -850,7 +852,7 @@ template <bool FIRST>
 __global__ void __launch_bounds__(kMfThreads) k_mfma_count(Plan p, const uint64_t *__restrict__ src,
                                                           uint64_t *__restrict__ fb, int pass) {
   Hdr *h = p.hdr;
-  if (stage1_bad(h)) return;
+  if (stage1_bad(h) || h->done) return;
   const int R = h->R;
   int X, Y;
   tri_decode(xcd_remap(blockIdx.x, gridDim.x), p.Rmax, X, Y);
@@ -985,7 +987,7 @@ __global__ void __launch_bounds__(kMfThreads) k_mfma_count(Plan p, const uint64_
 __global__ void __launch_bounds__(128) k_apply(Plan p, const uint64_t *__restrict__ scratch,
                                                uint64_t *__restrict__ cur) {
   const Hdr *h = p.hdr;
-  if (stage1_bad(h)) return;
+  if (stage1_bad(h) || h->done) return;
   const int R = h->R;
   const int cnt = h->tile_count;
   for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
@@ -1006,7 +1008,8 @@ __global__ void __launch_bounds__(128) k_apply(Plan p, const uint64_t *__restric
 __global__ void __launch_bounds__(256) k_unpack_dense(Plan p, const int *colour, const uint64_t *cur,
                                                       uint8_t *vmask, uint8_t *emask, int use_lds) {
   const Hdr *h = p.hdr;
-  if (stage1_bad(h)) return;
+  // the caller's masks are written once, at the fixpoint
+  if (stage1_bad(h) || !h->done || h->out.result.status != KZ_OK) return;
   extern __shared__ unsigned long long srow[];
   const int u = blockIdx.x, t = threadIdx.x;
   const int R = h->R, n = p.n;
@@ -1106,6 +1109,77 @@ void launch_edge_pass_mfma(const Plan &p, const uint64_t *src, uint64_t *dst, ui
     hipLaunchKernelGGL((k_mfma_count<false>), grid, dim3(kMfThreads), 0, s, p, src, fb, pass);
     hipLaunchKernelGGL((k_edge_mf<false>), tgrid, dim3(kEdgeThreads), 0, s, p, src, dst, pass, (const uint64_t *)fb);
   }
+}
+
+// End of pass `pass` (one wave): the pass's counters, summed over their
+// slots, fold into the result; the run is done at the first pass that
+// removes nothing (the fixpoint of section 4.2's iterated pruning), or at
+// pass 1 when validation found an input error.
+__global__ void __launch_bounds__(64) k_pass_end(Plan p, int pass, int csr, kz_out *out) {
+  Hdr *h = p.hdr;
+  if (h->done) return;
+  const int lane = threadIdx.x, par = pass & 1;
+  unsigned long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  if (lane < kCtrSlots) {
+    c0 = h->ctr(par, lane, 0);
+    c1 = h->ctr(par, lane, 1);
+    c2 = h->ctr(par, lane, 2);
+    c3 = h->ctr(1, lane, 3);  // CSR: entries above minus below the diagonal, with pass 1's counters
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c0 += (unsigned long long)__shfl_xor((long long)c0, off, kWave);
+    c1 += (unsigned long long)__shfl_xor((long long)c1, off, kWave);
+    c2 += (unsigned long long)__shfl_xor((long long)c2, off, kWave);
+    c3 += (unsigned long long)__shfl_xor((long long)c3, off, kWave);
+  }
+  if (lane != 0) return;
+  kz_out o = h->out;
+  int st = KZ_OK;
+  if (pass == 1) {
+    int prio = h->prio;
+    if (csr && c3 != 0 && prio < P_EASYM) prio = P_EASYM;  // an entry without its reverse
+    st = h->bad_colour           ? KZ_ECOLOUR
+         : h->bad_layout         ? KZ_EINVAL
+         : prio == P_EINVAL      ? KZ_EINVAL
+         : prio == P_ESELFLOOP   ? KZ_ESELFLOOP
+         : prio == P_EASYM       ? KZ_EASYM
+         : prio == P_EILLEGAL    ? KZ_EILLEGAL
+                                 : KZ_OK;
+  }
+  if (st != KZ_OK) {
+    o = kz_out{};
+    o.result.status = st;
+    o.converged = 1;
+  } else {
+    if (pass == 1) {
+      // pass 1 tests every edge once: the input's edge count
+      o.result.input_edges = (long long)c2;
+      o.result.surviving_edges = (long long)c2;
+      o.result.surviving_vertices = p.n;
+    }
+    o.result.edge_tests += (long long)c2;
+    o.result.surviving_vertices -= (long long)c0;
+    o.result.surviving_edges -= (long long)c1;
+    o.result.passes = pass;
+    o.last_removed = (long long)(c0 + c1);
+    if (c0 + c1 == 0) o.converged = 1;
+    else o.result.rounds += 1;
+    o.result.equals_input = o.result.rounds == 0;
+  }
+  h->out = o;
+  if (o.converged) h->done = 1;
+  if (out) *out = o;
+}
+
+__global__ void k_write_out(kz_out *out, kz_out v) { *out = v; }
+
+void launch_pass_end(const Plan &p, int pass, bool csr, kz_out *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(64), 0, s, p, pass, csr ? 1 : 0, out);
+}
+
+void launch_write_out(kz_out *out, const kz_out &v, hipStream_t s) {
+  hipLaunchKernelGGL(k_write_out, dim3(1), dim3(1), 0, s, out, v);
 }
 
 void launch_apply(const Plan &p, const uint64_t *scratch, uint64_t *cur, hipStream_t s) {

@@ -29,7 +29,7 @@ def test_header_declares_the_entry_points():
                           "kz_batch_workspace_bytes", "kz_clique_workspace_bytes", "kz_create", "kz_destroy",
                           "kz_dom_workspace_bytes",
                           "kz_dominance", "kz_find_clique", "kz_gen_bitset",
-                          "kz_kernelize", "kz_kernelize_batch", "kz_kernelize_noalloc", "kz_profile_enable",
+                          "kz_kernelize", "kz_kernelize_async", "kz_kernelize_batch", "kz_kernelize_noalloc", "kz_profile_enable",
                           "kz_profile_read",
                           "kz_server_configure", "kz_server_create", "kz_server_destroy", "kz_server_done", "kz_server_fixed_bytes",
                           "kz_server_poll",
