@@ -15,6 +15,7 @@ constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kBlk = 64;           // slots per block == bits per word
 constexpr int kEdgeThreads = 256;  // edge pass: 4 waves per workgroup
 constexpr long long kEdgeWaveTiles = 16384;  // tiles from which the edge pass gives a tile one wave, not four
+constexpr int kEdgeSquare = 16;              // then the side of its squares of tiles (in blocks)
 constexpr int kMfThreads = 256;    // MFMA count path: 4 waves per 128x128 group tile
 constexpr int kMfMaxWords = 2048;  // MFMA count path: row words it supports
 constexpr int kRankChunk = 256;    // vertices per stable-partition chunk
@@ -108,6 +109,11 @@ struct Plan {
   int n, k, Rmax, nchunks;
   int kF;            // row stride of F: k rounded up to the edge pass's class chunk
   long long Tmax;    // Rmax*(Rmax-1)/2
+  // the edge pass's tile order (set by its launcher): 0 or 1, row-major over
+  // the triangle of block pairs; else squares of Sq x Sq block pairs, the
+  // squares row-major over the triangle of squares, Tcells cells in all
+  int Sq;
+  long long Tcells;
 };
 
 // Classes per chunk of the bit-row edge test (the rows' first words of a

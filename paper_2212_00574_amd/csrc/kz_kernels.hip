@@ -64,6 +64,29 @@ __device__ __forceinline__ void tri_decode(long long t, int NB, int &X, int &Y) 
   Y = (int)(t - start(x) + x + 1);
 }
 
+// Tile t of the edge pass.  Row-major over the triangle (p.Sq <= 1), or in
+// squares of Sq x Sq block pairs: the squares (I, J), I <= J, row-major over
+// the triangle of squares with its diagonal, the cells of a square
+// row-major.  The tiles a chip's XCD has in flight then come from a few
+// squares, whose rows and first words fit its L2, instead of from one or
+// two block rows paired with every other block.  Cells with X >= Y or
+// Y >= NB are not tiles: false.
+__device__ __forceinline__ bool tile_decode(long long t, int NB, int Sq, int &X, int &Y) {
+  if (Sq <= 1) {
+    tri_decode(t, NB, X, Y);
+    return true;
+  }
+  const int NS = (NB + Sq - 1) / Sq;
+  const long long sq = t / ((long long)Sq * Sq);
+  const int cell = (int)(t - sq * Sq * Sq);
+  int I, J;
+  tri_decode(sq, NS + 1, I, J);  // (I, J+1) over NS+1 blocks: I <= J over NS
+  J -= 1;
+  X = I * Sq + cell / Sq;
+  Y = J * Sq + cell % Sq;
+  return X < Y && Y < NB;
+}
+
 // ---------------------------------------------------------------- setup
 
 // One workgroup: zeroes the header, counts the classes (stage-1 colour
@@ -627,8 +650,8 @@ __device__ __forceinline__ bool tile_begin(const Plan &p, const uint64_t *__rest
   const Hdr *h = p.hdr;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const long long t = xcd_remap(blockIdx.x, gridDim.x) * (kTileWaves / TW) + wid / TW;
-  if (t >= p.Tmax) return false;
-  tri_decode(t, p.Rmax, T.X, T.Y);
+  if (t >= (p.Sq > 1 ? p.Tcells : p.Tmax)) return false;
+  if (!tile_decode(t, p.Rmax, p.Sq, T.X, T.Y)) return false;
   // one round of independent loads (X, Y < Rmax: the block table is in
   // bounds even where this call's layout is shorter or invalid)
   const int bad = h->bad_colour | h->bad_layout | h->done, R = h->R;
@@ -1063,13 +1086,22 @@ void launch_vertex_pass(const Plan &p, const int *scls, const uint64_t *src, uin
     hipLaunchKernelGGL(k_vertex, grid, dim3(256), 0, s, p, scls, src, pass);
 }
 
-void launch_edge_pass(const Plan &p, const uint64_t *src, uint64_t *dst, int pass, bool first, hipStream_t s) {
-  if (p.Tmax <= 0) return;
+void launch_edge_pass(const Plan &plan, const uint64_t *src, uint64_t *dst, int pass, bool first,
+                      hipStream_t s) {
+  if (plan.Tmax <= 0) return;
+  Plan p = plan;
   const uint64_t *F = p.F, *S = p.S;
   // a wave per tile when there are tiles enough to fill the chip many times
   // over, else a workgroup per tile
   const bool wide = p.Tmax < kEdgeWaveTiles;
-  const dim3 grid((unsigned)(wide ? p.Tmax : (p.Tmax + kTileWaves - 1) / kTileWaves));
+  // many tiles: in squares of kEdgeSquare x kEdgeSquare block pairs
+  p.Sq = wide ? 1 : kEdgeSquare;
+  if (p.Sq > 1) {
+    const long long NS = (p.Rmax + p.Sq - 1) / p.Sq;
+    p.Tcells = NS * (NS + 1) / 2 * p.Sq * p.Sq;
+  }
+  const long long cells = p.Sq > 1 ? p.Tcells : p.Tmax;
+  const dim3 grid((unsigned)(wide ? cells : (cells + kTileWaves - 1) / kTileWaves));
   // classes per chunk: edge_chunk(k), which F's row stride is a multiple of
 #define KZ_EDGE(FI, KC)                                                                                       \
   do {                                                                                                        \
