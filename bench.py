@@ -38,9 +38,11 @@ import time
 import numpy as np
 
 # The serving workload runs the session lane, six single-graph workers and
-# the caller's stream at once: give each stream a hardware queue of its own
-# (HIP reads this when it starts, before any GPU call).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# the caller's stream at once, after the other workloads have made streams
+# of their own: give each stream a hardware queue of its own (HIP reads this
+# when it starts, before any GPU call; streams beyond it share queues, and a
+# stream that shares the session launch's queue waits for the launch).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -95,7 +97,7 @@ def parse(argv=None):
                     help="c5: requests of at least this many vertices take the single-graph lane")
     ap.add_argument("--idle-us", type=int, default=SERVE_IDLE_US, help="c5: a session launch ends after this idle time")
     ap.add_argument("--session-cus", type=int, default=0, help="c5: compute units of a session launch (0: 3/16)")
-    ap.add_argument("--lease-us", type=int, default=0, help="c5: session workgroup lease (0: the server's 50 ms)")
+    ap.add_argument("--lease-us", type=int, default=0, help="c5: session workgroup lease (0: the server's 10 ms)")
     ap.add_argument("--workers", type=int, default=SERVE_WORKERS,
                     help="c5: single-graph lane workers (requests of that lane in flight at once)")
     ap.add_argument("--resident-gib", type=float, default=SERVE_RESIDENT_GIB,
@@ -774,7 +776,7 @@ def run_serve(args):
             "ms_per_request": closed_s * 1e3 / N,
             "config": {"workload": "c5: " + WORKLOADS["c5"], "requests": N, "seed": args.seed,
                        "split_n": args.split_n, "idle_us": args.idle_us, "resident_limit_bytes": resident,
-                       "session_cus": args.session_cus or "3/16 of the device", "lease_us": args.lease_us or 50000,
+                       "session_cus": args.session_cus or "3/16 of the device", "lease_us": args.lease_us or 10000,
                        "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
                        "workers": args.workers,
                        "max_slots": 512,
@@ -1111,10 +1113,14 @@ def main():
     elif w == "colours":
         out = run_colours(args)
     else:
+        # serving first: its streams then take hardware queues before the
+        # other workloads' streams do (a stream that shares the running
+        # session launch's queue waits for that launch)
+        serve = run_serve(args) if args.workload == "headline" else None
         out = run_single(args, w, cpu_proc)
         if args.workload == "headline":
             out["batch"] = run_batch(args)
-            out["serve"] = run_serve(args)
+            out["serve"] = serve
             out["dominance"] = run_dom(args, dom_proc)
             out["clique"] = run_clique(args)
             out["struction"] = run_struction(args)

@@ -319,7 +319,9 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
  * lane.  The process then has workers + 2 streams of its own besides the
  * caller's; with fewer hardware queues than streams (HIP's
  * GPU_MAX_HW_QUEUES, 4 by default) streams share queues, and a short
- * kernel can wait behind a long one of another lane.
+ * kernel can wait behind a long one of another lane; work on a stream that
+ * shares the session launch's queue (the caller's input stream, say) waits
+ * for that launch to end, up to lease_us.
  *
  * A request is a KZ_BITSET_U64 graph in caller-owned device buffers (vmask
  * and emask 128-byte aligned, else KZ_EINVAL); results are the same as
@@ -375,7 +377,7 @@ typedef struct kz_server_config {
   int32_t idle_us;        /* a session launch ends after this long without
                              work, in microseconds (0 = 20000; at most 1e6)  */
   int32_t lease_us;       /* a session workgroup takes no new request this
-                             long after it started (0 = 50000; at most 1e6)  */
+                             long after it started (0 = 10000; at most 1e6)  */
   int32_t session_cus;    /* compute units a session launch fills, up to the
                              device's (0 = 3/16 of them)                     */
   int32_t workers;        /* single-graph lane: requests in flight at once,

@@ -320,7 +320,8 @@ int enqueue_csr(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k
   return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
 }
 
-constexpr int kMaxChunk = 16;  // passes the blocking call enqueues between two looks at the result
+constexpr int kMaxChunk = 16;      // passes the blocking call enqueues between two looks at the result
+constexpr int kSinglePasses = 8;   // ... one at a time up to this pass
 
 // Host-checkable errors of a single-graph call (nothing is enqueued when
 // one is found); the workspace plan and the edge path otherwise.
@@ -351,7 +352,7 @@ int check_call(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k,
 // the fixpoint.  No host synchronisation: the whole call can be captured.
 int enqueue_passes(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t k, char *base,
                    const kzi::WsSizes &z, bool mfma, uint8_t *vmask, void *emask, int first_pass, int npasses,
-                   hipStream_t s, kz_out *out) {
+                   bool unpack, hipStream_t s, kz_out *out) {
   if (g->format == KZ_CSR)
     return enqueue_csr(ctx, g, colour, k, base, z, vmask, (uint8_t *)emask, first_pass, npasses, s, out);
   const int n = g->n;
@@ -425,7 +426,7 @@ int enqueue_passes(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_
     }
     kzi::launch_pass_end(p, pass, false, out, s);
   }
-  if (dense) {
+  if (dense && unpack) {
     ProfScope t(ctx, KZ_KERNEL_UNPACK, s);
     kzi::launch_unpack_dense(p, colour, cur, vmask, (uint8_t *)emask, s);
   }
@@ -670,12 +671,15 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
   if (hipSetDevice(ctx->device) != hipSuccess) return finish(res, r);
   hipStream_t s = (hipStream_t)stream;
   // The asynchronous passes in chunks, with one look at the device's result
-  // per chunk: one pass at a time while passes remove much, longer chunks
-  // (the surplus passes do nothing) through the tail of a cascade.
+  // per chunk: one pass at a time for the first kSinglePasses passes (most
+  // runs end there, and a surplus pass still dispatches its grids), then
+  // doubling chunks through the tail of a long cascade.  The dense output
+  // is unpacked once, after the fixpoint.
   const kzi::Hdr *hdr = (const kzi::Hdr *)ws;
   int next = 1, chunk = 1;
   for (;;) {
-    if (enqueue_passes(ctx, g, colour, k, (char *)ws, z, mfma, vmask, emask, next, chunk, s, nullptr) != KZ_OK)
+    if (enqueue_passes(ctx, g, colour, k, (char *)ws, z, mfma, vmask, emask, next, chunk, false, s, nullptr) !=
+        KZ_OK)
       return finish(res, r);
     if (hipMemcpyAsync(ctx->pinned, hdr, sizeof(kzi::Hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -689,7 +693,18 @@ int kz_kernelize(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, int32_t 
     next += chunk;
     // every productive pass removes something: a run cannot outlast n + m + 1 passes
     if (next > (long long)g->n + o.result.input_edges + 2) return finish(res, r);
-    chunk = o.last_removed * 256 < o.result.input_edges + g->n ? std::min(2 * chunk, kMaxChunk) : 1;
+    chunk = next > kSinglePasses ? std::min(2 * chunk, kMaxChunk) : 1;
+  }
+  if (g->format == KZ_DENSE_U8 && r.status == KZ_OK &&
+      enqueue_passes(ctx, g, colour, k, (char *)ws, z, mfma, vmask, emask, next + chunk, 0, true, s, nullptr) !=
+          KZ_OK) {
+    r.status = KZ_EHIP;
+    return finish(res, r);
+  }
+  if (!ctx->pending.empty()) {
+    // timing enabled: the unpack's events are read before returning
+    if (hipStreamSynchronize(s) != hipSuccess) r.status = KZ_EHIP;
+    prof_collect(ctx);
   }
   return finish(res, r);
 }
@@ -712,7 +727,7 @@ int kz_kernelize_async(kz_ctx *ctx, const kz_graph *g, const int32_t *colour, in
     kzi::launch_write_out(out, o, s);
     return hipGetLastError() == hipSuccess ? KZ_OK : KZ_EHIP;
   }
-  return enqueue_passes(ctx, g, colour, k, (char *)ws, z, mfma, vmask, emask, first_pass, npasses, s, out);
+  return enqueue_passes(ctx, g, colour, k, (char *)ws, z, mfma, vmask, emask, first_pass, npasses, true, s, out);
 }
 
 }  // extern "C"

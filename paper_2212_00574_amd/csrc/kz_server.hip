@@ -58,7 +58,7 @@ constexpr int kMaxFences = 16;     // input-ready events in flight
 constexpr double kRelaunchUs = 500;  // untaken requests behind a running launch: queue another
 constexpr int kDefaultSplitN = 2048;
 constexpr int kDefaultIdleUs = 20000;
-constexpr int kDefaultLeaseUs = 50000;
+constexpr int kDefaultLeaseUs = 10000;
 
 // Session lane's share of the compute units by default: the batched
 // runtime is the better path only for the smallest requests, which are a
