@@ -104,6 +104,8 @@ def _load():
     lib.kzo_struction.argtypes = [i32, vp, i32, vp, i64, vp]
     lib.kzo_find_clique.restype = C.c_int
     lib.kzo_find_clique.argtypes = [i32, vp, vp, i32, vp, vp, vp]
+    lib.kzo_colour_jp.restype = C.c_int
+    lib.kzo_colour_jp.argtypes = [i32, vp, vp, vp, C.POINTER(i32)]
     _lib = lib
     return lib
 
@@ -343,3 +345,20 @@ def struction(adj, pivot=0):
     assert got == npr
     return out[:npr, :npr].copy(), mp[:npr].copy()
 
+
+
+# ---- upstream legal colouring (Jones-Plassmann), kz_oracle_ext.c
+def colour_jp(adj, priority):
+    """Jones and Plassmann's parallel greedy colouring of a dense graph with
+    the given uint64 priorities (keys (priority[v], v)): (colour int32[n],
+    rounds, number of colours)."""
+    a = np.ascontiguousarray(adj, dtype=np.uint8)
+    n = a.shape[0]
+    pri = np.ascontiguousarray(priority, dtype=np.uint64)
+    assert pri.shape == (n,)
+    col = np.zeros(max(n, 1), np.int32)
+    nc = C.c_int32(0)
+    r = _load().kzo_colour_jp(n, _ptr(a), _ptr(pri), _ptr(col), C.byref(nc))
+    if r < 0:
+        raise RuntimeError("oracle: a colouring round took no vertex")
+    return col[:n].copy(), int(r), int(nc.value)

@@ -248,3 +248,71 @@ int64_t kzo_struction(int32_t n, const uint8_t *adj, int32_t pivot, uint8_t *out
   }
   return np;
 }
+
+/*
+ * Upstream legal colouring.  The colour-index method (thesis section 4.2)
+ * needs a legal colouring of its input; the thesis assumes one is given
+ * and names no algorithm.  This is Jones and Plassmann's parallel greedy
+ * colouring (SIAM J. Sci. Comput. 14(3), 1993).  Every vertex v has the key
+ * (pri[v], v), compared lexicographically, so keys are distinct.  In each
+ * round, every uncoloured vertex whose key exceeds the key of each of its
+ * uncoloured neighbours is taken; each vertex taken receives the smallest
+ * colour that none of its neighbours coloured in earlier rounds holds.  Two
+ * vertices taken in one round are never adjacent (one of them has the larger
+ * key), so the colouring is legal and does not depend on the order in which
+ * a round's vertices are coloured.
+ *   adj: n*n bytes (symmetric, zero diagonal); pri: uint64[n];
+ *   colour: int32[n] out; *ncolours = 1 + the largest colour (0 for n = 0).
+ * Returns the number of rounds, or -1 if a round takes no vertex (cannot
+ * happen with distinct keys: the largest uncoloured key is always taken).
+ */
+static int jp_beats(const uint64_t *pri, int32_t u, int32_t v) {
+  return pri[u] > pri[v] || (pri[u] == pri[v] && u > v);
+}
+
+int kzo_colour_jp(int32_t n, const uint8_t *adj, const uint64_t *pri, int32_t *colour, int32_t *ncolours) {
+  int rounds = 0, left = n, top = -1;
+  uint8_t *taken = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+  uint8_t *used = (uint8_t *)calloc((size_t)(n > 0 ? n : 1) + 1, 1);
+  if (!taken || !used) {
+    free(taken);
+    free(used);
+    return -1;
+  }
+  for (int32_t v = 0; v < n; ++v) colour[v] = -1;
+  while (left > 0) {
+    /* the vertices this round takes, from the colours at its start */
+    int any = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      taken[v] = 0;
+      if (colour[v] >= 0) continue;
+      int best = 1;
+      for (int32_t u = 0; u < n && best; ++u)
+        if (adj[(int64_t)v * n + u] && colour[u] < 0 && jp_beats(pri, u, v)) best = 0;
+      taken[v] = (uint8_t)best;
+      any |= best;
+    }
+    if (!any) {
+      free(taken);
+      free(used);
+      return -1;
+    }
+    /* each takes the smallest colour its coloured neighbours leave free */
+    for (int32_t v = 0; v < n; ++v) {
+      if (!taken[v]) continue;
+      memset(used, 0, (size_t)n + 1);
+      for (int32_t u = 0; u < n; ++u)
+        if (adj[(int64_t)v * n + u] && colour[u] >= 0 && !taken[u]) used[colour[u]] = 1;
+      int c = 0;
+      while (used[c]) ++c;
+      colour[v] = c;
+      if (c > top) top = c;
+      --left;
+    }
+    ++rounds;
+  }
+  *ncolours = top + 1;
+  free(taken);
+  free(used);
+  return rounds;
+}

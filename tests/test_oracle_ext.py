@@ -296,3 +296,84 @@ def test_struction_lowers_the_clique_number_by_one(seed):
         assert mp.tolist() == [[a, -1] for a in A] + [list(e) for e in inner]
         assert (out == out.T).all() and not out.diagonal().any()
         assert omega(out) == omega(g) - 1          # Theorem 1
+
+
+# ---- upstream legal colouring (Jones and Plassmann, SIAM J. Sci. Comput.
+# 14(3), 1993), pinned by hand derivations, a closed form on complete
+# graphs, and the properties the algorithm guarantees, checked with Python
+# sets rather than a second copy of its loops.
+from oracle import colour_jp  # noqa: E402
+
+
+def test_jp_path_and_star_by_hand():
+    # path 0-1-2-3, priorities 10 40 20 30: round 1 takes 1 (beats 0 and 2)
+    # and 3 (beats 2), both colour 0; round 2 takes 0 and 2, colour 1
+    col, rounds, nc = colour_jp(graph(4, [(0, 1), (1, 2), (2, 3)]), np.array([10, 40, 20, 30], np.uint64))
+    assert col.tolist() == [1, 0, 1, 0] and rounds == 2 and nc == 2
+    # star with the centre lowest: the leaves first (colour 0), then the centre
+    col, rounds, nc = colour_jp(graph(5, [(0, i) for i in range(1, 5)]), np.array([1, 5, 4, 3, 2], np.uint64))
+    assert col.tolist() == [1, 0, 0, 0, 0] and rounds == 2 and nc == 2
+    # the centre highest: it alone first, then every leaf in round 2
+    col, rounds, nc = colour_jp(graph(5, [(0, i) for i in range(1, 5)]), np.array([9, 5, 4, 3, 2], np.uint64))
+    assert col.tolist() == [0, 1, 1, 1, 1] and rounds == 2 and nc == 2
+    # triangle 0-1-2 and a pendant 3 on 2, priorities 3 2 1 4: round 1 takes
+    # 0 (beats 1, 2) and 3 (beats 2): colour 0 each; round 2 takes 1 (its
+    # uncoloured neighbour 2 is lower): colour 1; round 3 takes 2: neighbours
+    # hold 0, 1, 0, so colour 2
+    col, rounds, nc = colour_jp(graph(4, [(0, 1), (1, 2), (0, 2), (2, 3)]), np.array([3, 2, 1, 4], np.uint64))
+    assert col.tolist() == [0, 1, 2, 0] and rounds == 3 and nc == 3
+
+
+def test_jp_complete_graph_colours_are_ranks():
+    """On K_n each round takes the one uncoloured vertex with the largest
+    key, which takes the next colour: colour(v) is v's rank by key,
+    largest first (ties in priority broken by the larger index)."""
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 7, 40):
+        a = np.ones((n, n), np.uint8) - np.eye(n, dtype=np.uint8)
+        pri = rng.integers(0, 2**63, size=n, dtype=np.uint64)
+        col, rounds, nc = colour_jp(a, pri)
+        order = sorted(range(n), key=lambda v: (int(pri[v]), v), reverse=True)
+        assert [int(col[v]) for v in order] == list(range(n))
+        assert rounds == n and nc == n
+        col, _, _ = colour_jp(a, np.zeros(n, np.uint64))          # equal priorities: by index
+        assert col.tolist() == list(range(n - 1, -1, -1))
+
+
+def test_jp_edgeless_and_empty():
+    col, rounds, nc = colour_jp(np.zeros((6, 6), np.uint8), np.arange(6, dtype=np.uint64))
+    assert col.tolist() == [0] * 6 and rounds == 1 and nc == 1
+    col, rounds, nc = colour_jp(np.zeros((0, 0), np.uint8), np.zeros(0, np.uint64))
+    assert len(col) == 0 and rounds == 0 and nc == 0
+
+
+def jp_random(n, p, seed):
+    rng = np.random.default_rng(seed)
+    a = np.triu((rng.random((n, n)) < p).astype(np.uint8), 1)
+    a = a | a.T
+    return a, rng.integers(0, 2**64, size=n, dtype=np.uint64)
+
+
+def test_jp_properties_on_random_graphs():
+    """A legal colouring; greedy (a vertex of colour c has neighbours of
+    every colour below c); at most max degree + 1 colours; the vertex with
+    the largest key takes colour 0; and relabelling the vertices (with
+    their priorities) relabels the colours the same way."""
+    for n, p, seed in ((30, 0.2, 1), (60, 0.5, 2), (80, 0.1, 3), (50, 0.9, 4)):
+        a, pri = jp_random(n, p, seed)
+        col, rounds, nc = colour_jp(a, pri)
+        nbrs = [set(np.nonzero(a[v])[0].tolist()) for v in range(n)]
+        for v in range(n):
+            assert all(col[u] != col[v] for u in nbrs[v])
+            assert set(range(col[v])) <= {int(col[u]) for u in nbrs[v]}
+        assert nc == col.max() + 1 <= max(len(s) for s in nbrs) + 1
+        top = max(range(n), key=lambda v: (int(pri[v]), v))
+        assert col[top] == 0
+        perm = np.random.default_rng(seed + 10).permutation(n)
+        inv = np.argsort(perm)
+        # vertex i of the relabelled graph is old vertex perm[i]; keys
+        # (priority, index) must order the same, so the priorities are
+        # distinct here (ties would be broken by the new indices)
+        assert len(set(pri.tolist())) == n
+        col2, rounds2, nc2 = colour_jp(a[np.ix_(perm, perm)], pri[perm])
+        assert np.array_equal(col2[inv], col) and rounds2 == rounds and nc2 == nc

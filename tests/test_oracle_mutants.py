@@ -54,6 +54,16 @@ MUTANTS = {
 # Mistakes planted in kz_oracle_ext.c (dominance, clique search, struction,
 # colourings); its pins are tests/test_oracle_ext.py.
 EXT_MUTANTS = {
+    "jp_takes_the_smallest_key": (
+        "  return pri[u] > pri[v] || (pri[u] == pri[v] && u > v);",
+        "  return pri[u] < pri[v] || (pri[u] == pri[v] && u < v);"),
+    "jp_no_tie_break_by_index": (
+        "  return pri[u] > pri[v] || (pri[u] == pri[v] && u > v);", "  return pri[u] > pri[v];"),
+    "jp_colour_above_the_largest_used": (
+        "      while (used[c]) ++c;", "      for (int32_t x = 0; x <= n; ++x) if (used[x]) c = x + 1;"),
+    "jp_coloured_neighbours_block": (
+        "if (adj[(int64_t)v * n + u] && colour[u] < 0 && jp_beats(pri, u, v)) best = 0;",
+        "if (adj[(int64_t)v * n + u] && jp_beats(pri, u, v)) best = 0;"),
     "dom_vertex_subset_reversed": (
         "    if (adj[(int64_t)a * n + x] && !adj[(int64_t)b * n + x]) return 0;",
         "    if (adj[(int64_t)b * n + x] && !adj[(int64_t)a * n + x]) return 0;"),
