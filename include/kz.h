@@ -472,6 +472,41 @@ int kz_profile_read(const kz_ctx *ctx, int kernel, double *total_ms, int64_t *la
 int kz_gen_bitset(kz_ctx *ctx, int32_t k, const int32_t *sizes, double p, uint32_t seed, uint32_t gid,
                   const int32_t *planted, uint64_t *rows, int32_t row_words, int32_t *colour, void *stream);
 
+/* ------------------------------------------------------------ colouring
+ * An upstream legal colouring, for graphs that arrive uncoloured: the
+ * colour-index method (section 4.2, Definition 4.2.1) needs a legal
+ * colouring of its input, and the thesis assumes one is given without
+ * naming an algorithm.  This is Jones and Plassmann's parallel greedy
+ * colouring (SIAM J. Sci. Comput. 14(3), 1993): vertex v has the key
+ * (priority[v], v); each round takes every uncoloured vertex whose key
+ * beats the key of each uncoloured neighbour, and each vertex taken gets
+ * the smallest colour no neighbour coloured in an earlier round holds.  The
+ * result is legal, uses at most max degree + 1 colours, and is the same for
+ * any order inside a round.  With m colours the graph goes to the
+ * colour-index method as m classes, with a clique size k <= m (the batched
+ * path's kz_batch_graph.clique).
+ *   rows: device uint64[n * row_words], plain rows as for kz_dominance
+ *         (bit w % 64 of word w / 64 of row v set iff {v, w} is an edge);
+ *         ceil(n / 64) <= row_words <= 1024 (else KZ_EINVAL / KZ_ETOOLARGE);
+ *         symmetric (KZ_EASYM), no self-loop (KZ_ESELFLOOP), no bit at or
+ *         beyond n (KZ_EINVAL);
+ *   priority: device uint64[n], the vertices' priorities (random numbers
+ *         the caller draws; equal ones are broken by the index);
+ *   ws, ws_bytes: device workspace of kz_colour_workspace_bytes() bytes,
+ *         256-byte aligned;
+ *   colour: device int32[n] out, in [0, colours).
+ * Blocking: each round is two launches and one small readback. */
+typedef struct kz_colour_result {
+  int32_t status;
+  int32_t rounds;
+  int32_t colours;  /* 1 + the largest colour given                      */
+  int32_t pad;
+} kz_colour_result;
+
+int kz_colour_workspace_bytes(int32_t n, size_t *bytes);
+int kz_colour_jp(kz_ctx *ctx, int32_t n, const uint64_t *rows, int32_t row_words, const uint64_t *priority,
+                 void *ws, size_t ws_bytes, int32_t *colour, void *stream, kz_colour_result *res);
+
 /* ------------------------------------------------------------ dominance
  * Dominance reductions (thesis section 4.3).  A different method from the
  * colour index and kept apart from it: it uses no colouring, and vertex

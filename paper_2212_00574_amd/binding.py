@@ -22,7 +22,7 @@ EXPORTED = ("kz_create", "kz_destroy", "kz_strerror", "kz_workspace_bytes", "kz_
             "kz_profile_enable", "kz_profile_read", "kz_batch_workspace_bytes", "kz_kernelize_batch",
             "kz_batch_autotune", "kz_batch_set_config", "kz_batch_get_config", "kz_gen_bitset",
             "kz_server_fixed_bytes", "kz_server_request_bytes", "kz_server_create", "kz_server_submit",
-            "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_server_configure", "kz_server_done", "kz_set_edge_path",
+            "kz_server_progress", "kz_server_poll", "kz_server_destroy", "kz_server_configure", "kz_server_done", "kz_set_edge_path", "kz_colour_workspace_bytes", "kz_colour_jp",
             "kz_kernelize_noalloc", "kz_dom_workspace_bytes", "kz_dominance", "kz_clique_workspace_bytes",
             "kz_find_clique", "kz_struction_workspace_bytes", "kz_struction")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # KZ_NOALLOC_SCRATCH_BYTES
@@ -96,6 +96,13 @@ def kz_out_from_bytes(raw: bytes) -> dict:
     return d
 
 
+class kz_colour_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("rounds", C.c_int32), ("colours", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_ if name != "pad"}
+
+
 class kz_server_config(C.Structure):
     _fields_ = [("split_n", C.c_int32), ("idle_us", C.c_int32), ("lease_us", C.c_int32), ("session_cus", C.c_int32),
                 ("workers", C.c_int32), ("partition", C.c_int32), ("resident_limit", C.c_size_t)]
@@ -135,6 +142,11 @@ def _load() -> C.CDLL:
     lib.kz_kernelize.restype = C.c_int
     lib.kz_kernelize.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, C.c_size_t, vp, vp, vp,
                                  C.POINTER(kz_result)]
+    lib.kz_colour_workspace_bytes.restype = C.c_int
+    lib.kz_colour_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.kz_colour_jp.restype = C.c_int
+    lib.kz_colour_jp.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp, C.c_size_t, vp, vp,
+                                 C.POINTER(kz_colour_result)]
     lib.kz_kernelize_async.restype = C.c_int
     lib.kz_kernelize_async.argtypes = [vp, C.POINTER(kz_graph), vp, C.c_int32, vp, C.c_size_t, vp, vp, C.c_int32,
                                        C.c_int32, vp, vp]
@@ -227,6 +239,22 @@ def kz_workspace_bytes(ctx: int, graph: kz_graph, k: int) -> int:
     if st != KZ_OK:
         raise KzError(st, "kz_workspace_bytes")
     return int(b.value)
+
+
+def kz_colour_workspace_bytes(n: int) -> int:
+    b = C.c_size_t(0)
+    st = LIB.kz_colour_workspace_bytes(int(n), C.byref(b))
+    if st != 0:
+        raise KzError(st, "kz_colour_workspace_bytes")
+    return int(b.value)
+
+
+def kz_colour_jp(ctx: int, n: int, rows_ptr: int, row_words: int, priority_ptr: int, ws_ptr: int, ws_bytes: int,
+                 colour_ptr: int, stream: int) -> kz_colour_result:
+    res = kz_colour_result()
+    LIB.kz_colour_jp(ctx, int(n), rows_ptr, int(row_words), priority_ptr, ws_ptr, int(ws_bytes), colour_ptr, stream,
+                     C.byref(res))
+    return res
 
 
 def kz_kernelize_async(ctx: int, graph: kz_graph, colour_ptr: int, k: int, ws_ptr: int, ws_bytes: int,
@@ -552,6 +580,21 @@ class Kernelizer:
                            _dev_ptr(emask), first_pass, npasses, _stream_handle(stream, self.device),
                            None if out is None else out.data_ptr())
         return ws
+
+    def colour_jp(self, rows: torch.Tensor, n: int, priority: torch.Tensor,
+                  stream: torch.cuda.Stream | None = None, check: bool = True) -> tuple[torch.Tensor, dict]:
+        """Jones-Plassmann colouring of plain bit rows (uint64 [n, row_words]):
+        (colour int32[n] on the device, result dict)."""
+        if priority.dtype not in (torch.int64, torch.uint64) or priority.numel() != n:
+            raise ValueError("priority must be n 64-bit values")
+        rw = int(rows.shape[1]) if rows.dim() == 2 else (int(rows.numel()) // n if n else 0)
+        ws = torch.empty(max(kz_colour_workspace_bytes(n), 256), dtype=torch.uint8, device=self.device)
+        colour = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        res = kz_colour_jp(self.ctx, n, _dev_ptr(rows), rw, _dev_ptr(priority), ws.data_ptr(), ws.numel(),
+                           colour.data_ptr(), _stream_handle(stream, self.device))
+        if check and res.status != KZ_OK:
+            raise KzError(res.status, "kz_colour_jp")
+        return colour[:n], res.as_dict()
 
     def kernelize_dense(self, adj: torch.Tensor, colour: torch.Tensor, k: int, **kw):
         """(vmask u8[n], emask u8[n,n], result dict) for a dense uint8 adjacency."""

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkz.so")
 SOURCES = ["kz_kernels.hip", "kz_csr.hip", "kz_batch.hip", "kz_gen.hip", "kz_api.hip", "kz_server.hip",
-           "kz_dom.hip", "kz_clique.hip", "kz_struction.hip"]
+           "kz_dom.hip", "kz_clique.hip", "kz_struction.hip", "kz_colour.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -26,7 +26,8 @@ def lib():
 
 def test_header_declares_the_entry_points():
     assert declared() == ["kz_batch_autotune", "kz_batch_get_config", "kz_batch_set_config",
-                          "kz_batch_workspace_bytes", "kz_clique_workspace_bytes", "kz_create", "kz_destroy",
+                          "kz_batch_workspace_bytes", "kz_clique_workspace_bytes", "kz_colour_jp",
+                          "kz_colour_workspace_bytes", "kz_create", "kz_destroy",
                           "kz_dom_workspace_bytes",
                           "kz_dominance", "kz_find_clique", "kz_gen_bitset",
                           "kz_kernelize", "kz_kernelize_async", "kz_kernelize_batch", "kz_kernelize_noalloc", "kz_profile_enable",
