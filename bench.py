@@ -67,6 +67,8 @@ WORKLOADS = {
     "clique": "k-clique search on the 4096 batching graphs (config 4), on each input graph and on its kernel",
     "colours": "the 4096 batching graphs (config 4) with clique size k-2 below their k colour classes "
                "(thresholds k-3 and k-4), batched runtime",
+    "colouring": "upstream legal colouring (Jones-Plassmann) of uncoloured G(n, p) graphs: n = 3000 at p = 0.3 "
+                 "and n = 20000 at p = 0.05, seeded uint64 priorities",
     "struction": "struction (section 4.1) of a random graph of 1000 vertices at p = 0.1 around vertex 0 "
                  "(G' about 40 000 nodes), plain bit rows",
 }
@@ -998,6 +1000,56 @@ def run_struction(args):
     return result
 
 
+# --------------------------------------------------------------- colouring
+def run_colouring(args):
+    """Jones-Plassmann colouring of two uncoloured random graphs: whole-call
+    time (median of three after a warm-up), rounds and colours; the smaller
+    graph's colours against the oracle's, with the oracle's time."""
+    import torch
+
+    from oracle import colour_jp
+    from paper_2212_00574_amd import inputs
+    from paper_2212_00574_amd.binding import Kernelizer
+    kz = Kernelizer(0)
+    out = {}
+    for i, (n, p) in enumerate(((3000, 0.3), (20000, 0.05))):
+        rng = np.random.default_rng(np.random.SeedSequence([args.seed, 0x4A50, i]))
+        dense = np.zeros((n, n), np.uint8)
+        for v0 in range(0, n, 2048):       # the upper triangle by blocks of rows, then mirrored
+            blk = rng.random((min(2048, n - v0), n), dtype=np.float32) < p
+            dense[v0:v0 + blk.shape[0]] = np.triu(blk, v0 + 1)
+        dense |= dense.T
+        rows = inputs.dense_to_rows(dense)
+        pri = rng.integers(0, 2**64, size=n, dtype=np.uint64)
+        t_rows = torch.from_numpy(rows.view(np.int64)).to(kz.device)
+        t_pri = torch.from_numpy(pri.view(np.int64)).to(kz.device)
+        col, res = kz.colour_jp(t_rows, n, t_pri)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            col, res = kz.colour_jp(t_rows, n, t_pri)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = float(np.median(times))
+        entry = {"n": n, "p": p, "ms": round(ms, 3), "rounds": res["rounds"], "colours": res["colours"],
+                 "us_per_round": round(ms * 1e3 / max(res["rounds"], 1), 2)}
+        if n <= 5000:
+            t0 = time.perf_counter()
+            ref, rounds, nc = colour_jp(dense, pri)
+            entry["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+            entry["oracle_equal"] = bool(np.array_equal(col.cpu().numpy(), ref) and rounds == res["rounds"])
+        say("colouring: n %d p %.2f: %.2f ms, %d rounds, %d colours%s" % (
+            n, p, ms, res["rounds"], res["colours"],
+            ", oracle %.0f ms, equal %s" % (entry["oracle_ms"], entry["oracle_equal"]) if "oracle_ms" in entry else ""))
+        out["n%d" % n] = entry
+    kz.close()
+    return {"metric": "colouring time", "value": out["n20000"]["ms"], "unit": "ms", "higher_is_better": False,
+            "config": {"workload": "colouring: " + WORKLOADS["colouring"], "seed": args.seed},
+            "graphs": out, "oracle_equal": out["n3000"].get("oracle_equal"),
+            "note": "each round is two launches and one readback: launch-latency bound (us_per_round)"}
+
+
 # --------------------------------------------------------------- dominance
 def run_dom(args, cpu_proc=None):
     """Dominance reductions (section 4.3) on the ten evaluation graphs, both
@@ -1112,6 +1164,8 @@ def main():
         out = run_struction(args)
     elif w == "colours":
         out = run_colours(args)
+    elif w == "colouring":
+        out = run_colouring(args)
     else:
         # serving first: its streams then take hardware queues before the
         # other workloads' streams do (a stream that shares the running
@@ -1125,6 +1179,7 @@ def main():
             out["clique"] = run_clique(args)
             out["struction"] = run_struction(args)
             out["colours"] = run_colours(args)
+            out["colouring"] = run_colouring(args)
     out.setdefault("n_gpus", 1)
     print(json.dumps(out), flush=True)
 
