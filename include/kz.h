@@ -495,7 +495,8 @@ int kz_gen_bitset(kz_ctx *ctx, int32_t k, const int32_t *sizes, double p, uint32
  *   ws, ws_bytes: device workspace of kz_colour_workspace_bytes() bytes,
  *         256-byte aligned;
  *   colour: device int32[n] out, in [0, colours).
- * Blocking: each round is two launches and one small readback. */
+ * Blocking: rounds end on the device and go out in chunks, with one small
+ * readback per chunk. Blocking: each round is two launches and one small readback. */
 typedef struct kz_colour_result {
   int32_t status;
   int32_t rounds;

@@ -18,6 +18,8 @@
 // its neighbours, so no one reads that bit for it.
 #include <string.h>
 
+#include <algorithm>
+
 #include "kz.h"
 #include "kz_internal.h"
 
@@ -26,12 +28,14 @@ namespace {
 constexpr int kColWaves = 4;                // waves (vertices) per workgroup
 constexpr int kColMaxWords = 1024;          // row words (65536 vertices)
 constexpr size_t kColAlign = 256;
+constexpr int kColFirstChunk = 8;           // rounds enqueued before the first look at the count
+constexpr int kColMaxChunk = 128;           // ... and at most between two looks
 
 struct ColCtr {
-  int taken;  // vertices taken this round
-  int bad;    // validation: a KZ_* status, most severe first (see k_col_check)
-  int maxc;   // largest colour given
-  int pad;
+  int left;    // vertices not yet coloured; every round kernel returns at once at 0
+  int bad;     // validation: a KZ_* status, most severe first (see k_col_check)
+  int maxc;    // largest colour given
+  int rounds;  // rounds that ran
 };
 
 size_t col_up(size_t x) { return (x + kColAlign - 1) / kColAlign * kColAlign; }
@@ -88,6 +92,7 @@ __global__ void __launch_bounds__(kColWaves * 64) k_col_check(int n, const uint6
   if (lane == 0) {
     colour[v] = -1;
     if (bad) atomicMax(&ctr->bad, bad);
+    if (v == 0) ctr->left = n;
   }
   if (lane == 0 && (v & 63) == 0) {
     const int nb = min(64, n - v);
@@ -103,6 +108,8 @@ __global__ void __launch_bounds__(kColWaves * 64) k_col_select(int n, const uint
                                                                ColCtr *ctr) {
   const int lane = threadIdx.x & 63;
   const int v = blockIdx.x * kColWaves + (threadIdx.x >> 6);
+  if (ctr->left == 0) return;  // coloured in an earlier round of this chunk
+  if (v == 0 && lane == 0) atomicAdd(&ctr->rounds, 1);
   if (v >= n) return;
   const bool unc = (U[v >> 6] >> (v & 63)) & 1ull;
   if (!unc) {
@@ -127,10 +134,7 @@ __global__ void __launch_bounds__(kColWaves * 64) k_col_select(int n, const uint
     if (__ballot(beaten)) break;
   }
   const bool taken = __ballot(beaten) == 0ull;
-  if (lane == 0) {
-    sel[v] = taken ? 1 : 0;
-    if (taken) atomicAdd(&ctr->taken, 1);
-  }
+  if (lane == 0) sel[v] = taken ? 1 : 0;
 }
 
 // One round's colours, one wave per vertex taken: the smallest colour that
@@ -141,7 +145,9 @@ __global__ void __launch_bounds__(kColWaves * 64) k_col_colour(int n, const uint
   __shared__ unsigned long long used[kColWaves][kColMaxWords];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int v = blockIdx.x * kColWaves + wid;
-  if (v >= n || !sel[v]) return;
+  // left is unchanged since this round's select kernel read it: 0 means
+  // that kernel returned at once and sel is a previous round's
+  if (v >= n || ctr->left == 0 || !sel[v]) return;
   const int W = (n + 63) >> 6;
   unsigned long long *mine = used[wid];
   for (int w = lane; w < W; w += 64) mine[w] = 0ull;
@@ -176,6 +182,7 @@ __global__ void __launch_bounds__(kColWaves * 64) k_col_colour(int n, const uint
     colour[v] = c;
     atomicMax(&ctr->maxc, c);
     atomicAnd(&U[v >> 6], ~(1ull << (v & 63)));
+    atomicSub(&ctr->left, 1);
   }
 }
 
@@ -232,22 +239,25 @@ int kz_colour_jp(kz_ctx *ctx, int32_t n, const uint64_t *rows, int32_t row_words
     r.status = h->bad == 3 ? KZ_EINVAL : h->bad == 2 ? KZ_ESELFLOOP : KZ_EASYM;
     return done();
   }
-  long long left = n;
-  int rounds = 0;
-  while (left > 0) {
-    if (hipMemsetAsync(&ctr->taken, 0, sizeof(int), s) != hipSuccess) return done();
-    hipLaunchKernelGGL(k_col_select, grid, block, 0, s, n, rows, (int)row_words, priority, U, sel, ctr);
-    hipLaunchKernelGGL(k_col_colour, grid, block, 0, s, n, rows, (int)row_words, sel, U, colour, ctr);
+  // rounds in chunks, ended on the device: one readback per chunk (rounds
+  // past the last one return at once)
+  int chunk = kColFirstChunk, last_left = n;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) {
+      hipLaunchKernelGGL(k_col_select, grid, block, 0, s, n, rows, (int)row_words, priority, U, sel, ctr);
+      hipLaunchKernelGGL(k_col_colour, grid, block, 0, s, n, rows, (int)row_words, sel, U, colour, ctr);
+    }
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(h, ctr, sizeof(ColCtr), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return done();
-    ++rounds;
-    if (h->taken <= 0) return done();  // cannot happen: the largest uncoloured key is always taken
-    left -= h->taken;
+    if (h->left == 0) break;
+    if (h->left >= last_left) return done();  // cannot happen: every round takes the largest uncoloured key
+    last_left = h->left;
+    chunk = std::min(2 * chunk, kColMaxChunk);
   }
   r.status = KZ_OK;
-  r.rounds = rounds;
+  r.rounds = h->rounds;
   r.colours = h->maxc + 1;
   return done();
 }
