@@ -496,7 +496,7 @@ int kz_gen_bitset(kz_ctx *ctx, int32_t k, const int32_t *sizes, double p, uint32
  *         256-byte aligned;
  *   colour: device int32[n] out, in [0, colours).
  * Blocking: rounds end on the device and go out in chunks, with one small
- * readback per chunk. Blocking: each round is two launches and one small readback. */
+ * readback per chunk. */
 typedef struct kz_colour_result {
   int32_t status;
   int32_t rounds;
