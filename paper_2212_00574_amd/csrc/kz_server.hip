@@ -56,6 +56,9 @@ constexpr int kMaxWorkers = 8;     // single-graph lane: requests in flight at o
 constexpr int kDefaultWorkers = 6;
 constexpr int kMaxFences = 16;     // input-ready events in flight
 constexpr double kRelaunchUs = 500;  // untaken requests behind a running launch: queue another
+constexpr int kSlicePasses = 8;    // single-graph lane: passes a request runs before the next one's turn
+constexpr size_t kOutBytes = 256;  // its kz_out, after its workspace
+static_assert(sizeof(kz_out) <= kOutBytes, "a request's kz_out fits its slot");
 constexpr int kDefaultSplitN = 2048;
 constexpr int kDefaultIdleUs = 20000;
 constexpr int kDefaultLeaseUs = 10000;
@@ -166,6 +169,7 @@ struct Req {
   int state;         // 0 admitted, 1 published / taken by a worker, 2 done
   bool big;          // single-graph lane
   int slot;          // session lane
+  int next_pass;     // single-graph lane: the next pass to run (0: not started)
   hipEvent_t ready;  // single-graph lane: inputs complete on the caller's stream
   kz_result res;
 };
@@ -264,7 +268,11 @@ void release(kz_server *s) {
   delete s;
 }
 
-// The single-graph lane: worker `id` runs one large request at a time.
+// The single-graph lane: worker `id` takes the request at the front of the
+// lane's queue and runs up to kSlicePasses of its passes (the asynchronous
+// call, continued from the request's own workspace); a request not yet at
+// its fixpoint goes to the back of the queue, so a long cascade shares the
+// workers with the requests behind it instead of holding one to its end.
 void work(kz_server *s, int id) {
   kz_ctx *ctx = s->wctx[id];
   hipStream_t stream = s->wstream[id];
@@ -282,21 +290,37 @@ void work(kz_server *s, int id) {
       r.state = 1;
       q = r;
     }
-    kz_result res{};
-    res.status = KZ_EHIP;
-    if (hipStreamWaitEvent(stream, q.ready, 0) == hipSuccess) {
+    const int first = q.next_pass > 0 ? q.next_pass : 1;
+    kz_out o{};
+    o.result.status = KZ_EHIP;
+    o.converged = 1;
+    // the first slice waits for the inputs; later ones follow a slice that
+    // was waited for on the host
+    if (first > 1 || hipStreamWaitEvent(stream, q.ready, 0) == hipSuccess) {
       kz_graph gr{};
       gr.format = KZ_BITSET_U64;
       gr.n = q.r.n;
       gr.rows = q.r.rows;
       gr.row_words = q.r.row_words;
-      (void)kz_kernelize(ctx, &gr, q.r.colour, q.r.k, s->arena + q.at, q.bytes, q.r.vmask, q.r.emask, stream,
-                         &res);
-      if (hipStreamSynchronize(stream) != hipSuccess) res.status = KZ_EHIP;
+      kz_out *dout = (kz_out *)(s->arena + q.at + q.bytes - kOutBytes);
+      const int st = kz_kernelize_async(ctx, &gr, q.r.colour, q.r.k, s->arena + q.at, q.bytes - kOutBytes,
+                                        q.r.vmask, q.r.emask, first, kSlicePasses, stream, dout);
+      if (st != KZ_OK) {
+        o.result.status = st;
+      } else if (hipMemcpyAsync(ctx->pinned, dout, sizeof(kz_out), hipMemcpyDeviceToHost, stream) == hipSuccess &&
+                 hipStreamSynchronize(stream) == hipSuccess) {
+        o = *(const kz_out *)ctx->pinned;
+      }
     }
     std::lock_guard<std::mutex> g(s->mu);
     Req &r = s->reqs[t];
-    r.res = res;
+    if (!o.converged) {
+      r.next_pass = first + kSlicePasses;
+      s->big.push_back(t);
+      s->cv.notify_one();
+      continue;
+    }
+    r.res = o.result;
     r.state = 2;
     s->finished.push_back(t);
     (void)hipEventDestroy(r.ready);
@@ -519,7 +543,7 @@ int single_bytes(kz_ctx *ctx, const kz_request &r, size_t *bytes) {
   gr.rows = r.rows;
   gr.row_words = r.row_words;
   const int st = kz_workspace_bytes(ctx, &gr, r.k, bytes);
-  *bytes = up(*bytes);
+  *bytes = up(*bytes) + kOutBytes;  // and the result the device writes after every pass
   return st;
 }
 
@@ -700,6 +724,7 @@ int kz_server_submit(kz_server *s, const kz_request *req, uint64_t *ticket) {
   q.state = 0;
   q.big = big;
   q.slot = -1;
+  q.next_pass = 0;
   q.ready = nullptr;
   if (big && (hipEventCreateWithFlags(&q.ready, hipEventDisableTiming) != hipSuccess ||
               hipEventRecord(q.ready, s->stream) != hipSuccess)) {

@@ -455,3 +455,54 @@ def test_server_done_queue(kz):
         res[i] = r
     check(reqs, res, "done queue")
     srv.close()
+
+
+def test_server_sliced_cascades(kz):
+    """The single-graph lane runs a request eight passes at a time and puts
+    it back in the queue until its fixpoint: requests of the serving stream
+    whose cascades last 31-50 rounds (so four to seven slices each, resumed
+    by whichever worker is free) beside short ones, all in that lane, equal
+    the oracle."""
+    say("server: cascades in slices")
+    specs = inputs.config5_specs(0, requests=50000)
+    long_ids = [15604, 5366, 37098, 12684, 41312, 12120]   # 31-50 rounds each
+    short = [i for i in range(2000) if sum(specs[i].sizes) <= 1500][:40]
+    ids = long_ids + short
+    srv = Server(kz, arena_bytes=256 << 20, max_slots=64)
+    srv.configure(split_n=100, workers=6)                   # every one of these takes the single-graph lane
+    bufs = []
+    for i in ids:
+        sp = specs[i]
+        lay = inputs.class_layout(sp.sizes)
+        rows = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+        colour = torch.empty(lay.n, dtype=torch.int32, device=DEV)
+        kz_gen_bitset(kz.ctx, sp.sizes, sp.p, 0, i, None, rows.data_ptr(), lay.R, colour.data_ptr(),
+                      srv.stream.cuda_stream)
+        vm = torch.empty(lay.n, dtype=torch.uint8, device=DEV)
+        em = torch.empty(lay.n * lay.R, dtype=torch.int64, device=DEV)
+        bufs.append((rows, colour, sp.k, vm, em, lay))
+    tickets = {}
+    res = [None] * len(bufs)
+    t0 = time.time()
+    for j, (rows, colour, k, vm, em, lay) in enumerate(bufs):
+        t = srv.submit(rows, colour, k, vm, em)
+        while t is None:                                    # no room now: collect finished ones
+            for tk, r in srv.done(64):
+                res[tickets[tk]] = r
+            assert time.time() - t0 < 120, "admission did not resume"
+            t = srv.submit(rows, colour, k, vm, em)
+        tickets[t] = j
+    while any(r is None for r in res):
+        for t, r in srv.done(64):
+            res[tickets[t]] = r
+        assert time.time() - t0 < 120, "requests did not complete"
+    for j, (rows, colour, k, vm, em, lay) in enumerate(bufs):
+        rows_np = rows.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R)
+        ref = kernelize_bitset(rows_np, colour.cpu().numpy(), k)
+        r = res[j]
+        assert r["status"] == 0 and r["rounds"] == ref["rounds"], (ids[j], r["rounds"], ref["rounds"])
+        assert r["edge_tests"] == ref["edge_tests"] and r["surviving_edges"] == ref["surv_edges"], ids[j]
+        assert np.array_equal(vm.cpu().numpy(), ref["vmask"]), ids[j]
+        assert np.array_equal(em.cpu().numpy().view(np.uint64).reshape(lay.n, lay.R), ref["emask"]), ids[j]
+    assert min(res[j]["rounds"] for j in range(len(long_ids))) > 16
+    srv.close()
