@@ -315,8 +315,11 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
  * Single-graph lane: requests of split_n vertices or more (default 2048),
  * or beyond the batched path's k and row-word limits, go to worker threads
  * (six by default), each with a stream of its own, that run them through
- * the single-graph path one request each at a time, beside the session
- * lane.  The process then has workers + 2 streams of its own besides the
+ * the single-graph path beside the session lane: a worker runs the request
+ * at the front of the lane's queue for two passes (the asynchronous call,
+ * continued from the request's workspace) and puts it back at the end of
+ * the queue until its fixpoint, so a long cascade does not hold a worker
+ * while short requests wait.  The process then has workers + 2 streams of its own besides the
  * caller's; with fewer hardware queues than streams (HIP's
  * GPU_MAX_HW_QUEUES, 4 by default) streams share queues, and a short
  * kernel can wait behind a long one of another lane; work on a stream that

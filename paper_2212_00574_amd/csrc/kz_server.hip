@@ -56,7 +56,7 @@ constexpr int kMaxWorkers = 8;     // single-graph lane: requests in flight at o
 constexpr int kDefaultWorkers = 6;
 constexpr int kMaxFences = 16;     // input-ready events in flight
 constexpr double kRelaunchUs = 500;  // untaken requests behind a running launch: queue another
-constexpr int kSlicePasses = 8;    // single-graph lane: passes a request runs before the next one's turn
+constexpr int kSlicePasses = 2;    // single-graph lane: passes a request runs before the next one's turn
 constexpr size_t kOutBytes = 256;  // its kz_out, after its workspace
 static_assert(sizeof(kz_out) <= kOutBytes, "a request's kz_out fits its slot");
 constexpr int kDefaultSplitN = 2048;

@@ -458,11 +458,11 @@ def test_server_done_queue(kz):
 
 
 def test_server_sliced_cascades(kz):
-    """The single-graph lane runs a request eight passes at a time and puts
-    it back in the queue until its fixpoint: requests of the serving stream
-    whose cascades last 31-50 rounds (so four to seven slices each, resumed
-    by whichever worker is free) beside short ones, all in that lane, equal
-    the oracle."""
+    """The single-graph lane runs a request two passes at a time and puts it
+    back in the queue until its fixpoint: requests of the serving stream
+    whose cascades last 31-50 rounds (16 to 26 slices each, resumed by
+    whichever worker is free) beside short ones, all in that lane, equal the
+    oracle."""
     say("server: cascades in slices")
     specs = inputs.config5_specs(0, requests=50000)
     long_ids = [15604, 5366, 37098, 12684, 41312, 12120]   # 31-50 rounds each
