@@ -222,8 +222,9 @@ def test_server_large_and_generated(kz):
 
 
 def test_server_trickle_shared_passes(kz):
-    """Requests submitted one at a time, each launched at once: the graphs
-    run nearly alone on the device, so the idle workgroups of every XCD join
+    """Requests submitted one at a time, each published at once into the
+    running session launch: the graphs run nearly alone on the device, so
+    the idle workgroups of every XCD join
     their passes (many claims, many carriers on other XCDs).  The results
     must equal those of the same requests with every pass kept by one
     workgroup, which a sample pins to the oracle."""
