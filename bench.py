@@ -850,6 +850,36 @@ def run_clique(args):
     ksearch_s = time.perf_counter() - t0
     same = all(np.array_equal(x, y) for x, y in zip(raw, ker))
     found = sum(int(x[0] >= 0) for x in raw)
+
+    def search_threads(nthreads):
+        """The same searches from nthreads host threads, each with a context
+        and a stream of its own (each call still blocks its own thread)."""
+        import concurrent.futures as cf
+        kzs = [Kernelizer(0) for _ in range(nthreads)]
+        streams = [torch.cuda.Stream(dev) for _ in range(nthreads)]
+        got = [None] * len(views)
+
+        def work(t):
+            with torch.cuda.stream(streams[t]):
+                for i in range(t, len(views), nthreads):
+                    rows, col, k, _, _ = views[i]
+                    got[i] = kzs[t].find_clique(rows, col, k, stream=streams[t])[0]
+            streams[t].synchronize()
+
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(nthreads) as ex:
+            list(ex.map(work, range(nthreads)))
+        el = time.perf_counter() - t0
+        answers = [c.cpu().numpy() for c in got]
+        for k_ in kzs:
+            k_.close()
+        return el, all(np.array_equal(x, y) for x, y in zip(raw, answers))
+
+    concurrent = {}
+    for nt in (4, 8):
+        el, eq = search_threads(nt)
+        concurrent["threads_%d" % nt] = {"value": b.G / el, "seconds": round(el, 4), "same_answers": eq}
+        say("clique: %d threads, search only %.3f s, same answers %s" % (nt, el, eq))
     # oracle on a sample of the input graphs
     sample = list(range(0, b.G, 128))
     ok = True
@@ -871,6 +901,7 @@ def run_clique(args):
                                   "kernelize_seconds": round(kern_s, 4), "search_seconds": round(ksearch_s, 4),
                                   "nodes": ker_nodes},
            "same_answers": same,
+           "concurrent_callers": concurrent,
            "oracle_equal": ok,
            "oracle_check": "the class-order search of the oracle on every 128th input graph (%d graphs)" % len(sample),
            "cpu_baseline": {"value": len(sample) / t_or if t_or else None, "unit": "graphs/s", "cores": 1,
