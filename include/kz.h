@@ -572,7 +572,7 @@ int kz_dominance(kz_ctx *ctx, int32_t mode, int32_t n, const uint64_t *rows, int
  *   g: KZ_BITSET_U64 (class-major slots; the rows are not re-validated, they
  *      must be a valid kz_kernelize input or output);
  *   colour: device int32[n], sorted, in [0, k) (KZ_ECOLOUR / KZ_EINVAL);
- *   k: 1..64 (KZ_ETOOLARGE beyond);
+ *   k: 1..64, and n below 2^21 (KZ_ETOOLARGE beyond);
  *   vmask: device uint8[n] (0 = deleted), or NULL for all vertices;
  *   ws, ws_bytes: device workspace of kz_clique_workspace_bytes() bytes,
  *      256-byte aligned;

@@ -101,6 +101,41 @@ def test_multiword_classes_and_large_k(kz):
         assert same(kz, rows, colour, adj, k, ctx=(k, s, p)) is not None
 
 
+def test_few_roots_children_shared(kz):
+    """Few (class 0, class 1) roots and wide classes after them: nearly all
+    the work is the roots' class-2 children, taken by waves that have no
+    root of their own."""
+    rng = np.random.default_rng(9)
+    found = 0
+    for i in range(12):
+        k = int(rng.integers(4, 11))
+        sizes = np.concatenate([rng.integers(1, 4, size=2), rng.integers(40, 130, size=k - 2)])
+        p = float(rng.uniform(0.25, 0.5))
+        rows, colour, lay, adj = case(sizes, p, 9, i, plant=bool(rng.random() < 0.3))
+        vmask = (rng.random(lay.n) < 0.95).astype(np.uint8) if i % 3 == 0 else None
+        say("clique search: few roots, k=%d p=%.2f" % (k, p))
+        found += same(kz, rows, colour, adj, k, vmask, (i, k, p)) is not None
+    assert found >= 3
+    # wider searches before the first clique (the oracle extends 10^2 to
+    # 3.4 * 10^4 partial cliques)
+    for i, (sizes, p) in enumerate([([2, 2] + [100] * 10, 0.5), ([1, 1] + [120] * 8, 0.45),
+                                    ([2, 3] + [128] * 12, 0.55), ([3, 3] + [110] * 9, 0.5)]):
+        rows, colour, lay, adj = case(sizes, p, 13, i, plant=False)
+        say("clique search: few roots, wide, k=%d p=%.2f" % (len(sizes), p))
+        assert same(kz, rows, colour, adj, len(sizes), ctx=(sizes, p)) is not None
+
+
+def test_stack_in_global_memory(kz):
+    """k * R above the LDS stack (1024 words per wave): the stack lives in
+    the workspace."""
+    for i, (k, s, p, plant) in enumerate([(8, 1100, 0.3, True), (24, 65, 0.35, False), (24, 65, 0.9, True)]):
+        rows, colour, lay, adj = case([s] * k, p, 11, i, plant=plant)
+        assert k * lay.R > 1024
+        say("clique search: global stack, k=%d s=%d p=%.2f" % (k, s, p))
+        ref = same(kz, rows, colour, adj, k, ctx=(k, s, p))
+        assert ref is not None or not plant
+
+
 def test_degenerate_and_errors(kz):
     rows, colour, lay, adj = case([5, 0, 4], 0.9, 3, 0, plant=False)
     assert same(kz, rows, colour, adj, 3) is None                # an empty class: no clique
