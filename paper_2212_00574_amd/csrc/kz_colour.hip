@@ -145,8 +145,10 @@ __global__ void __launch_bounds__(kColWaves * 64) k_col_colour(int n, const uint
   __shared__ unsigned long long used[kColWaves][kColMaxWords];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int v = blockIdx.x * kColWaves + wid;
-  // left is unchanged since this round's select kernel read it: 0 means
-  // that kernel returned at once and sel is a previous round's
+  // left is 0 here only if it was 0 when this round's select kernel read it
+  // (that kernel then returned at once and sel is a previous round's): a
+  // vertex taken in this round keeps it positive until its own wave below
+  // has coloured it
   if (v >= n || ctr->left == 0 || !sel[v]) return;
   const int W = (n + 63) >> 6;
   unsigned long long *mine = used[wid];
