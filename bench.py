@@ -745,6 +745,12 @@ def run_serve(args):
             h.update(digests[i])
         check = h.hexdigest() == fx["buckets"][0]["hash"]
     base_arr = np.array([sp.arrival_s for sp in specs])   # offered rate 1000/s in the specs
+    small = np.array([sp.n < args.split_n for sp in specs])   # the session lane's requests
+
+    def pct(x):
+        return {"requests": int(x.size), "p50_ms": float(np.percentile(x, 50) * 1e3),
+                "p99_ms": float(np.percentile(x, 99) * 1e3), "max_ms": float(x.max() * 1e3)} if x.size else None
+
     phases = {}
     for frac in (0.5, 0.8):
         rate = frac * S
@@ -754,6 +760,8 @@ def run_serve(args):
         phases["%.1fS" % frac] = {"offered_rps": rate, "achieved_rps": N / el,
                                   "p50_ms": float(np.percentile(lat, 50) * 1e3),
                                   "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3),
+                                  "by_lane": {"session (n < split_n)": pct(lat[small]),
+                                              "single_graph (n >= split_n)": pct(lat[~small])},
                                   "same_results_as_closed_loop": same}
         say("c5 phase %.1fS: %s" % (frac, phases["%.1fS" % frac]))
     srv.close()
