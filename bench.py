@@ -72,7 +72,8 @@ WORKLOADS = {
     "struction": "struction (section 4.1) of a random graph of 1000 vertices at p = 0.1 around vertex 0 "
                  "(G' about 40 000 nodes), plain bit rows",
 }
-SERVE_SPLIT_N = 2048       # c5 lane split (vertices)
+SERVE_SPLIT_N = 1024       # c5 lane split (vertices): below the library's 2048, as the session lane's
+                           # largest jobs set the small requests' tail
 SERVE_IDLE_US = 20000
 SERVE_RESIDENT_GIB = 8.0
 SERVE_WORKERS = 6          # c5: single-graph lane workers
