@@ -5,18 +5,22 @@
 //
 // Roots are the pairs (v0, v1) of class 0 x class 1 in lexicographic order,
 // handed out one at a time from an atomic counter.  The children of a root
-// are its class-2 vertices j; the wave that took the root opens them on its
-// share word, and any wave -- its own, or one that has run out of roots --
-// takes the next child with an atomic add and runs the depth-first search
-// below it over classes 3, 4, ... in index order.  A wave keeps the common
-// neighbourhood of its current pick (AND of the picked rows and the live
-// mask) for every depth on a stack, lanes over row words, and extends a pick
-// only when every class after it still holds a candidate.  The key of a
-// child is (root, j) in lexicographic order; the first clique a child's
-// search meets is that child's smallest, so the smallest key with a clique
-// holds the smallest clique overall: an atomic minimum over keys keeps it,
-// and waves holding larger keys stop as soon as it is known.  Nothing waits
-// for anything, so the launch cannot deadlock.
+// are its class-2 vertices j, each searched depth first over classes 3, 4,
+// ... in index order.  The wave that took a root searches its children in
+// order itself; once it has extended kClqShareAfter picks below the root it
+// opens the remaining children on its share word, and from then on any wave
+// -- its own, or a helper (a wave of the first kClqHelperBlocks blocks that
+// has run out of roots) -- takes the next kClqTake children with one atomic
+// add.  A wave keeps the common neighbourhood of its current pick (AND of
+// the picked rows and the live mask) for every depth on a stack, lanes over
+// row words, and extends a pick only when every class after it still holds
+// a candidate.  The key of a child is (root, j) in lexicographic order; the
+// first clique a child's search meets is that child's smallest, so the
+// smallest key with a clique holds the smallest clique overall: an atomic
+// minimum over keys keeps it, and waves holding larger keys stop as soon as
+// it is known.  Helpers only poll, a bounded number of times in a row, for
+// work opened by waves that are already running; nothing else waits, so the
+// launch cannot deadlock.
 #include "kz_internal.h"
 
 namespace kzi {
@@ -174,7 +178,8 @@ __device__ __forceinline__ bool extend_all(const int *soff, int c0, int k, int l
 }
 
 // The search.  stack: kClqMaxWaves slots of k * R words; share: a word per
-// slot; found: per slot the key (int64) and the k picks.
+// slot; omask: the open-slot bit mask; found: per slot the key (int64) and
+// the k picks.
 // LDS: the stack lives in LDS when it fits (k * R <= kClqLdsWords per wave).
 template <bool LDS>
 __global__ void __launch_bounds__(kClqWaves * 64) k_clique_search(const uint64_t *__restrict__ rows, int k, int R,
