@@ -50,7 +50,7 @@ extern "C" {
 #define KZ_ENOMEM     (-7)  /* host staging allocation failed                    */
 #define KZ_EHIP       (-8)  /* a HIP runtime call failed                         */
 #define KZ_EAGAIN     (-9)  /* serving: no slot or memory free yet               */
-#define KZ_ETOOLARGE  (-10) /* batch: graph beyond the batched path's limits     */
+#define KZ_ETOOLARGE  (-10) /* a size beyond an entry point's stated limits     */
 
 /* Input validation happens in two stages and reports one code:
  *   1. colours: any colour outside [0,k) -> KZ_ECOLOUR; otherwise, for the

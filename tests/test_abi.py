@@ -63,6 +63,51 @@ def test_status_strings_and_host_argument_checks(lib):
     assert lib.kz_create(None, 0) == -1
 
 
+def test_clique_and_colouring_host_checks(lib):
+    """Argument checks of the clique search and the colouring that end on
+    the host, before the context is touched or any HIP call is made."""
+    from paper_2212_00574_amd import binding as b
+    lib.kz_clique_workspace_bytes.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+    lib.kz_find_clique.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.kz_colour_workspace_bytes.argtypes = [C.c_int32, C.c_void_p]
+    lib.kz_colour_jp.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p]
+    g = b.kz_graph(format=b.KZ_BITSET_U64, n=2000, rows=None, row_words=40)
+    size = C.c_size_t(0)
+    assert lib.kz_clique_workspace_bytes(C.byref(g), 20, C.byref(size)) == b.KZ_OK
+    assert size.value >= 2048 * 20 * 40 * 8              # a stack of k * R words per wave
+    bigger = C.c_size_t(0)
+    assert lib.kz_clique_workspace_bytes(C.byref(g), 21, C.byref(bigger)) == b.KZ_OK and bigger.value > size.value
+    assert lib.kz_clique_workspace_bytes(C.byref(g), 65, C.byref(size)) == b.KZ_EINVAL
+    dense = b.kz_graph(format=b.KZ_DENSE_U8, n=10)
+    assert lib.kz_clique_workspace_bytes(C.byref(dense), 3, C.byref(size)) == b.KZ_EINVAL
+    res = b.kz_clique_result()
+    fake_ctx = C.create_string_buffer(64)                 # never dereferenced on these paths
+    assert lib.kz_find_clique(None, C.byref(g), None, 3, None, None, 0, None, None, C.byref(res)) == b.KZ_EINVAL
+    assert res.status == b.KZ_EINVAL
+    assert lib.kz_find_clique(fake_ctx, C.byref(dense), None, 3, None, None, 0, None, None, None) == b.KZ_EINVAL
+    assert lib.kz_find_clique(fake_ctx, C.byref(g), None, 65, None, None, 0, None, None, None) == b.KZ_ETOOLARGE
+    huge = b.kz_graph(format=b.KZ_BITSET_U64, n=1 << 21, rows=None, row_words=1 << 15)
+    assert lib.kz_find_clique(fake_ctx, C.byref(huge), None, 3, None, None, 0, None, None,
+                              C.byref(res)) == b.KZ_ETOOLARGE and res.status == b.KZ_ETOOLARGE
+    assert lib.kz_colour_workspace_bytes(-1, C.byref(size)) == b.KZ_EINVAL
+    assert lib.kz_colour_workspace_bytes(1000, C.byref(size)) == b.KZ_OK and size.value >= 1000
+    cres = b.kz_colour_result()
+    assert lib.kz_colour_jp(None, 10, None, 1, None, None, 0, None, None, C.byref(cres)) == b.KZ_EINVAL
+    assert cres.status == b.KZ_EINVAL
+    addr = C.c_void_p(1 << 20)                           # 256-byte aligned, never dereferenced here
+    assert lib.kz_colour_jp(fake_ctx, 100, addr, 1, addr, addr, 1 << 20, addr, None,
+                            None) == b.KZ_EINVAL       # rows narrower than n bits
+    assert lib.kz_colour_jp(fake_ctx, 100, addr, 1025, addr, addr, 1 << 20, addr, None,
+                            None) == b.KZ_ETOOLARGE    # rows beyond 1024 words
+    assert lib.kz_colour_jp(fake_ctx, 100, addr, 2, addr, None, 0, addr, None,
+                            None) == b.KZ_EINVAL       # no workspace
+    assert lib.kz_colour_jp(fake_ctx, 100, addr, 2, addr, C.c_void_p((1 << 20) + 8), 1 << 20, addr, None,
+                            None) == b.KZ_EINVAL       # workspace not 256-byte aligned
+    assert lib.kz_colour_jp(None, 0, None, 0, None, None, 0, None, None, None) == b.KZ_EINVAL
+
+
 def test_product_does_not_reference_the_oracle():
     """The HIP library and its binding never load, link or name the oracle."""
     pkg = os.path.join(ROOT, "paper_2212_00574_amd")
