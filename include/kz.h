@@ -309,8 +309,11 @@ int kz_batch_get_config(const kz_ctx *ctx, kz_batch_config *cfg);
  * launch has session_cus workgroups of 16 waves (each fills a compute unit's
  * registers, so the other units stay free for the other lane); a workgroup
  * takes no new request once lease_us has passed since it started, and
- * leaves once idle, so under load a launch ends about every lease_us and
- * the server starts the next when requests wait.
+ * leaves once idle, so under load a launch ends about every lease_us -- or
+ * when its longest job does, which for requests just under split_n can be
+ * tens of ms -- and the server starts the next when requests wait (queued
+ * behind the running launch, so they wait for that job: a lower split_n
+ * shortens the wait).
  *
  * Single-graph lane: requests of split_n vertices or more (default 2048),
  * or beyond the batched path's k and row-word limits, go to worker threads
