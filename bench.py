@@ -318,7 +318,7 @@ def class_pair_edges(rows_host, sizes):
 
 
 def full_segment_work(cnt, sizes):
-    """Survey model of one full sweep: operand bytes 2 (n - s_cu - s_cv) / 8
+    """Full-segment model of one sweep: operand bytes 2 (n - s_cu - s_cv) / 8
     per edge (both rows streamed) and 4 ops per word of every third class."""
     sizes = np.asarray(sizes, np.int64)
     n = int(sizes.sum())
@@ -495,7 +495,7 @@ def run_single(args, name, cpu_proc=None):
                 "avg_launch_ms": round(edge_avg_ms, 5), "launches_per_step": edge_launches / psteps,
                 "full_segment": {"ops_per_launch": fs_per_launch, "achieved": round(fs_achieved, 3),
                                  "frac": round(fs_achieved / VALU_PEAK_TOPS, 4),
-                                 "note": "every word of every third class (the survey's model); a search that "
+                                 "note": "every word of every third class (the full-segment model); a search that "
                                          "stops at the first witness does less, so this can pass 1"},
                 "operand_stream": {"GBps": round(stream_gbps, 1), "frac_of_hbm": round(stream_gbps / HBM_PEAK_GBPS, 3),
                                    "note": "both rows streamed per edge, 2 (n - s_u - s_v)/8 bytes: the bandwidth a "
